@@ -1,0 +1,416 @@
+"""CPU oracle for deferred software rasterization of strand hair.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg may import this module; the product path never does.  It
+shares no code with the HIP library: the plain C part (hm_oracle.c) covers the
+hash, LOD, strand generation, rasterization and the filtered resolve, and this
+file adds the soft-coverage resolve in binary64 with plain torch CPU ops, whose
+autograd gradient is the reference gradient.
+
+Functions with no independent pin are marked "parity unpinned" below; at the
+time of writing there are none (see tests/test_oracle_*.py for the pins).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "hm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+ID_BITS = 40
+ID_MASK = (1 << 40) - 1
+ID_OPAQUE = (1 << 40) - 2
+
+
+def build(force: bool = True) -> str:
+    """Compile hm_oracle.c with gcc (binary32 ops kept separate: no contraction)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+               "-shared", "-o", _LIB, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        u32, u64, f32, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float, ctypes.c_int
+        P = ctypes.c_void_p
+        L.orc_pcg.restype = u32
+        L.orc_pcg.argtypes = [u32]
+        L.orc_strand_rand.argtypes = [u32, u32, u32, P]
+        L.orc_lod_delta.restype = f32
+        L.orc_lod_delta.argtypes = [u32, u32]
+        L.orc_lod_counts.argtypes = [f32, u32, f32, u32, u32, P, P]
+        L.orc_sin_export.restype = f32
+        L.orc_sin_export.argtypes = [f32]
+        L.orc_cos_export.restype = f32
+        L.orc_cos_export.argtypes = [f32]
+        L.orc_project_export.restype = i32
+        L.orc_project_export.argtypes = [P, P, P]
+        L.orc_qdepth_export.restype = u32
+        L.orc_qdepth_export.argtypes = [f32, f32, f32]
+        L.orc_cover_export.restype = i32
+        L.orc_cover_export.argtypes = [P, P, i32, i32, f32, f32, f32, P]
+        L.orc_lod_select.restype = i32
+        L.orc_lod_select.argtypes = [P, P, u32, u32, u32, P, P, P, P, P, u32, i32, i32, i32,
+                                     f32, u32, P, P, P]
+        L.orc_generate.restype = i32
+        L.orc_generate.argtypes = [P, P, u32, u32, u32, P, P, P, P, u32, f32, f32, f32, P,
+                                   P, P, P]
+        L.orc_raster.restype = i32
+        L.orc_raster.argtypes = [P, P, P, P, u32, i32, i32, f32, P, i32, P, u64, P]
+        L.orc_cover_counts.restype = i32
+        L.orc_cover_counts.argtypes = [P, P, P, P, u32, i32, i32, f32, P]
+        L.orc_resolve.restype = i32
+        L.orc_resolve.argtypes = [P, P, P, P, P, u32, i32, i32, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ----------------------------------------------------------------- small pieces
+def pcg(v: int) -> int:
+    return int(lib().orc_pcg(v & 0xFFFFFFFF))
+
+
+def strand_rand(seed: int, key: int, k: int):
+    o = np.zeros(3, np.float32)
+    lib().orc_strand_rand(seed, key, k, _p(o))
+    return o
+
+
+def lod_delta(seed: int, key: int) -> float:
+    return float(lib().orc_lod_delta(seed, key))
+
+
+def lod_counts(L: float, N: int, delta: float, cmax: int, n_layers: int):
+    n = ctypes.c_uint32()
+    c = ctypes.c_uint32()
+    lib().orc_lod_counts(L, N, delta, cmax, n_layers, ctypes.byref(n), ctypes.byref(c))
+    return n.value, c.value
+
+
+def sin32(a: float) -> float:
+    return float(lib().orc_sin_export(a))
+
+
+def cos32(a: float) -> float:
+    return float(lib().orc_cos_export(a))
+
+
+def project(cam: np.ndarray, p_w: np.ndarray):
+    """(x_px, y_px, width_px, 1/z) of one control point, or None if clipped."""
+    cam = _c(cam, np.float32)
+    p = _c(p_w, np.float32)
+    o = np.zeros(4, np.float32)
+    ok = lib().orc_project_export(_p(cam), _p(p), _p(o))
+    return o if ok else None
+
+
+def qdepth(z: float, znear: float, zfar: float) -> int:
+    return int(lib().orc_qdepth_export(z, znear, zfar))
+
+
+def cover(a, b, i, j, r_min, znear, zfar):
+    """(mask, q): mask bit0 centre, bit1 conservative for projected endpoints a, b."""
+    a = _c(a, np.float32)
+    b = _c(b, np.float32)
+    q = ctypes.c_uint32(0)
+    m = lib().orc_cover_export(_p(a), _p(b), i, j, r_min, znear, zfar, ctypes.byref(q))
+    return m, q.value
+
+
+# ----------------------------------------------------------------- stages
+def lod_select(sc, mode: Optional[int] = None):
+    """Returns (table [B][4] u32, scene_off [S+1] u32, totals (strands, cps))."""
+    B = sc.n_bundles
+    table = np.zeros((B, 4), np.uint32)
+    soff = np.zeros(sc.n_scenes + 1, np.uint32)
+    tot = np.zeros(2, np.uint64)
+    lp = _c(sc.layer_pos, np.float32)
+    arrs = [_c(x, np.uint32) for x in (sc.quads, sc.bundle_key, sc.bundle_nstrands,
+                                       sc.bundle_cmax, sc.bundle_scene)]
+    cams = _c(sc.cams, np.float32)
+    rc = lib().orc_lod_select(_p(lp), _p(arrs[0]), B, sc.n_layers, lp.shape[1], _p(arrs[1]),
+                              _p(arrs[2]), _p(arrs[3]), _p(arrs[4]), _p(cams), sc.n_scenes,
+                              sc.width, sc.height, sc.lod_mode if mode is None else mode,
+                              sc.lod_lambda, sc.seed, _p(table), _p(soff), _p(tot))
+    if rc != 0:
+        raise OverflowError("oracle lod_select: counts exceed 32 bits")
+    return table, soff, (int(tot[0]), int(tot[1]))
+
+
+def generate(sc, table: np.ndarray, n_cp: int):
+    pos_w = np.zeros((max(n_cp, 1), 4), np.float32)
+    rgb = np.zeros((max(n_cp, 1), 4), np.float32)
+    flags = np.zeros(max(n_cp, 1), np.uint8)
+    lp = _c(sc.layer_pos, np.float32)
+    quads = _c(sc.quads, np.uint32)
+    key = _c(sc.bundle_key, np.uint32)
+    tab = _c(table, np.uint32)
+    base = _c(sc.strand_base, np.uint32)
+    srgb = None if sc.strand_rgb is None else _c(sc.strand_rgb, np.float32)
+    brgb = np.asarray(sc.base_rgb, np.float32)
+    rc = lib().orc_generate(_p(lp), _p(quads), sc.n_bundles, sc.n_layers, lp.shape[1], _p(key),
+                            _p(tab), _p(base), _p(srgb), sc.seed, sc.strand_width, sc.curl_amp,
+                            sc.curl_turns, _p(brgb), _p(pos_w), _p(rgb), _p(flags))
+    if rc != 0:
+        raise ValueError("oracle generate: unsupported layer count")
+    return pos_w[:n_cp], rgb[:n_cp], flags[:n_cp]
+
+
+def raster(pos_w, flags, scene_off, cams, width, height, r_min=0.0, scene_z=None,
+           brute=False, order=None):
+    """Visibility buffer [S][2][H][W] uint64 (layer 0 centre, 1 conservative)."""
+    S = int(np.asarray(cams).reshape(-1, 18).shape[0])
+    vis = np.zeros((S, 2, height, width), np.uint64)
+    pos_w = _c(pos_w, np.float32)
+    flags = _c(flags, np.uint8)
+    soff = _c(scene_off, np.uint32)
+    cams = _c(cams, np.float32)
+    sz = None if scene_z is None else _c(scene_z, np.float32)
+    od = None if order is None else _c(order, np.uint32)
+    lib().orc_raster(_p(pos_w), _p(flags), _p(soff), _p(cams), S, width, height, r_min, _p(sz),
+                     1 if brute else 0, _p(od), 0 if od is None else od.shape[0], _p(vis))
+    return vis
+
+
+def cover_counts(pos_w, flags, scene_off, cams, width, height, r_min=0.0):
+    """(segments, centre pairs, conservative pairs) -- the raster's algorithmic work."""
+    S = int(np.asarray(cams).reshape(-1, 18).shape[0])
+    out = np.zeros(3, np.uint64)
+    lib().orc_cover_counts(_p(_c(pos_w, np.float32)), _p(_c(flags, np.uint8)),
+                           _p(_c(scene_off, np.uint32)), _p(_c(cams, np.float32)), S, width,
+                           height, r_min, _p(out))
+    return tuple(int(x) for x in out)
+
+
+class _ShadeParams(ctypes.Structure):
+    _fields_ = [("light_dir", ctypes.c_double * 3), ("light_rgb", ctypes.c_double * 3),
+                ("ka", ctypes.c_double), ("kd", ctypes.c_double), ("ks", ctypes.c_double),
+                ("spec_squarings", ctypes.c_int), ("filter_radius", ctypes.c_int),
+                ("s_par", ctypes.c_double), ("s_perp", ctypes.c_double),
+                ("sigma_c", ctypes.c_double), ("iso_scale", ctypes.c_double),
+                ("dq_reject", ctypes.c_uint32), ("dq_mismatch", ctypes.c_uint32),
+                ("strip_half2", ctypes.c_float), ("iso_len", ctypes.c_float),
+                ("bg", ctypes.c_double * 3), ("mode", ctypes.c_int)]
+
+
+def depth_code_thresholds(rp):
+    """Depth thresholds of Sec. 3.3 converted to 24-bit depth-code units:
+    rejection when |dq| > floor(t_reject 2^24); mismatch when the conservative
+    key is nearer by at least ceil(t_mismatch 2^24)."""
+    return (int(math.floor(rp.depth_reject * 2.0 ** 24)),
+            int(math.ceil(rp.depth_mismatch * 2.0 ** 24)))
+
+
+def _shade_struct(rp, mode, bg):
+    dq_rej, dq_mis = depth_code_thresholds(rp)
+    s = _ShadeParams()
+    s.light_dir[:] = [float(x) for x in rp.light_dir]
+    s.light_rgb[:] = [float(x) for x in rp.light_rgb]
+    s.ka, s.kd, s.ks = rp.ka, rp.kd, rp.ks
+    s.spec_squarings = rp.spec_squarings
+    s.filter_radius = rp.filter_radius
+    s.s_par, s.s_perp, s.sigma_c, s.iso_scale = rp.s_par, rp.s_perp, rp.sigma_c, rp.iso_scale
+    s.dq_reject, s.dq_mismatch = dq_rej, dq_mis
+    h = np.float32(rp.strip_half)
+    s.strip_half2 = float(h * h)
+    s.iso_len = float(np.float32(rp.iso_len))
+    s.bg[:] = [float(x) for x in bg]
+    s.mode = mode
+    return s
+
+
+def resolve(pos_w, rgb, flags, vis, cams, width, height, rp, mode=0, bg=(0.0, 0.0, 0.0),
+            want_center=False):
+    """Filtered (mode 0) or centre-only (mode 2) RGBA [S][H][W][4] in float64."""
+    S = int(np.asarray(cams).reshape(-1, 18).shape[0])
+    out = np.zeros((S, height, width, 4), np.float64)
+    cc = np.zeros((S, height, width, 3), np.float64) if want_center else None
+    sp = _shade_struct(rp, mode, bg)
+    rc = lib().orc_resolve(_p(_c(pos_w, np.float32)), _p(_c(rgb, np.float32)),
+                           _p(_c(flags, np.uint8)), _p(_c(vis, np.uint64)),
+                           _p(_c(cams, np.float32)), S, width, height, ctypes.byref(sp),
+                           _p(out), _p(cc))
+    if rc != 0:
+        raise ValueError(f"oracle resolve failed ({rc})")
+    return (out, cc) if want_center else out
+
+
+# ----------------------------------------------------------------- soft coverage (binary64)
+def _torch():
+    import torch
+    return torch
+
+
+def soft_gather(vis: np.ndarray, flags: np.ndarray):
+    """Per-pixel visible segment for the soft resolve: centre key if it is a
+    hair hit, else the conservative key.  Returns (scene, j, i, v) int64 arrays."""
+    S, _, H, W = vis.shape
+    v = vis.astype(np.uint64)
+    ids = (v & np.uint64(ID_MASK)).astype(np.int64)
+    hit = (v != EMPTY) & (ids != ID_OPAQUE)
+    src = np.where(hit[:, 0], ids[:, 0], np.where(hit[:, 1], ids[:, 1], -1))
+    s, j, i = np.nonzero(src >= 0)
+    return s, j, i, src[s, j, i]
+
+
+def soft_forward(pos_w, rgb, flags, vis, cams, width, height, rp, bg=(0.0, 0.0, 0.0)):
+    """Soft-coverage resolve in binary64 with torch CPU ops.
+
+    pos_w, rgb: float64 torch tensors [n_cp][4] (may require grad).
+    For each pixel whose visibility names a hair segment v (centre layer first):
+      closest screen-space parameter t* of the pixel centre on the projected
+      segment, distance d and interpolated pixel width w_t there;
+      coverage a = Phi((d + w_t/2)/s) - Phi((d - w_t/2)/s): the area of a
+      width-w_t band under a Gaussian pixel filter of std s (1/sqrt(12) px
+      matches a box pixel's variance);
+      shading S at the perspective-correct point (as the deferred shading);
+      I = a S + (1 - a) bg.
+    Returns [S][H][W][4] float64 (rgb, a) as a torch tensor.
+    """
+    torch = _torch()
+    S = vis.shape[0]
+    s_np, j_np, i_np, v_np = soft_gather(vis, flags)
+    out = torch.zeros((S, height, width, 4), dtype=torch.float64)
+    out[..., 0] = bg[0]
+    out[..., 1] = bg[1]
+    out[..., 2] = bg[2]
+    if v_np.size == 0:
+        return out
+    fl = torch.as_tensor(flags.astype(np.int64))
+    v = torch.as_tensor(v_np)
+    sc = torch.as_tensor(s_np)
+    cams_t = torch.as_tensor(np.asarray(cams, np.float64).reshape(-1, 18))[sc]
+    R = cams_t[:, 0:9].reshape(-1, 3, 3)
+    eye = cams_t[:, 9:12]
+    fx, fy, cx, cy = cams_t[:, 12], cams_t[:, 13], cams_t[:, 14], cams_t[:, 15]
+    P = pos_w[:, :3]
+    wid = pos_w[:, 3]
+    n_cp = P.shape[0]
+    P0, P1 = P[v], P[v + 1]
+    root_v = (fl[v] & 1) != 0
+    tip_v1 = (fl[v + 1] & 2) != 0
+    Pm = P[torch.clamp(v - 1, min=0)]
+    Pp = P[torch.clamp(v + 2, max=n_cp - 1)]
+
+    def nrm(a):
+        return a / torch.linalg.norm(a, dim=-1, keepdim=True)
+
+    T0 = nrm(torch.where(root_v[:, None], P1 - P0, P1 - Pm))
+    T1 = nrm(torch.where(tip_v1[:, None], P1 - P0, Pp - P0))
+
+    def proj(X):
+        d = X - eye
+        Xc = torch.einsum("nij,nj->ni", R, d)
+        iz = 1.0 / Xc[:, 2]
+        return cx + fx * Xc[:, 0] * iz, cy - fy * Xc[:, 1] * iz, iz
+
+    x0, y0, iz0 = proj(P0)
+    x1, y1, iz1 = proj(P1)
+    w0 = wid[v] * fy * iz0
+    w1 = wid[v + 1] * fy * iz1
+    px = torch.as_tensor(i_np, dtype=torch.float64) + 0.5
+    py = torch.as_tensor(j_np, dtype=torch.float64) + 0.5
+    dx, dy = x1 - x0, y1 - y0
+    len2 = dx * dx + dy * dy
+    safe = torch.where(len2 > 0, len2, torch.ones_like(len2))
+    ts = torch.where(len2 > 0, ((px - x0) * dx + (py - y0) * dy) / safe, torch.zeros_like(len2))
+    ts = torch.clamp(ts, 0.0, 1.0)
+    qx, qy = x0 + ts * dx, y0 + ts * dy
+    ex, ey = px - qx, py - qy
+    d2 = ex * ex + ey * ey
+    dist = torch.sqrt(torch.where(d2 > 0, d2, torch.ones_like(d2))) * (d2 > 0)
+    wt = w0 + ts * (w1 - w0)
+    sg = rp.soft_sigma
+    k = 1.0 / (sg * math.sqrt(2.0))
+
+    def Phi(x):
+        return 0.5 * torch.erfc(-x * k)
+
+    alpha = Phi(dist + 0.5 * wt) - Phi(dist - 0.5 * wt)
+    iz = iz0 + ts * (iz1 - iz0)
+    t3 = ts * iz1 / iz
+    X = P0 + t3[:, None] * (P1 - P0)
+    T = nrm(T0 + t3[:, None] * (T1 - T0))
+    c0, c1 = rgb[v, :3], rgb[v + 1, :3]
+    alb = c0 + t3[:, None] * (c1 - c0)
+    V = nrm(eye - X)
+    Ld = torch.as_tensor(np.asarray(rp.light_dir, np.float64))
+    Ld = Ld / torch.linalg.norm(Ld)
+    Hh = nrm(Ld[None, :] + V)
+    tl = (T * Ld[None, :]).sum(-1)
+    th = (T * Hh).sum(-1)
+    sd = 1.0 - tl * tl
+    diff = torch.sqrt(torch.where(sd > 0, sd, torch.ones_like(sd))) * (sd > 0)
+    sh = torch.clamp(1.0 - th * th, min=0.0)
+    spec = sh
+    for _ in range(rp.spec_squarings):
+        spec = spec * spec
+    E = torch.as_tensor(np.asarray(rp.light_rgb, np.float64))[None, :]
+    Sh = alb * E * (rp.ka + rp.kd * diff)[:, None] + rp.ks * E * spec[:, None]
+    bgt = torch.as_tensor(np.asarray(bg, np.float64))[None, :]
+    I = alpha[:, None] * Sh + (1.0 - alpha[:, None]) * bgt
+    vals = torch.cat([I, alpha[:, None]], dim=1)
+    idx = (torch.as_tensor(s_np) * height + torch.as_tensor(j_np)) * width + torch.as_tensor(i_np)
+    flat = out.reshape(-1, 4).index_put((idx,), vals)
+    return flat.reshape(S, height, width, 4)
+
+
+def soft_grad(pos_w, rgb, flags, vis, cams, width, height, rp, d_out, bg=(0.0, 0.0, 0.0)):
+    """Reference gradient (binary64 autograd of soft_forward) for upstream d_out.
+    Returns (grad_pos_w [n_cp][4], grad_rgb [n_cp][4]) as float64 numpy."""
+    torch = _torch()
+    pw = torch.tensor(np.asarray(pos_w, np.float64), requires_grad=True)
+    cr = torch.tensor(np.asarray(rgb, np.float64), requires_grad=True)
+    out = soft_forward(pw, cr, flags, vis, cams, width, height, rp, bg)
+    g = torch.as_tensor(np.asarray(d_out, np.float64))
+    gp, gc = torch.autograd.grad(out, [pw, cr], grad_outputs=g, allow_unused=True)
+    gp = torch.zeros_like(pw) if gp is None else gp
+    gc = torch.zeros_like(cr) if gc is None else gc
+    return gp.numpy(), gc.numpy()
+
+
+# ----------------------------------------------------------------- whole frame
+def render(sc, rp=None, want=("vis", "out")):
+    """Oracle for the whole path on one Scene: LOD -> generate -> raster -> resolve."""
+    from paper_2607_04230_amd.scenes import ResolveParams, MODE_SOFT  # inputs only
+    rp = rp or ResolveParams()
+    table, soff, (ns, ncp) = lod_select(sc)
+    pos_w, rgb, flags = generate(sc, table, ncp)
+    vis = raster(pos_w, flags, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+    res = dict(table=table, scene_off=soff, n_strands=ns, n_cp=ncp, pos_w=pos_w, rgb=rgb,
+               flags=flags, vis=vis)
+    if "out" in want:
+        if sc.mode == MODE_SOFT:
+            torch = _torch()
+            res["out"] = soft_forward(torch.as_tensor(pos_w.astype(np.float64)),
+                                      torch.as_tensor(rgb.astype(np.float64)), flags, vis,
+                                      sc.cams, sc.width, sc.height, rp, sc.bg).numpy()
+        else:
+            res["out"] = resolve(pos_w, rgb, flags, vis, sc.cams, sc.width, sc.height, rp,
+                                 sc.mode, sc.bg)
+    return res
