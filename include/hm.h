@@ -1,0 +1,249 @@
+/*
+ * hm.h -- C ABI of libhm, an MI355X (gfx950) implementation of deferred
+ * software rasterization of strand hair after Lipp, Jarabo, Wimmer and Bode,
+ * "Deferred Software Rasterization for Efficient Real-time Hair Rendering".
+ *
+ * Pipeline (Sec. 3, pipeline figure): a per-bundle LOD pre-pass produces the
+ * dispatch table; strands are generated from the hair mesh; every styled
+ * segment is rasterized into two 64-bit visibility layers with an atomic
+ * minimum on (depth, segment id); a deferred per-pixel resolve shades the
+ * visible segments and reconstructs / filters the strands, or evaluates the
+ * differentiable soft-coverage resolve.
+ *
+ * General conventions
+ *   - Every pointer inside a struct or passed as an array argument is a DEVICE
+ *     pointer unless marked "host".  Struct arguments themselves (the hm_*
+ *     descriptors) are host pointers read during the call only.
+ *   - The caller owns every buffer.  The library never allocates device
+ *     memory; scratch space is the caller's workspace (size from
+ *     hm_workspace_size).  Nothing is retained between calls.
+ *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = the null
+ *     stream): it validates its arguments on the host, enqueues kernels and
+ *     returns; it never synchronises.  Calls are safe to capture in a HIP
+ *     graph (no memset nodes, no host reads of device data).
+ *   - Return value: HM_OK, or an error code with nothing enqueued for
+ *     argument errors.  hm_last_error() gives a message (per host thread).
+ *   - Images are row-major, pixel (i, j) = column i, row j, centre at
+ *     (i + 0.5, j + 0.5).  A frame holds S scenes ("views") of equal size.
+ *   - Counts of strands and control points (CPs) are 32-bit: one call handles
+ *     fewer than 2^32 - 1 control points (137 GB of strand stream).
+ */
+#ifndef HM_H
+#define HM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    HM_OK = 0,
+    HM_ERR_INVALID = 1,   /* null pointer, zero size, bad enum, inconsistent descriptor */
+    HM_ERR_RANGE = 2,     /* a size outside the supported range */
+    HM_ERR_WORKSPACE = 3, /* workspace smaller than hm_workspace_size() */
+    HM_ERR_HIP = 4        /* a HIP launch failed (message in hm_last_error) */
+} hm_status;
+
+/* Pinhole camera (Sec. 3.2.1 projects bundles "to screen space").
+ * R: world-to-camera rotation, rows = camera right, up, forward.  Camera
+ * space has +z forward and +y up; pixel x = cx + fx X/Z, y = cy - fy Y/Z.
+ * Depth is normalised linear view depth (Z - znear)/(zfar - znear). */
+typedef struct {
+    float R[9];
+    float eye[3];
+    float fx, fy, cx, cy, znear, zfar;
+} hm_camera;
+
+/* S scenes of width x height pixels; scene s uses camera s. */
+typedef struct {
+    uint32_t n_scenes;
+    uint32_t width;   /* 1 .. 16384 */
+    uint32_t height;  /* 1 .. 16384 */
+} hm_frame;
+
+/* Hair mesh (Sec. 2, "Background: Hair mesh rendering"): bundles of n_layers
+ * stacked quads, roots on layer 0, tips on layer n_layers - 1.  Bundle b uses
+ * the vertices quads[b][0..3] = (A, B, C, D), counter-clockwise, of every
+ * layer.  Several scenes may share one mesh: bundle b belongs to scene
+ * bundle_scene[b] (non-decreasing in b). */
+typedef struct {
+    const float *layer_pos;          /* [n_layers][n_verts][3] */
+    const uint32_t *quads;           /* [n_bundles][4] vertex indices < n_verts */
+    const uint32_t *bundle_key;      /* [n_bundles] hash key: strand k of a bundle is
+                                        determined by (seed, key, k) */
+    const uint32_t *bundle_nstrands; /* [n_bundles] full strand count N_b */
+    const uint32_t *bundle_cmax;     /* [n_bundles] control points per strand (>= 2):
+                                        the cap C_max of eq. cp-lod, or the count when LOD is off */
+    const uint32_t *bundle_scene;    /* [n_bundles] scene index < n_scenes */
+    uint32_t n_bundles;              /* >= 1 */
+    uint32_t n_layers;               /* 2 .. 64 */
+    uint32_t n_verts;                /* >= 1 */
+} hm_hair_mesh;
+
+/* Generated strand stream: control points of all strands, strand after
+ * strand, bundle after bundle (table order).  Segment v joins CP v and CP
+ * v + 1 when CP v is not a tip. */
+typedef struct {
+    float *pos_w;               /* [cap][4]: x, y, z (world), width (world units) */
+    float *rgb;                 /* [cap][4]: albedo r, g, b, ambient occlusion (1) */
+    uint8_t *flags;             /* [cap]: bit0 root CP, bit1 tip CP */
+    const uint32_t *scene_off;  /* [n_scenes + 1]: first CP of each scene; scene_off[S] = n_cp */
+    uint32_t n_scenes;
+    uint32_t cap;               /* host upper bound on n_cp; sizes the launches */
+} hm_strands;
+
+/* ------------------------------------------------------------------ LOD */
+enum { HM_LOD_OFF = 0, HM_LOD_ON = 1 };
+
+typedef struct {
+    int32_t mode;     /* HM_LOD_OFF: N_b strands with bundle_cmax[b] CPs, no culling.
+                         HM_LOD_ON: Sec. 3.2.1 / 3.2.2 */
+    float lambda;     /* LOD sensitivity (eq. lod-factor) */
+    uint32_t seed;    /* per-bundle offset delta ~ U[0,1) of eq. strand-lod */
+} hm_lod_params;
+
+/* LOD pre-pass (Sec. 3.2; one thread per bundle as in the paper).  For every
+ * bundle: project the quad vertices of all layers, take the screen AABB,
+ * L = clamp(|AABB diagonal| / height * lambda, 0, 1) (eq. lod-factor);
+ * bundles whose AABB lies outside the viewport, or with every vertex at or
+ * behind the near plane, are culled (0 strands); a bundle crossing the near
+ * plane gets L = 1.  N_LOD = clamp(ceil(L (N_b + delta)), 1, N_b)
+ * (eq. strand-lod); C = min(2^floor(log2(C_raw - 1)) + 1, C_max) with
+ * C_raw = max(floor(sqrt(L) C_max), n_layers) (eqs. cp-lod, cp-snap).
+ * Outputs (device):
+ *   table[n_bundles][4] = {N_LOD, C, first strand, first CP} -- the paper's
+ *     one uint4 per bundle, plus the exclusive prefix sums that replace its
+ *     indirect dispatch;
+ *   scene_off[n_scenes + 1] = first CP of each scene, scene_off[S] = n_cp;
+ *   totals[2] = {n_strands, n_cp} (uint64).
+ * If n_cp would reach 2^32 - 1 the counts are clamped and totals[1] reports
+ * the true count (callers compare it against their cap).
+ * ws: hm_workspace_size(HM_CALL_LOD, ...) bytes. */
+hm_status hm_lod_select(const hm_hair_mesh *mesh, const hm_camera *cams, const hm_frame *frame,
+                        const hm_lod_params *p, uint32_t *table, uint32_t *scene_off,
+                        uint64_t *totals, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ generation */
+typedef struct {
+    uint32_t seed;        /* strand (u, v) and curl phase hash seed */
+    float width;          /* strand width (world units), written to every CP */
+    float curl_amp;       /* styling: curl radius at the tip */
+    float curl_turns;     /* styling: turns from root to tip */
+    float base_rgb[3];    /* albedo when strand_rgb is NULL */
+} hm_gen_params;
+
+/* Strand generation (Sec. 3.1.1, Code 1).  Strand k of bundle b: (u, v) and
+ * a curl phase from the PCG hash of (seed, bundle_key[b], k); base points =
+ * bilinear interpolation of each layer quad at (u, v); finite-difference unit
+ * tangents (Code 1's calcTangent); cubic Hermite between layers with tangents
+ * scaled by the interval chord; C CPs uniformly spaced in w in [0, 1]; then
+ * the styling f(x): a curl of radius curl_amp * w about the bundle axis.
+ * table: the LOD table of hm_lod_select.  strand_base[b]: index of bundle b's
+ * first record in strand_rgb ([.][3], per full strand); strand_rgb may be
+ * NULL (base_rgb for all).  out->pos_w/rgb/flags receive n_cp CPs;
+ * out->scene_off must already hold the LOD output. */
+hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
+                              const uint32_t *strand_base, const float *strand_rgb,
+                              const hm_gen_params *p, const hm_strands *out, void *stream);
+
+/* ------------------------------------------------------------------ rasterization */
+enum { HM_RASTER_TILED = 0, HM_RASTER_DIRECT = 1 };
+
+typedef struct {
+    float r_min;              /* minimum coverage half width (px): the centre sample's
+                                 "configurable diameter" / 2 (Sec. 3.1.2); 0 = exact width */
+    int32_t algo;             /* HM_RASTER_TILED (LDS tiles) or HM_RASTER_DIRECT (global atomics) */
+    uint32_t tile;            /* tile edge in pixels: 8, 16, 32 or 64 */
+    uint32_t chunk;           /* segments per work item of a tile (>= 1) */
+    uint32_t max_tiles_per_seg; /* segments touching more tiles take the direct path (1..64) */
+    uint32_t block;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    uint32_t grid;            /* persistent workgroups (0 = auto) */
+} hm_raster_params;
+
+/* Visibility buffer (Sec. 3.1.2).  vis[s][0] = centre-sample layer,
+ * vis[s][1] = conservative layer, each [height][width] uint64.  Key of a
+ * segment v at pixel p: depth24 << 40 | v, where depth24 is the 24-bit
+ * truncated normalised linear depth at the segment point closest to the
+ * pixel centre (perspective-correct through 1/z); empty = 2^64 - 1.
+ * Centre layer: the pixel centre lies within max(w(t)/2, r_min) of the
+ * projected segment with the perpendicular foot at t in [0, 1).
+ * Conservative layer: the segment meets the pixel square dilated by
+ * max(max(w0, w1)/2, r_min).  vis[s][l][p] = min(prefill, keys of covering
+ * segments); results are bit-identical for every tuning parameter.
+ * scene_z (optional, [S][height][width] float): linear view depth of the
+ * opaque scene (Sec. 3's existing depth buffer); pixels with znear < z < zfar
+ * are prefilled with depth24(z) << 40 | (2^40 - 2) for early rejection.
+ * ws: hm_workspace_size(HM_CALL_RASTER, ...) bytes. */
+hm_status hm_raster_vis(const hm_strands *s, const hm_camera *cams, const hm_frame *frame,
+                        const hm_raster_params *p, const float *scene_z, uint64_t *vis,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ resolve */
+enum { HM_RESOLVE_FILTER = 0, HM_RESOLVE_SOFT = 1, HM_RESOLVE_CENTER = 2 };
+
+typedef struct {
+    float light_dir[3];    /* towards the directional light (normalised internally) */
+    float light_rgb[3];
+    float ka, kd, ks;      /* ambient, Kajiya-Kay diffuse, specular weights */
+    int32_t spec_squarings;/* specular (1 - (T.H)^2)^(2^n), 0 .. 8 */
+    int32_t filter_radius; /* r of the (2r+1)^2 window (Sec. 3.3.1), 0 .. 8 */
+    float s_par, s_perp;   /* sigma_par = r s_par, sigma_perp = r s_perp */
+    float sigma_c;         /* colour similarity sigma */
+    float iso_scale;       /* isotropic fallback sigma_iso = iso_scale r */
+    float depth_reject;    /* neighbour depth rejection threshold (normalised depth) */
+    float depth_mismatch;  /* centre vs conservative depth mismatch (normalised depth) */
+    float strip_half;      /* alpha strip half width in px (Sec. 3.3.3) */
+    float iso_len;         /* screen tangent shorter than this (px) -> isotropic */
+    float soft_sigma;      /* soft coverage: std of the Gaussian pixel filter (px) */
+    float bg[3];           /* background the result is composited over */
+    int32_t mode;          /* HM_RESOLVE_FILTER / HM_RESOLVE_SOFT / HM_RESOLVE_CENTER */
+} hm_shade_params;
+
+/* Deferred resolve, out_rgba[S][height][width][4] float (straight colour
+ * composited over bg, alpha in .w).
+ * FILTER (Sec. 3.3, 3.4, Code 2): centre pixels are shaded once (Kajiya-Kay
+ * diffuse + specular, one directional light); each hair pixel is then
+ * reconstructed with the elliptical bilateral filter over centre hits within
+ * the depth threshold, conservative-only pixels are promoted (colour term off),
+ * a nearer conservative strand (depth mismatch) is blended over the centre
+ * hit with alpha 1, and alpha = centre hits / all hits in the tangent strip.
+ * CENTER: plain 1-spp deferred shading of the centre layer.
+ * SOFT: coverage of the visible segment (centre layer first) under a Gaussian
+ * pixel filter, alpha = Phi((d + w/2)/s) - Phi((d - w/2)/s), composited over bg.
+ * ws: hm_workspace_size(HM_CALL_RESOLVE, ...) bytes. */
+hm_status hm_resolve_shade(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,
+                           const hm_frame *frame, const hm_shade_params *p, float *out_rgba,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Backward of the SOFT resolve with the visibility held fixed: given
+ * d_out = dLoss/d out_rgba ([S][H][W][4]), ACCUMULATES dLoss/d pos_w into
+ * grad_pos_w[cap][4] (x, y, z, width) and dLoss/d rgb into grad_rgb[cap][4]
+ * (.w untouched).  Callers zero the gradients first. */
+hm_status hm_resolve_shade_bwd(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,
+                               const hm_frame *frame, const hm_shade_params *p,
+                               const float *d_out, float *grad_pos_w, float *grad_rgb,
+                               void *stream);
+
+/* ------------------------------------------------------------------ workspace */
+enum { HM_CALL_LOD = 0, HM_CALL_RASTER = 1, HM_CALL_RESOLVE = 2 };
+
+/* Workspace bytes for `call`.  n_bundles (LOD) or cap (raster) size it;
+ * raster params may be NULL (defaults).  Returns HM_ERR_RANGE on overflow. */
+hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bundles,
+                            uint32_t cap, const hm_raster_params *p, size_t *bytes);
+
+/* Default raster parameters for a frame. */
+hm_status hm_raster_defaults(const hm_frame *frame, hm_raster_params *p);
+
+/* Message of the last error on this host thread ("" if none). */
+const char *hm_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int32_t hm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_H */

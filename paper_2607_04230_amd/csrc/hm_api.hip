@@ -1,0 +1,272 @@
+// C ABI of libhm: argument validation, workspace sizing, error reporting.
+// Kernels are enqueued on the caller's stream; nothing here synchronises or
+// allocates device memory.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "hm_device.hpp"
+#include "hm_internal.hpp"
+
+namespace hm {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+uint32_t stride_grid(size_t n, uint32_t block)
+{
+    size_t g = (n + block - 1) / block;
+    const size_t cap = 256u * 16u;        // 256 CUs x 16 resident workgroups
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (uint32_t)g;
+}
+
+}  // namespace hm
+
+using namespace hm;
+
+static thread_local char g_err[512] = "";
+
+static hm_status fail(hm_status st, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+static hm_status ok() { g_err[0] = 0; return HM_OK; }
+
+static hm_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(HM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    return ok();
+}
+
+#define REQUIRE(cond, code, ...) \
+    do { if (!(cond)) return fail(code, __VA_ARGS__); } while (0)
+
+static hm_status check_frame(const hm_frame *f)
+{
+    REQUIRE(f, HM_ERR_INVALID, "frame is NULL");
+    REQUIRE(f->n_scenes >= 1, HM_ERR_INVALID, "frame.n_scenes must be >= 1");
+    REQUIRE(f->width >= 1 && f->width <= 16384 && f->height >= 1 && f->height <= 16384,
+            HM_ERR_RANGE, "frame size %ux%u outside [1, 16384]", f->width, f->height);
+    const double pix = (double)f->width * f->height * f->n_scenes;
+    REQUIRE(pix < 4.0e9, HM_ERR_RANGE, "frame has too many pixels (%.0f)", pix);
+    return HM_OK;
+}
+
+static hm_status check_mesh(const hm_hair_mesh *m)
+{
+    REQUIRE(m, HM_ERR_INVALID, "mesh is NULL");
+    REQUIRE(m->layer_pos && m->quads && m->bundle_key && m->bundle_nstrands && m->bundle_cmax &&
+                m->bundle_scene,
+            HM_ERR_INVALID, "mesh has a NULL array");
+    REQUIRE(m->n_bundles >= 1 && m->n_verts >= 1, HM_ERR_INVALID, "mesh has no bundles / vertices");
+    REQUIRE(m->n_layers >= 2 && m->n_layers <= 64, HM_ERR_RANGE, "n_layers %u outside [2, 64]",
+            m->n_layers);
+    return HM_OK;
+}
+
+static hm_status check_strands(const hm_strands *s)
+{
+    REQUIRE(s, HM_ERR_INVALID, "strands is NULL");
+    REQUIRE(s->pos_w && s->rgb && s->flags && s->scene_off, HM_ERR_INVALID,
+            "strands has a NULL array");
+    REQUIRE(s->n_scenes >= 1, HM_ERR_INVALID, "strands.n_scenes must be >= 1");
+    REQUIRE(s->cap >= 1 && s->cap < 0xFFFFFFFFu, HM_ERR_RANGE,
+            "strands.cap must be in [1, 2^32 - 2]");
+    return HM_OK;
+}
+
+static hm_status check_ws(void *ws, size_t have, size_t need)
+{
+    REQUIRE(have >= need, HM_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", have, need);
+    REQUIRE(need == 0 || ws, HM_ERR_INVALID, "workspace is NULL");
+    return HM_OK;
+}
+
+static hm_status check_raster_params(const hm_raster_params *p)
+{
+    REQUIRE(p, HM_ERR_INVALID, "raster params NULL");
+    REQUIRE(p->algo == HM_RASTER_TILED || p->algo == HM_RASTER_DIRECT, HM_ERR_INVALID,
+            "unknown raster algo %d", p->algo);
+    REQUIRE(p->tile == 8 || p->tile == 16 || p->tile == 32, HM_ERR_RANGE,
+            "tile must be 8, 16 or 32 (got %u)", p->tile);
+    REQUIRE(p->chunk >= 1 && p->chunk <= (1u << 20), HM_ERR_RANGE, "chunk outside [1, 2^20]");
+    REQUIRE(p->max_tiles_per_seg >= 1 && p->max_tiles_per_seg <= 64, HM_ERR_RANGE,
+            "max_tiles_per_seg outside [1, 64]");
+    REQUIRE(p->block >= 64 && p->block <= 1024 && p->block % 64 == 0, HM_ERR_RANGE,
+            "block must be a multiple of 64 in [64, 1024]");
+    REQUIRE(p->grid <= 65536, HM_ERR_RANGE, "grid outside [0, 65536]");
+    REQUIRE(isfinite(p->r_min) && p->r_min >= 0.0f && p->r_min <= 64.0f, HM_ERR_RANGE,
+            "r_min outside [0, 64]");
+    return HM_OK;
+}
+
+static hm_status make_shade(const hm_shade_params *p, ShadeK &k)
+{
+    REQUIRE(p, HM_ERR_INVALID, "shade params NULL");
+    REQUIRE(p->mode == HM_RESOLVE_FILTER || p->mode == HM_RESOLVE_SOFT ||
+                p->mode == HM_RESOLVE_CENTER,
+            HM_ERR_INVALID, "unknown resolve mode %d", p->mode);
+    REQUIRE(p->filter_radius >= 0 && p->filter_radius <= 8, HM_ERR_RANGE,
+            "filter_radius outside [0, 8]");
+    REQUIRE(p->spec_squarings >= 0 && p->spec_squarings <= 8, HM_ERR_RANGE,
+            "spec_squarings outside [0, 8]");
+    REQUIRE(p->s_par > 0 && p->s_perp > 0 && p->sigma_c > 0 && p->iso_scale > 0 &&
+                p->soft_sigma > 0,
+            HM_ERR_RANGE, "filter / soft sigmas must be > 0");
+    REQUIRE(p->depth_reject >= 0 && p->depth_reject < 1 && p->depth_mismatch >= 0 &&
+                p->depth_mismatch < 1,
+            HM_ERR_RANGE, "depth thresholds outside [0, 1)");
+    const double lx = p->light_dir[0], ly = p->light_dir[1], lz = p->light_dir[2];
+    const double ln = sqrt(lx * lx + ly * ly + lz * lz);
+    REQUIRE(ln > 0, HM_ERR_INVALID, "light_dir is zero");
+    k.Lx = (float)(lx / ln); k.Ly = (float)(ly / ln); k.Lz = (float)(lz / ln);
+    k.Er = p->light_rgb[0]; k.Eg = p->light_rgb[1]; k.Eb = p->light_rgb[2];
+    k.ka = p->ka; k.kd = p->kd; k.ks = p->ks;
+    k.nsq = p->spec_squarings;
+    k.r = p->filter_radius;
+    const double r = p->filter_radius > 0 ? p->filter_radius : 1;
+    const double spar = r * p->s_par, sperp = r * p->s_perp, siso = r * p->iso_scale;
+    k.inv_spar2 = (float)(1.0 / (spar * spar));
+    k.inv_sperp2 = (float)(1.0 / (sperp * sperp));
+    k.inv_siso2 = (float)(1.0 / (siso * siso));
+    k.inv_sc2 = (float)(1.0 / ((double)p->sigma_c * p->sigma_c));
+    // depth thresholds in 24-bit code units: reject |dq| > floor(t 2^24),
+    // mismatch when nearer by >= ceil(t 2^24)
+    k.dq_rej = (uint32_t)floor((double)p->depth_reject * 16777216.0);
+    k.dq_mis = (uint32_t)ceil((double)p->depth_mismatch * 16777216.0);
+    const float h = p->strip_half;
+    k.strip2 = h * h;
+    k.iso_len = p->iso_len;
+    k.soft_k = (float)(1.0 / ((double)p->soft_sigma * sqrt(2.0)));
+    k.bgr = p->bg[0]; k.bgg = p->bg[1]; k.bgb = p->bg[2];
+    k.mode = p->mode;
+    return HM_OK;
+}
+
+extern "C" {
+
+const char *hm_last_error(void) { return g_err; }
+
+int32_t hm_version(void) { return 100; }
+
+hm_status hm_raster_defaults(const hm_frame *frame, hm_raster_params *p)
+{
+    hm_status st = check_frame(frame);
+    if (st) return st;
+    REQUIRE(p, HM_ERR_INVALID, "params NULL");
+    raster_defaults(*frame, *p);
+    return ok();
+}
+
+hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bundles, uint32_t cap,
+                            const hm_raster_params *p, size_t *bytes)
+{
+    REQUIRE(bytes, HM_ERR_INVALID, "bytes is NULL");
+    hm_status st = check_frame(frame);
+    if (st) return st;
+    if (call == HM_CALL_LOD) {
+        REQUIRE(n_bundles >= 1, HM_ERR_INVALID, "n_bundles must be >= 1");
+        *bytes = lod_workspace(n_bundles);
+    } else if (call == HM_CALL_RASTER) {
+        REQUIRE(cap >= 1 && cap < 0xFFFFFFFFu, HM_ERR_RANGE, "cap outside [1, 2^32 - 2]");
+        hm_raster_params d;
+        if (!p) { raster_defaults(*frame, d); p = &d; }
+        st = check_raster_params(p);
+        if (st) return st;
+        *bytes = raster_workspace(*frame, cap, *p);
+    } else if (call == HM_CALL_RESOLVE) {
+        *bytes = resolve_workspace(*frame);
+    } else {
+        return fail(HM_ERR_INVALID, "unknown call %d", call);
+    }
+    return ok();
+}
+
+hm_status hm_lod_select(const hm_hair_mesh *mesh, const hm_camera *cams, const hm_frame *frame,
+                        const hm_lod_params *p, uint32_t *table, uint32_t *scene_off,
+                        uint64_t *totals, void *ws, size_t ws_bytes, void *stream)
+{
+    hm_status st;
+    if ((st = check_mesh(mesh)) || (st = check_frame(frame))) return st;
+    REQUIRE(cams && p && table && scene_off && totals, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(p->mode == HM_LOD_OFF || p->mode == HM_LOD_ON, HM_ERR_INVALID, "unknown LOD mode %d",
+            p->mode);
+    REQUIRE(isfinite(p->lambda) && p->lambda >= 0, HM_ERR_RANGE, "lambda must be finite, >= 0");
+    if ((st = check_ws(ws, ws_bytes, lod_workspace(mesh->n_bundles)))) return st;
+    launch_lod(*mesh, cams, *frame, *p, table, scene_off, totals, ws, (hipStream_t)stream);
+    return check_launch("hm_lod_select");
+}
+
+hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
+                              const uint32_t *strand_base, const float *strand_rgb,
+                              const hm_gen_params *p, const hm_strands *out, void *stream)
+{
+    hm_status st;
+    if ((st = check_mesh(mesh)) || (st = check_strands(out))) return st;
+    REQUIRE(table && p, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(!strand_rgb || strand_base, HM_ERR_INVALID, "strand_rgb needs strand_base");
+    REQUIRE(isfinite(p->width) && isfinite(p->curl_amp) && isfinite(p->curl_turns) &&
+                p->curl_turns >= 0,
+            HM_ERR_RANGE, "generation parameters must be finite (curl_turns >= 0)");
+    launch_generate(*mesh, table, strand_base, strand_rgb, *p, *out, (hipStream_t)stream);
+    return check_launch("hm_generate_strands");
+}
+
+hm_status hm_raster_vis(const hm_strands *s, const hm_camera *cams, const hm_frame *frame,
+                        const hm_raster_params *p, const float *scene_z, uint64_t *vis,
+                        void *ws, size_t ws_bytes, void *stream)
+{
+    hm_status st;
+    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = check_raster_params(p)))
+        return st;
+    REQUIRE(cams && vis, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(s->n_scenes == frame->n_scenes, HM_ERR_INVALID, "strands.n_scenes != frame.n_scenes");
+    const double tiles = (double)((frame->width + p->tile - 1) / p->tile) *
+                         ((frame->height + p->tile - 1) / p->tile) * frame->n_scenes;
+    REQUIRE(tiles < 1.0e9, HM_ERR_RANGE, "too many tiles");
+    REQUIRE((double)s->cap * p->max_tiles_per_seg < 4.0e9, HM_ERR_RANGE,
+            "cap * max_tiles_per_seg exceeds 32-bit bin offsets");
+    if ((st = check_ws(ws, ws_bytes, raster_workspace(*frame, s->cap, *p)))) return st;
+    launch_raster(*s, cams, *frame, *p, scene_z, vis, ws, (hipStream_t)stream);
+    return check_launch("hm_raster_vis");
+}
+
+hm_status hm_resolve_shade(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,
+                           const hm_frame *frame, const hm_shade_params *p, float *out_rgba,
+                           void *ws, size_t ws_bytes, void *stream)
+{
+    hm_status st;
+    ShadeK k;
+    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    REQUIRE(vis && cams && out_rgba, HM_ERR_INVALID, "NULL argument");
+    if (k.mode == HM_RESOLVE_FILTER) {
+        if ((st = check_ws(ws, ws_bytes, resolve_workspace(*frame)))) return st;
+    }
+    launch_resolve(*s, vis, cams, *frame, k, out_rgba, ws, (hipStream_t)stream);
+    return check_launch("hm_resolve_shade");
+}
+
+hm_status hm_resolve_shade_bwd(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,
+                               const hm_frame *frame, const hm_shade_params *p,
+                               const float *d_out, float *grad_pos_w, float *grad_rgb,
+                               void *stream)
+{
+    hm_status st;
+    ShadeK k;
+    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    REQUIRE(vis && cams && d_out && grad_pos_w && grad_rgb, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(k.mode == HM_RESOLVE_SOFT, HM_ERR_INVALID, "backward exists for the SOFT resolve only");
+    launch_resolve_bwd(*s, vis, cams, *frame, k, d_out, grad_pos_w, grad_rgb,
+                       (hipStream_t)stream);
+    return check_launch("hm_resolve_shade_bwd");
+}
+
+}  // extern "C"

@@ -1,0 +1,217 @@
+// Device-side building blocks of libhm (gfx950, wave64).
+//
+// Floating-point contract: the steps whose results decide integers (strand
+// hash -> uv, LOD counts, generation, projection, coverage predicates,
+// 24-bit depth code, filter strip decisions) use binary32 with the operation
+// order spelled out here, compiled with -ffp-contract=off and correctly
+// rounded division / square root, so they reproduce the same bits as any
+// IEEE binary32 evaluation of the same expressions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "hm.h"
+
+#define HM_EMPTY 0xFFFFFFFFFFFFFFFFull
+#define HM_ID_BITS 40
+#define HM_ID_MASK ((1ull << HM_ID_BITS) - 1ull)
+#define HM_ID_OPAQUE ((1ull << HM_ID_BITS) - 2ull)
+#define HM_QMAX 16777215u
+#define HM_ROOT 1u
+#define HM_TIP 2u
+
+namespace hm {
+
+// ----------------------------------------------------------------- hashing
+// PCG hash (Jarzynski & Olano 2020): LCG step + RXS-M-XS output permutation.
+__device__ __forceinline__ uint32_t pcg(uint32_t v)
+{
+    uint32_t s = v * 747796405u + 2891336453u;
+    uint32_t w = ((s >> ((s >> 28u) + 4u)) ^ s) * 277803737u;
+    return (w >> 22u) ^ w;
+}
+
+// top 24 bits as a float in [0, 1)
+__device__ __forceinline__ float unit24(uint32_t h) { return (float)(h >> 8) * 0x1p-24f; }
+
+__device__ __forceinline__ uint32_t bundle_hash(uint32_t seed, uint32_t key)
+{
+    return pcg(pcg(seed) ^ key);
+}
+
+__device__ __forceinline__ float fminx(float a, float b) { return a < b ? a : b; }
+__device__ __forceinline__ float fmaxx(float a, float b) { return a > b ? a : b; }
+
+// ----------------------------------------------------------------- camera
+struct Cam {
+    float R[9];
+    float ex, ey, ez;
+    float fx, fy, cx, cy, zn, zf;
+};
+
+__device__ __forceinline__ Cam load_cam(const hm_camera *c)
+{
+    Cam k;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) k.R[i] = c->R[i];
+    k.ex = c->eye[0]; k.ey = c->eye[1]; k.ez = c->eye[2];
+    k.fx = c->fx; k.fy = c->fy; k.cx = c->cx; k.cy = c->cy;
+    k.zn = c->znear; k.zf = c->zfar;
+    return k;
+}
+
+// Camera-space coordinates: rows of R dotted with (P - eye), summed left to right.
+__device__ __forceinline__ void to_camera(const Cam &c, float px, float py, float pz,
+                                         float &X, float &Y, float &Z)
+{
+    float dx = px - c.ex, dy = py - c.ey, dz = pz - c.ez;
+    X = (c.R[0] * dx + c.R[1] * dy) + c.R[2] * dz;
+    Y = (c.R[3] * dx + c.R[4] * dy) + c.R[5] * dz;
+    Z = (c.R[6] * dx + c.R[7] * dy) + c.R[8] * dz;
+}
+
+// Screen record of a control point: (x_px, y_px, width_px, 1/z); 1/z = 0 marks
+// a point outside the open depth range (znear, zfar).
+__device__ __forceinline__ float4 project(const Cam &c, float4 p)
+{
+    float X, Y, Z;
+    to_camera(c, p.x, p.y, p.z, X, Y, Z);
+    if (!(Z > c.zn && Z < c.zf)) return make_float4(0.f, 0.f, 0.f, 0.f);
+    float iz = 1.0f / Z;
+    float4 o;
+    o.x = c.cx + c.fx * (X * iz);
+    o.y = c.cy - c.fy * (Y * iz);
+    o.z = p.w * (c.fy * iz);
+    o.w = iz;
+    return o;
+}
+
+// 24-bit normalised linear depth, truncated and clamped.
+__device__ __forceinline__ uint32_t depth_code(float z, float zn, float inv_range)
+{
+    float d = (z - zn) * inv_range;
+    float fq = d * 16777216.0f;
+    if (!(fq > 0.0f)) return 0u;
+    if (fq >= 16777215.0f) return HM_QMAX;
+    return (uint32_t)fq;
+}
+
+// ----------------------------------------------------------------- coverage
+// Per-segment constants of the two coverage tests.
+struct Seg {
+    float x0, y0, w0, iz0;
+    float dx, dy, dw, diz;
+    float len2, ilen2, ra;
+    float sxmn, sxmx, symn, symx;
+};
+
+__device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
+{
+    Seg s;
+    s.x0 = a.x; s.y0 = a.y; s.w0 = a.z; s.iz0 = a.w;
+    s.dx = b.x - a.x;
+    s.dy = b.y - a.y;
+    s.dw = b.z - a.z;
+    s.diz = b.w - a.w;
+    s.len2 = s.dx * s.dx + s.dy * s.dy;
+    s.ilen2 = s.len2 > 0.0f ? 1.0f / s.len2 : 0.0f;
+    float ra = 0.5f * fmaxx(a.z, b.z);
+    s.ra = fmaxx(ra, r_min);
+    s.sxmn = fminx(a.x, b.x); s.sxmx = fmaxx(a.x, b.x);
+    s.symn = fminx(a.y, b.y); s.symx = fmaxx(a.y, b.y);
+    return s;
+}
+
+// Coverage of pixel (i, j): bit0 centre sample, bit1 conservative; *q gets the
+// depth code at the clamped closest point when either bit is set.
+__device__ __forceinline__ uint32_t cover(const Seg &s, int i, int j, float r_min, float zn,
+                                          float inv_range, uint32_t &q)
+{
+    float fi = (float)i, fj = (float)j;
+    float ux = (fi + 0.5f) - s.x0;
+    float uy = (fj + 0.5f) - s.y0;
+    float tn = ux * s.dx + uy * s.dy;
+    bool centre;
+    if (s.len2 > 0.0f) {
+        float t = tn * s.ilen2;
+        float wt = s.w0 + t * s.dw;
+        float r = fmaxx(0.5f * wt, r_min);
+        float cr = ux * s.dy - uy * s.dx;
+        centre = (tn >= 0.0f) && (tn < s.len2) && (cr * cr <= (r * r) * s.len2);
+    } else {
+        float r = fmaxx(0.5f * s.w0, r_min);
+        centre = (ux * ux + uy * uy) <= r * r;
+    }
+    float bx0 = fi - s.ra, bx1 = (fi + 1.0f) + s.ra;
+    float by0 = fj - s.ra, by1 = (fj + 1.0f) + s.ra;
+    bool cons = (s.sxmn <= bx1) && (s.sxmx >= bx0) && (s.symn <= by1) && (s.symx >= by0);
+    if (cons) {
+        float fa = (bx0 - s.x0) * s.dy, fb = (bx1 - s.x0) * s.dy;
+        float ga = (by0 - s.y0) * s.dx, gb = (by1 - s.y0) * s.dx;
+        float lo = fminx(fa, fb) - fmaxx(ga, gb);
+        float hi = fmaxx(fa, fb) - fminx(ga, gb);
+        cons = (lo <= 0.0f) && (hi >= 0.0f);
+    }
+    if (!(centre || cons)) return 0u;
+    float ts = tn * s.ilen2;
+    ts = fmaxx(ts, 0.0f);
+    ts = fminx(ts, 1.0f);
+    float iz = s.iz0 + ts * s.diz;
+    float z = 1.0f / iz;
+    q = depth_code(z, zn, inv_range);
+    return (centre ? 1u : 0u) | (cons ? 2u : 0u);
+}
+
+// Scene of control point c: last s with scene_off[s] <= c (scene_off non-decreasing).
+__device__ __forceinline__ uint32_t scene_of(const uint32_t *scene_off, uint32_t n_scenes,
+                                             uint32_t c)
+{
+    uint32_t lo = 0, hi = n_scenes;      // invariant: scene_off[lo] <= c < scene_off[hi]
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (scene_off[mid] <= c) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ----------------------------------------------------------------- wave / block scans
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+template <typename T>
+__device__ __forceinline__ T wave_inclusive_scan(T x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan over the block; lds must hold blockDim.x / 64 values.  Returns
+// the exclusive prefix and writes the block total to `total`.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T *lds, T &total)
+{
+    const int lane = lane_id();
+    const int wid = (int)(threadIdx.x >> 6);
+    const int nw = (int)(blockDim.x >> 6);
+    T inc = wave_inclusive_scan(x);
+    if (lane == 63) lds[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        T v = lane < nw ? lds[lane] : (T)0;
+        T vi = wave_inclusive_scan(v);
+        if (lane < nw) lds[lane] = vi - v;
+        if (lane == nw - 1) lds[nw] = vi;
+    }
+    __syncthreads();
+    T res = inc - x + lds[wid];
+    total = lds[nw];
+    __syncthreads();
+    return res;
+}
+
+}  // namespace hm

@@ -1,0 +1,58 @@
+// Host-side launchers shared by the C-ABI layer (hm_api.hip) and the kernel
+// translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hm.h"
+
+namespace hm {
+
+// Resolve constants prepared on the host.
+struct ShadeK {
+    float Lx, Ly, Lz;          // normalised direction towards the light
+    float Er, Eg, Eb;          // light colour
+    float ka, kd, ks;
+    int nsq;                   // specular squarings
+    int r;                     // filter radius
+    float inv_spar2, inv_sperp2, inv_siso2, inv_sc2;
+    uint32_t dq_rej, dq_mis;   // depth thresholds in 24-bit code units
+    float strip2;              // squared strip half width (binary32)
+    float iso_len;
+    float soft_k;              // 1 / (sigma * sqrt(2))
+    float bgr, bgg, bgb;
+    int mode;
+};
+
+size_t align_up(size_t x, size_t a = 256);
+
+// LOD + generation
+void launch_lod(const hm_hair_mesh &m, const hm_camera *cams, const hm_frame &f,
+                const hm_lod_params &p, uint32_t *table, uint32_t *scene_off, uint64_t *totals,
+                void *ws, hipStream_t st);
+size_t lod_workspace(uint32_t n_bundles);
+void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
+                     const float *strand_rgb, const hm_gen_params &p, const hm_strands &s,
+                     hipStream_t st);
+
+// rasterization
+size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p);
+void raster_defaults(const hm_frame &f, hm_raster_params &p);
+void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,
+                   const hm_raster_params &p, const float *scene_z, uint64_t *vis, void *ws,
+                   hipStream_t st);
+
+// resolve
+size_t resolve_workspace(const hm_frame &f);
+void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *cams,
+                    const hm_frame &f, const ShadeK &k, float *out, void *ws, hipStream_t st);
+void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camera *cams,
+                        const hm_frame &f, const ShadeK &k, const float *d_out, float *gpos,
+                        float *grgb, hipStream_t st);
+
+// number of workgroups for grid-stride kernels
+uint32_t stride_grid(size_t n, uint32_t block);
+
+}  // namespace hm

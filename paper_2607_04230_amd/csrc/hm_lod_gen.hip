@@ -1,0 +1,342 @@
+// LOD pre-pass (Sec. 3.2) and strand generation (Sec. 3.1.1) for gfx950.
+//
+// The paper dispatches one workgroup per strand indirectly from the LOD
+// buffer.  HIP has no indirect dispatch, so the LOD pass writes the per-bundle
+// counts, a device prefix sum turns them into offsets, and generation is a
+// grid-stride loop over control points (one thread per CP, coalesced 16-byte
+// stores) that locates its bundle by binary search in the offset table.  The
+// per-CP work (four bilinear layer points, two tangents, a Hermite step and
+// the curl) reads the bundle's mesh data from cache, so no shuffles or LDS
+// staging are needed to avoid redundant memory traffic.
+#include "hm_device.hpp"
+#include "hm_internal.hpp"
+#include "hm_scan.hpp"
+
+namespace hm {
+
+// ------------------------------------------------------------------ LOD
+__device__ __forceinline__ void lod_counts(float L, uint32_t N, float delta, uint32_t cmax,
+                                           uint32_t n_layers, uint32_t &n_lod, uint32_t &cps)
+{
+    int n = (int)ceilf(L * ((float)N + delta));
+    n = n < 1 ? 1 : n;
+    n = n > (int)N ? (int)N : n;
+    n_lod = (uint32_t)n;
+    int craw = (int)floorf(sqrtf(L) * (float)cmax);
+    craw = craw < (int)n_layers ? (int)n_layers : craw;
+    uint32_t p2 = 1u << (31 - __clz((uint32_t)(craw - 1)));   // 2^floor(log2(craw - 1))
+    uint32_t c = p2 + 1u;
+    cps = c > cmax ? cmax : c;
+}
+
+__global__ __launch_bounds__(256) void k_lod(hm_hair_mesh m, const hm_camera *cams, uint32_t W,
+                                             uint32_t H, int mode, float lambda, uint32_t seed,
+                                             uint32_t *table, uint64_t *cnt_s, uint64_t *cnt_c)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= m.n_bundles) return;
+    const uint32_t N = m.bundle_nstrands[b];
+    const uint32_t cmax = m.bundle_cmax[b] < 2u ? 2u : m.bundle_cmax[b];   // C >= 2 always
+    uint32_t n = N, cp = cmax;
+    if (mode == HM_LOD_ON && N > 0) {
+        const Cam c = load_cam(cams + m.bundle_scene[b]);
+        const uint4 q = reinterpret_cast<const uint4 *>(m.quads)[b];
+        const uint32_t qi[4] = {q.x, q.y, q.z, q.w};
+        float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
+        uint32_t n_near = 0;
+        for (uint32_t l = 0; l < m.n_layers; ++l) {
+            const float *lay = m.layer_pos + (size_t)l * m.n_verts * 3;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float *P = lay + (size_t)qi[k] * 3;
+                float X, Y, Z;
+                to_camera(c, P[0], P[1], P[2], X, Y, Z);
+                if (Z <= c.zn) { n_near++; continue; }
+                float iz = 1.0f / Z;
+                float x = c.cx + c.fx * (X * iz);
+                float y = c.cy - c.fy * (Y * iz);
+                xmn = fminx(x, xmn); xmx = fmaxx(x, xmx);
+                ymn = fminx(y, ymn); ymx = fmaxx(y, ymx);
+            }
+        }
+        bool keep = true;
+        float L = 1.0f;
+        if (n_near == 4u * m.n_layers) {
+            keep = false;
+        } else if (n_near == 0) {
+            if (xmx < 0.0f || xmn > (float)W || ymx < 0.0f || ymn > (float)H) {
+                keep = false;
+            } else {
+                float ex = xmx - xmn, ey = ymx - ymn;
+                float diag = sqrtf(ex * ex + ey * ey);
+                L = (diag / (float)H) * lambda;
+                L = fmaxx(L, 0.0f);
+                L = fminx(L, 1.0f);
+            }
+        }
+        if (!keep) {
+            n = 0;
+        } else {
+            const float delta =
+                unit24(pcg(bundle_hash(seed, m.bundle_key[b]) ^ 0xA511E9B3u));
+            lod_counts(L, N, delta, cmax, m.n_layers, n, cp);
+        }
+    }
+    if (n == 0) cp = 0;
+    table[4 * (size_t)b + 0] = n;
+    table[4 * (size_t)b + 1] = cp;
+    cnt_s[b] = n;
+    cnt_c[b] = (uint64_t)n * cp;
+}
+
+__global__ __launch_bounds__(256) void k_lod_finish(uint32_t *table, const uint64_t *off_s,
+                                                    const uint64_t *off_c, uint32_t B,
+                                                    const uint32_t *bundle_scene, uint32_t S,
+                                                    uint32_t *scene_off, uint64_t *totals)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t lim = 0xFFFFFFFFull;
+    if (t < B) {
+        table[4 * (size_t)t + 2] = (uint32_t)(off_s[t] < lim ? off_s[t] : lim);
+        table[4 * (size_t)t + 3] = (uint32_t)(off_c[t] < lim ? off_c[t] : lim);
+    }
+    if (t <= S) {
+        // first bundle with scene >= t (bundle_scene is non-decreasing)
+        uint32_t lo = 0, hi = B;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (bundle_scene[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        uint64_t o = off_c[lo];   // off_c[B] is the total
+        scene_off[t] = (uint32_t)(o < lim ? o : lim);
+    }
+    if (t == 0) {
+        totals[0] = off_s[B];
+        totals[1] = off_c[B];
+    }
+}
+
+size_t lod_workspace(uint32_t B)
+{
+    size_t nb = scan_blocks(B) + 1;
+    return 2 * align_up(sizeof(uint64_t) * ((size_t)B + 1)) + 2 * align_up(sizeof(uint64_t) * nb);
+}
+
+void launch_lod(const hm_hair_mesh &m, const hm_camera *cams, const hm_frame &f,
+                const hm_lod_params &p, uint32_t *table, uint32_t *scene_off, uint64_t *totals,
+                void *ws, hipStream_t st)
+{
+    const uint32_t B = m.n_bundles;
+    char *w = (char *)ws;
+    uint64_t *cs = (uint64_t *)w;
+    w += align_up(sizeof(uint64_t) * ((size_t)B + 1));
+    uint64_t *cc = (uint64_t *)w;
+    w += align_up(sizeof(uint64_t) * ((size_t)B + 1));
+    const size_t nb = scan_blocks(B) + 1;
+    uint64_t *ps = (uint64_t *)w;
+    w += align_up(sizeof(uint64_t) * nb);
+    uint64_t *pc = (uint64_t *)w;
+    hipLaunchKernelGGL(k_lod, dim3((B + 255) / 256), dim3(256), 0, st, m, cams, f.width,
+                       f.height, (int)p.mode, p.lambda, p.seed, table, cs, cc);
+    scan_exclusive<uint64_t>(cs, cs, B, ps, st);
+    scan_exclusive<uint64_t>(cc, cc, B, pc, st);
+    const uint32_t n = (B > f.n_scenes + 1 ? B : f.n_scenes + 1);
+    hipLaunchKernelGGL(k_lod_finish, dim3((n + 255) / 256), dim3(256), 0, st, table,
+                       (const uint64_t *)cs, (const uint64_t *)cc, B, m.bundle_scene,
+                       f.n_scenes, scene_off, totals);
+}
+
+// ------------------------------------------------------------------ generation
+// Taylor polynomials of sin (degree 17) and cos (degree 16) about 0 in Horner
+// form in a^2, coefficients = binary32 nearest 1/n!; argument in [-pi, pi).
+__device__ __forceinline__ float tsin(float a)
+{
+    const float s = a * a;
+    float p = 0x1.952c78p-49f;
+    p = -0x1.ae7f3ep-41f + s * p;
+    p = 0x1.612462p-33f + s * p;
+    p = -0x1.ae6456p-26f + s * p;
+    p = 0x1.71de3ap-19f + s * p;
+    p = -0x1.a01a02p-13f + s * p;
+    p = 0x1.111112p-7f + s * p;
+    p = -0x1.555556p-3f + s * p;
+    return a + (a * s) * p;
+}
+
+__device__ __forceinline__ float tcos(float a)
+{
+    const float s = a * a;
+    float p = 0x1.ae7f3ep-45f;
+    p = -0x1.93974ap-37f + s * p;
+    p = 0x1.1eed8ep-29f + s * p;
+    p = -0x1.27e4fcp-22f + s * p;
+    p = 0x1.a01a02p-16f + s * p;
+    p = -0x1.6c16c2p-10f + s * p;
+    p = 0x1.555556p-5f + s * p;
+    p = -0x1.0p-1f + s * p;
+    return 1.0f + s * p;
+}
+
+struct F3 { float x, y, z; };
+
+__device__ __forceinline__ F3 f3sub(F3 a, F3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ F3 f3norm(F3 a)
+{
+    float n2 = (a.x * a.x + a.y * a.y) + a.z * a.z;
+    if (n2 > 0.0f) {
+        float inv = 1.0f / sqrtf(n2);
+        return {a.x * inv, a.y * inv, a.z * inv};
+    }
+    return {0.0f, 0.0f, 0.0f};
+}
+__device__ __forceinline__ F3 f3cross(F3 a, F3 b)
+{
+    return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ F3 ld3(const float *p) { return {p[0], p[1], p[2]}; }
+
+// Base point of layer l at bilinear coordinates (u, v): lerp along AB and DC
+// by u, then between the two by v.
+__device__ __forceinline__ F3 layer_point(const float *layer_pos, uint32_t n_verts, uint32_t l,
+                                          const uint32_t q[4], float u, float v)
+{
+    const float *L0 = layer_pos + (size_t)l * n_verts * 3;
+    F3 A = ld3(L0 + 3 * (size_t)q[0]), B = ld3(L0 + 3 * (size_t)q[1]);
+    F3 C = ld3(L0 + 3 * (size_t)q[2]), D = ld3(L0 + 3 * (size_t)q[3]);
+    F3 ab = {A.x + u * (B.x - A.x), A.y + u * (B.y - A.y), A.z + u * (B.z - A.z)};
+    F3 dc = {D.x + u * (C.x - D.x), D.y + u * (C.y - D.y), D.z + u * (C.z - D.z)};
+    return {ab.x + v * (dc.x - ab.x), ab.y + v * (dc.y - ab.y), ab.z + v * (dc.z - ab.z)};
+}
+
+struct GenK {
+    uint32_t seed;
+    float width, curl_amp, curl_turns;
+    float br, bg, bb;
+};
+
+__global__ __launch_bounds__(256) void k_generate(hm_hair_mesh m, const uint32_t *table,
+                                                  const uint32_t *strand_base,
+                                                  const float *strand_rgb, GenK g,
+                                                  float4 *pos_w, float4 *rgb, uint8_t *flags,
+                                                  const uint32_t *scene_off, uint32_t S,
+                                                  uint32_t cap)
+{
+    const uint32_t total = scene_off[S];
+    const uint32_t n_cp = total < cap ? total : cap;
+    const uint32_t B = m.n_bundles, NL = m.n_layers;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cp;
+         c += gridDim.x * blockDim.x) {
+        // bundle owning CP c: last b with first-CP offset <= c
+        uint32_t lo = 0, hi = B;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (table[4 * (size_t)mid + 3] <= c) lo = mid; else hi = mid;
+        }
+        const uint32_t b = lo;
+        const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
+        const uint32_t C = tb.y;
+        const uint32_t rel = c - tb.w;
+        const uint32_t k = rel / C;
+        const uint32_t j = rel - k * C;
+
+        const uint32_t h1 = pcg(bundle_hash(g.seed, m.bundle_key[b]) + k);
+        const uint32_t h2 = pcg(h1);
+        const uint32_t h3 = pcg(h2);
+        const float u = unit24(h1), v = unit24(h2), ph = unit24(h3);
+
+        const uint4 q4 = reinterpret_cast<const uint4 *>(m.quads)[b];
+        const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
+
+        const float w = (float)j / (float)(C - 1u);
+        const float x = w * (float)(NL - 1u);
+        int i = (int)x;
+        i = i > (int)NL - 2 ? (int)NL - 2 : i;
+        const float t = x - (float)i;
+
+        // base points needed by the interval [i, i+1] and its two tangents
+        const F3 Pi = layer_point(m.layer_pos, m.n_verts, i, q, u, v);
+        const F3 Pj = layer_point(m.layer_pos, m.n_verts, i + 1, q, u, v);
+        F3 Ti, Tj;
+        if (i == 0) {
+            Ti = f3norm(f3sub(Pj, Pi));
+        } else {
+            const F3 Pm = layer_point(m.layer_pos, m.n_verts, i - 1, q, u, v);
+            Ti = f3norm(f3sub(Pj, Pm));
+        }
+        if (i + 1 == (int)NL - 1) {
+            Tj = f3norm(f3sub(Pj, Pi));
+        } else {
+            const F3 Pp = layer_point(m.layer_pos, m.n_verts, i + 2, q, u, v);
+            Tj = f3norm(f3sub(Pp, Pi));
+        }
+        const F3 ch = f3sub(Pj, Pi);
+        const float chord = sqrtf((ch.x * ch.x + ch.y * ch.y) + ch.z * ch.z);
+        const float t2 = t * t, t3 = t2 * t;
+        const float h00 = (2.0f * t3 - 3.0f * t2) + 1.0f;
+        const float h10 = (t3 - 2.0f * t2) + t;
+        const float h01 = 3.0f * t2 - 2.0f * t3;
+        const float h11 = t3 - t2;
+        const float pi3[3] = {Pi.x, Pi.y, Pi.z}, pj3[3] = {Pj.x, Pj.y, Pj.z};
+        const float ti3[3] = {Ti.x, Ti.y, Ti.z}, tj3[3] = {Tj.x, Tj.y, Tj.z};
+        float X[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float m0 = chord * ti3[d], m1 = chord * tj3[d];
+            X[d] = ((h00 * pi3[d] + h10 * m0) + h01 * pj3[d]) + h11 * m1;
+        }
+
+        // bundle styling frame from the first layer interval
+        F3 s0 = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            const F3 a0 = ld3(m.layer_pos + 3 * (size_t)q[k2]);
+            const F3 a1 = ld3(m.layer_pos + ((size_t)m.n_verts + q[k2]) * 3);
+            const F3 d = f3sub(a1, a0);
+            s0.x = s0.x + d.x; s0.y = s0.y + d.y; s0.z = s0.z + d.z;
+        }
+        const F3 nb = f3norm(s0);
+        F3 ax = {0.0f, 0.0f, 1.0f};
+        if (fabsf(nb.z) > 0.9f) { ax.x = 1.0f; ax.z = 0.0f; }
+        const F3 e1 = f3norm(f3cross(nb, ax));
+        const F3 e2 = f3cross(nb, e1);
+
+        float f = g.curl_turns * w + ph;
+        f = f - floorf(f);
+        const float a = (f - 0.5f) * 0x1.921fb6p+2f;
+        const float cth = -tcos(a), sth = -tsin(a);
+        const float amp = g.curl_amp * w;
+        float4 o;
+        o.x = X[0] + amp * (cth * e1.x + sth * e2.x);
+        o.y = X[1] + amp * (cth * e1.y + sth * e2.y);
+        o.z = X[2] + amp * (cth * e1.z + sth * e2.z);
+        o.w = g.width;
+        pos_w[c] = o;
+        float4 col;
+        if (strand_rgb) {
+            const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k);
+            col = make_float4(sr[0], sr[1], sr[2], 1.0f);
+        } else {
+            col = make_float4(g.br, g.bg, g.bb, 1.0f);
+        }
+        rgb[c] = col;
+        uint8_t fl = 0;
+        if (j == 0) fl |= (uint8_t)HM_ROOT;
+        if (j == C - 1u) fl |= (uint8_t)HM_TIP;
+        flags[c] = fl;
+    }
+}
+
+void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
+                     const float *strand_rgb, const hm_gen_params &p, const hm_strands &s,
+                     hipStream_t st)
+{
+    GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
+           p.base_rgb[2]};
+    const uint32_t grid = stride_grid(s.cap, 256);
+    hipLaunchKernelGGL(k_generate, dim3(grid), dim3(256), 0, st, m, table, strand_base,
+                       strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
+                       reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
+                       s.cap);
+}
+
+}  // namespace hm

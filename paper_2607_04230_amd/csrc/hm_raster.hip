@@ -1,0 +1,512 @@
+// Visibility-buffer rasterization (Sec. 3.1.2) for gfx950.
+//
+// The paper draws every styled segment with a DDA line and a 64-bit
+// image atomicMin per pixel and layer.  Here:
+//   1. k_prefill writes both layers (empty or the opaque scene depth);
+//   2. k_project computes each control point's screen record once;
+//   3. TILED path: k_bin counts, then scatters, segment ids into per-screen-
+//      tile lists (T x T pixels), with wave-level ballot aggregation of the
+//      list atomics; an exclusive scan turns counts into offsets and each tile
+//      is cut into work items of `chunk` segments;
+//   4. k_raster_tiles is a persistent kernel: each workgroup pulls work items
+//      from a device counter, keeps the tile's two layers in LDS, resolves all
+//      coverage with LDS ds_min_u64, then merges the touched pixels into the
+//      global buffer with one 64-bit atomic min each;
+//   5. segments touching more than `max_tiles_per_seg` tiles go to a list
+//      rasterized by k_raster_long (one wave per segment, global atomics).
+// The DIRECT path (one thread per segment, global atomics everywhere) is kept
+// as the reference launch shape.  Every path evaluates the same binary32
+// predicates per pixel, and min is order-independent, so the buffer is
+// bit-identical across paths and tuning parameters.
+#include "hm_device.hpp"
+#include "hm_internal.hpp"
+#include "hm_scan.hpp"
+
+namespace hm {
+
+struct RasterK {
+    uint32_t S, W, H;
+    float r_min;
+    uint32_t T, ntx, nty, n_tiles;
+    uint32_t chunk, K;
+};
+
+// ------------------------------------------------------------------ prefill
+__global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *scene_z,
+                                                 const hm_camera *cams, uint32_t S, uint32_t W,
+                                                 uint32_t H)
+{
+    const size_t hw = (size_t)W * H;
+    const size_t n = hw * S;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
+         p += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t s = (uint32_t)(p / hw);
+        const size_t loc = p - (size_t)s * hw;
+        uint64_t key = HM_EMPTY;
+        if (scene_z) {
+            const float z = scene_z[p];
+            const float zn = cams[s].znear, zf = cams[s].zfar;
+            if (z > zn && z < zf) {
+                const float inv_range = 1.0f / (zf - zn);
+                key = ((uint64_t)depth_code(z, zn, inv_range) << HM_ID_BITS) | HM_ID_OPAQUE;
+            }
+        }
+        uint64_t *base = vis + (size_t)s * 2 * hw;
+        base[loc] = key;
+        base[hw + loc] = key;
+    }
+}
+
+// ------------------------------------------------------------------ projection
+__global__ __launch_bounds__(256) void k_project(const float4 *pos_w, const uint32_t *scene_off,
+                                                 uint32_t S, const hm_camera *cams, uint32_t cap,
+                                                 float4 *proj)
+{
+    const uint32_t total = scene_off[S];
+    const uint32_t n = total < cap ? total : cap;
+    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const uint32_t s = scene_of(scene_off, S, c);
+        const Cam cam = load_cam(cams + s);
+        proj[c] = project(cam, pos_w[c]);
+    }
+}
+
+// ------------------------------------------------------------------ helpers
+// Candidate pixel box of a segment (superset of every pixel either predicate
+// can accept), clipped to the image.  Returns false if empty.
+__device__ __forceinline__ bool seg_box(const Seg &sg, uint32_t W, uint32_t H, int &i0, int &i1,
+                                        int &j0, int &j1)
+{
+    const float xmn = sg.sxmn - sg.ra - 2.0f, xmx = sg.sxmx + sg.ra + 2.0f;
+    const float ymn = sg.symn - sg.ra - 2.0f, ymx = sg.symx + sg.ra + 2.0f;
+    if (!(xmx >= 0.0f && ymx >= 0.0f && xmn <= (float)W && ymn <= (float)H)) return false;
+    i0 = xmn > 0.0f ? (int)xmn : 0;
+    j0 = ymn > 0.0f ? (int)ymn : 0;
+    i1 = xmx < (float)(W - 1) ? (int)xmx : (int)W - 1;
+    j1 = ymx < (float)(H - 1) ? (int)ymx : (int)H - 1;
+    return i0 <= i1 && j0 <= j1;
+}
+
+// Column range of candidate pixels in row j: the part of the segment whose y
+// lies within the row band widened by ra + 1.5 px, widened by ra + 1.5 px in x.
+__device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
+{
+    const float m = sg.ra + 1.5f;
+    const float ylo = (float)j - m, yhi = ((float)j + 1.0f) + m;
+    float xlo = sg.sxmn, xhi = sg.sxmx;
+    if (fabsf(sg.dy) > 1e-3f) {
+        float ta = (ylo - sg.y0) / sg.dy, tb = (yhi - sg.y0) / sg.dy;
+        float t0 = fmaxx(fminx(ta, tb), 0.0f), t1 = fminx(fmaxx(ta, tb), 1.0f);
+        if (t0 > t1) { i0 = 1; i1 = 0; return; }
+        float xa = sg.x0 + t0 * sg.dx, xb = sg.x0 + t1 * sg.dx;
+        xlo = fminx(xa, xb);
+        xhi = fmaxx(xa, xb);
+    }
+    const float flo = xlo - m, fhi = xhi + m;
+    i0 = flo > -1.0e9f ? (int)floorf(flo) : -1000000000;
+    i1 = fhi < 1.0e9f ? (int)ceilf(fhi) : 1000000000;
+}
+
+__device__ __forceinline__ bool load_seg(const float4 *proj, const uint8_t *flags, uint32_t v,
+                                         uint32_t n_cp, float r_min, Seg &sg)
+{
+    if (v + 1 >= n_cp || (flags[v] & HM_TIP)) return false;
+    const float4 a = proj[v], b = proj[v + 1];
+    if (a.w == 0.0f || b.w == 0.0f) return false;
+    sg = make_seg(a, b, r_min);
+    return true;
+}
+
+__device__ __forceinline__ void scene_depth_consts(const hm_camera *cams, uint32_t s, float &zn,
+                                                   float &inv_range)
+{
+    zn = cams[s].znear;
+    inv_range = 1.0f / (cams[s].zfar - zn);
+}
+
+// ------------------------------------------------------------------ direct path
+__global__ __launch_bounds__(256) void k_raster_direct(const float4 *proj, const uint8_t *flags,
+                                                       const uint32_t *scene_off,
+                                                       const hm_camera *cams, RasterK rk,
+                                                       uint32_t cap, uint64_t *vis)
+{
+    const uint32_t total = scene_off[rk.S];
+    const uint32_t n = total < cap ? total : cap;
+    const size_t hw = (size_t)rk.W * rk.H;
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        Seg sg;
+        if (!load_seg(proj, flags, v, n, rk.r_min, sg)) continue;
+        int i0, i1, j0, j1;
+        if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
+        const uint32_t s = scene_of(scene_off, rk.S, v);
+        float zn, inv_range;
+        scene_depth_consts(cams, s, zn, inv_range);
+        uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
+        for (int j = j0; j <= j1; ++j) {
+            int a0, a1;
+            row_span(sg, j, a0, a1);
+            a0 = a0 > i0 ? a0 : i0;
+            a1 = a1 < i1 ? a1 : i1;
+            for (int i = a0; i <= a1; ++i) {
+                uint32_t q;
+                const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
+                if (!msk) continue;
+                const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
+                const size_t p = (size_t)j * rk.W + i;
+                if (msk & 1u) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
+                if (msk & 2u) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ binning
+// Tile-box test: can the segment reach any pixel of tile box [px0, px1) x
+// [py0, py1)?  Separating axes x, y and the segment normal on the box widened
+// by ra + 1 px (a superset of both predicates' support).
+__device__ __forceinline__ bool seg_hits_box(const Seg &sg, float px0, float px1, float py0,
+                                             float py1)
+{
+    const float m = sg.ra + 1.0f;
+    const float bx0 = px0 - m, bx1 = px1 + m, by0 = py0 - m, by1 = py1 + m;
+    if (!(sg.sxmn <= bx1 && sg.sxmx >= bx0 && sg.symn <= by1 && sg.symx >= by0)) return false;
+    const float fa = (bx0 - sg.x0) * sg.dy, fb = (bx1 - sg.x0) * sg.dy;
+    const float ga = (by0 - sg.y0) * sg.dx, gb = (by1 - sg.y0) * sg.dx;
+    const float lo = fminx(fa, fb) - fmaxx(ga, gb);
+    const float hi = fmaxx(fa, fb) - fminx(ga, gb);
+    // widen the sign test by a relative slack against rounding
+    const float slack = 1e-4f * (fabsf(fa) + fabsf(fb) + fabsf(ga) + fabsf(gb)) + 1e-3f;
+    return lo <= slack && hi >= -slack;
+}
+
+// pass 0: count per tile (+ long list); pass 1: scatter ids into the lists.
+__global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const uint8_t *flags,
+                                             const uint32_t *scene_off, RasterK rk, uint32_t cap,
+                                             uint32_t *tile_cnt, const uint32_t *tile_off,
+                                             uint32_t *tile_cur, uint32_t *entries,
+                                             uint32_t *long_list, uint32_t *counters)
+{
+    const uint32_t total = scene_off[rk.S];
+    const uint32_t n = total < cap ? total : cap;
+    const int lane = lane_id();
+    const uint64_t lt_mask = (1ull << lane) - 1ull;
+    // uniform trip count per wave: every lane of the wave runs the ballots
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    for (uint32_t base = base0; base < n; base += stride) {
+        const uint32_t v = base + lane;
+        Seg sg;
+        bool ok = v < n && load_seg(proj, flags, v, n, rk.r_min, sg);
+        int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
+        if (ok) ok = seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
+        uint32_t s = 0, tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0, nt = 0;
+        if (ok) {
+            s = scene_of(scene_off, rk.S, v);
+            tx0 = (uint32_t)i0 / rk.T; tx1 = (uint32_t)i1 / rk.T;
+            ty0 = (uint32_t)j0 / rk.T; ty1 = (uint32_t)j1 / rk.T;
+            nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            if (nt > rk.K) {
+                if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
+                ok = false;
+                nt = 0;
+            }
+        }
+        // iterate the k-th tile of every lane's box; aggregate equal tiles per wave
+        uint32_t maxnt = nt;
+        for (int d = 32; d >= 1; d >>= 1) {
+            uint32_t o = __shfl_xor(maxnt, d, 64);
+            maxnt = o > maxnt ? o : maxnt;
+        }
+        const uint32_t bw = tx1 - tx0 + 1;
+        for (uint32_t k = 0; k < maxnt; ++k) {
+            bool has = ok && k < nt;
+            uint32_t tile = 0;
+            if (has) {
+                const uint32_t tx = tx0 + k % bw, ty = ty0 + k / bw;
+                const float px0 = (float)(tx * rk.T), py0 = (float)(ty * rk.T);
+                has = seg_hits_box(sg, px0, px0 + (float)rk.T, py0, py0 + (float)rk.T);
+                tile = (s * rk.nty + ty) * rk.ntx + tx;
+            }
+            uint64_t active = __ballot(has);
+            while (active) {
+                const int leader = __ffsll((unsigned long long)active) - 1;
+                const uint32_t lt = __shfl(tile, leader, 64);
+                const bool mine = has && tile == lt;
+                const uint64_t same = __ballot(mine);
+                uint32_t b = 0;
+                if (lane == leader) {
+                    const uint32_t cnt = (uint32_t)__popcll(same);
+                    b = pass == 0 ? atomicAdd(&tile_cnt[lt], cnt) : atomicAdd(&tile_cur[lt], cnt);
+                }
+                b = __shfl(b, leader, 64);
+                if (mine) {
+                    if (pass == 1)
+                        entries[tile_off[lt] + b + (uint32_t)__popcll(same & lt_mask)] = v;
+                    has = false;
+                }
+                active &= ~same;
+            }
+        }
+    }
+}
+
+// items per tile = ceil(count / chunk); also resets the cursors.
+__global__ __launch_bounds__(256) void k_tile_items(const uint32_t *tile_off, uint32_t n_tiles,
+                                                    uint32_t chunk, uint32_t *items,
+                                                    uint32_t *tile_cur)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t c = tile_off[t + 1] - tile_off[t];
+    items[t] = (c + chunk - 1) / chunk;
+    tile_cur[t] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint32_t val)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = val;
+}
+
+// ------------------------------------------------------------------ tiled raster
+// Dynamic LDS: two layers of T*T keys.  Work items are pulled from counters[1].
+__global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
+                               const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
+                               uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
+                               const uint32_t *entries, uint32_t *counters, uint64_t *vis)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t sh_item;
+    const uint32_t TT = rk.T * rk.T;
+    uint64_t *lc = lds, *la = lds + TT;
+    const uint32_t total = scene_off[rk.S];
+    const uint32_t n = total < cap ? total : cap;
+    const uint32_t n_items = item_off[rk.n_tiles];
+    const size_t hw = (size_t)rk.W * rk.H;
+    const uint32_t tiles_per_scene = rk.ntx * rk.nty;
+    for (;;) {
+        if (threadIdx.x == 0) sh_item = atomicAdd(&counters[1], 1u);
+        for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
+            lc[x] = HM_EMPTY;
+            la[x] = HM_EMPTY;
+        }
+        __syncthreads();
+        const uint32_t item = sh_item;
+        if (item >= n_items) break;
+        // tile of the item: last t with item_off[t] <= item
+        uint32_t lo = 0, hi = rk.n_tiles;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (item_off[mid] <= item) lo = mid; else hi = mid;
+        }
+        const uint32_t t = lo;
+        const uint32_t beg = tile_off[t] + (item - item_off[t]) * rk.chunk;
+        const uint32_t end0 = beg + rk.chunk, tend = tile_off[t + 1];
+        const uint32_t end = end0 < tend ? end0 : tend;
+        const uint32_t s = t / tiles_per_scene;
+        const uint32_t r = t - s * tiles_per_scene;
+        const uint32_t ty = r / rk.ntx, tx = r - ty * rk.ntx;
+        const int px0 = (int)(tx * rk.T), py0 = (int)(ty * rk.T);
+        const int px1 = min(px0 + (int)rk.T, (int)rk.W) - 1;
+        const int py1 = min(py0 + (int)rk.T, (int)rk.H) - 1;
+        float zn, inv_range;
+        scene_depth_consts(cams, s, zn, inv_range);
+
+        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
+            const uint32_t v = entries[e];
+            Seg sg;
+            if (!load_seg(proj, flags, v, n, rk.r_min, sg)) continue;
+            int i0, i1, j0, j1;
+            if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
+            i0 = max(i0, px0); i1 = min(i1, px1);
+            j0 = max(j0, py0); j1 = min(j1, py1);
+            for (int j = j0; j <= j1; ++j) {
+                int a0, a1;
+                row_span(sg, j, a0, a1);
+                a0 = max(a0, i0);
+                a1 = min(a1, i1);
+                for (int i = a0; i <= a1; ++i) {
+                    uint32_t q;
+                    const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
+                    if (!msk) continue;
+                    const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | v;
+                    const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
+                    if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
+                    if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
+                }
+            }
+        }
+        __syncthreads();
+        uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
+        const uint32_t tw = (uint32_t)(px1 - px0 + 1);
+        for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
+            const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+            if (lx >= tw || (int)ly > py1 - py0) continue;
+            const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
+            const uint64_t kc = lc[x], ka = la[x];
+            if (kc != HM_EMPTY) atomicMin((unsigned long long *)(vc + p), (unsigned long long)kc);
+            if (ka != HM_EMPTY) atomicMin((unsigned long long *)(va + p), (unsigned long long)ka);
+        }
+        __syncthreads();
+    }
+}
+
+// One wave per long segment: lanes stride over its candidate rows.
+__global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const uint8_t *flags,
+                                                     const uint32_t *scene_off,
+                                                     const hm_camera *cams, RasterK rk,
+                                                     uint32_t cap, const uint32_t *long_list,
+                                                     const uint32_t *counters, uint64_t *vis)
+{
+    const uint32_t total = scene_off[rk.S];
+    const uint32_t n = total < cap ? total : cap;
+    const uint32_t n_long = counters[0];
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = lane_id();
+    const size_t hw = (size_t)rk.W * rk.H;
+    for (uint32_t e = wid; e < n_long; e += waves) {
+        const uint32_t v = long_list[e];
+        Seg sg;
+        if (!load_seg(proj, flags, v, n, rk.r_min, sg)) continue;
+        int i0, i1, j0, j1;
+        if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
+        const uint32_t s = scene_of(scene_off, rk.S, v);
+        float zn, inv_range;
+        scene_depth_consts(cams, s, zn, inv_range);
+        uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
+        for (int j = j0 + lane; j <= j1; j += 64) {
+            int a0, a1;
+            row_span(sg, j, a0, a1);
+            a0 = max(a0, i0);
+            a1 = min(a1, i1);
+            for (int i = a0; i <= a1; ++i) {
+                uint32_t q;
+                const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
+                if (!msk) continue;
+                const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
+                const size_t p = (size_t)j * rk.W + i;
+                if (msk & 1u) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
+                if (msk & 2u) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ host side
+static RasterK make_rk(const hm_frame &f, const hm_raster_params &p)
+{
+    RasterK rk;
+    rk.S = f.n_scenes;
+    rk.W = f.width;
+    rk.H = f.height;
+    rk.r_min = p.r_min;
+    rk.T = p.tile;
+    rk.ntx = (f.width + p.tile - 1) / p.tile;
+    rk.nty = (f.height + p.tile - 1) / p.tile;
+    rk.n_tiles = rk.ntx * rk.nty * f.n_scenes;
+    rk.chunk = p.chunk;
+    rk.K = p.max_tiles_per_seg;
+    return rk;
+}
+
+struct RasterWs {
+    float4 *proj;
+    uint32_t *tile_cnt;   // n_tiles + 1 (scanned in place into offsets)
+    uint32_t *tile_cur;   // n_tiles
+    uint32_t *items;      // n_tiles + 1 (scanned in place)
+    uint32_t *partials;   // scan scratch
+    uint32_t *counters;   // [0] long count, [1] work counter
+    uint32_t *long_list;  // cap
+    uint32_t *entries;    // cap * K
+    size_t bytes;
+};
+
+static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster_params &p)
+{
+    const RasterK rk = make_rk(f, p);
+    const size_t nt = rk.n_tiles;
+    char *b = (char *)ws;
+    size_t o = 0;
+    RasterWs w;
+    auto take = [&](size_t bytes) { char *r = b ? b + o : nullptr; o += align_up(bytes); return r; };
+    w.proj = (float4 *)take(sizeof(float4) * (size_t)cap);
+    w.tile_cnt = (uint32_t *)take(sizeof(uint32_t) * (nt + 1));
+    w.tile_cur = (uint32_t *)take(sizeof(uint32_t) * nt);
+    w.items = (uint32_t *)take(sizeof(uint32_t) * (nt + 1));
+    w.partials = (uint32_t *)take(sizeof(uint32_t) * (scan_blocks((uint32_t)nt) + 1));
+    w.counters = (uint32_t *)take(sizeof(uint32_t) * 64);
+    if (p.algo == HM_RASTER_TILED) {
+        w.long_list = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
+        w.entries = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap * p.max_tiles_per_seg);
+    } else {
+        w.long_list = nullptr;
+        w.entries = nullptr;
+    }
+    w.bytes = o;
+    return w;
+}
+
+size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p)
+{
+    return carve(nullptr, f, cap, p).bytes;
+}
+
+void raster_defaults(const hm_frame &f, hm_raster_params &p)
+{
+    (void)f;
+    p.r_min = 0.0f;
+    p.algo = HM_RASTER_TILED;
+    p.tile = 32;
+    p.chunk = 256;
+    p.max_tiles_per_seg = 4;
+    p.block = 256;
+    p.grid = 0;
+}
+
+void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,
+                   const hm_raster_params &p, const float *scene_z, uint64_t *vis, void *ws,
+                   hipStream_t st)
+{
+    const RasterK rk = make_rk(f, p);
+    RasterWs w = carve(ws, f, s.cap, p);
+    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
+    hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
+                       cams, f.n_scenes, f.width, f.height);
+    const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
+    hipLaunchKernelGGL(k_project, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st, pos,
+                       s.scene_off, s.n_scenes, cams, s.cap, w.proj);
+    if (p.algo == HM_RASTER_DIRECT) {
+        hipLaunchKernelGGL(k_raster_direct, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st,
+                           (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
+                           rk, s.cap, vis);
+        return;
+    }
+    const uint32_t nt = rk.n_tiles;
+    hipLaunchKernelGGL(k_fill_u32, dim3(stride_grid(nt + 1, 256)), dim3(256), 0, st, w.tile_cnt,
+                       nt + 1, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, w.counters, 64u, 0u);
+    const uint32_t gb = stride_grid(s.cap, 256);
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 0, (const float4 *)w.proj,
+                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
+                       (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);
+    scan_exclusive<uint32_t>(w.tile_cnt, w.tile_cnt, nt, w.partials, st);
+    hipLaunchKernelGGL(k_tile_items, dim3((nt + 255) / 256), dim3(256), 0, st,
+                       (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 1, (const float4 *)w.proj,
+                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
+                       (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
+                       w.counters);
+    scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
+    const uint32_t lds = 2u * p.tile * p.tile * (uint32_t)sizeof(uint64_t);
+    uint32_t grid = p.grid ? p.grid : 256u * 8u;
+    hipLaunchKernelGGL(k_raster_tiles, dim3(grid), dim3(p.block), lds, st,
+                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,
+                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
+                       (const uint32_t *)w.entries, w.counters, vis);
+    hipLaunchKernelGGL(k_raster_long, dim3(256), dim3(256), 0, st, (const float4 *)w.proj,
+                       (const uint8_t *)s.flags, s.scene_off, cams, rk, s.cap,
+                       (const uint32_t *)w.long_list, (const uint32_t *)w.counters, vis);
+}
+
+}  // namespace hm

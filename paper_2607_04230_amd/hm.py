@@ -1,0 +1,213 @@
+"""Python binding of libhm (argument marshalling only).
+
+Every function takes torch CUDA tensors, passes their device pointers and the
+current torch stream to the C ABI declared in include/hm.h, and raises
+RuntimeError with the library's message on any non-OK status.  There is no
+fallback: if libhm.so is missing or no GPU is present, calls fail loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhm.so")
+
+HM_OK = 0
+LOD_OFF, LOD_ON = 0, 1
+RASTER_TILED, RASTER_DIRECT = 0, 1
+RESOLVE_FILTER, RESOLVE_SOFT, RESOLVE_CENTER = 0, 1, 2
+CALL_LOD, CALL_RASTER, CALL_RESOLVE = 0, 1, 2
+
+_u32, _i32, _f32, _vp, _sz = ctypes.c_uint32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("R", _f32 * 9), ("eye", _f32 * 3), ("fx", _f32), ("fy", _f32), ("cx", _f32),
+                ("cy", _f32), ("znear", _f32), ("zfar", _f32)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("n_scenes", _u32), ("width", _u32), ("height", _u32)]
+
+
+class HairMesh(ctypes.Structure):
+    _fields_ = [("layer_pos", _vp), ("quads", _vp), ("bundle_key", _vp), ("bundle_nstrands", _vp),
+                ("bundle_cmax", _vp), ("bundle_scene", _vp), ("n_bundles", _u32),
+                ("n_layers", _u32), ("n_verts", _u32)]
+
+
+class Strands(ctypes.Structure):
+    _fields_ = [("pos_w", _vp), ("rgb", _vp), ("flags", _vp), ("scene_off", _vp),
+                ("n_scenes", _u32), ("cap", _u32)]
+
+
+class LodParams(ctypes.Structure):
+    _fields_ = [("mode", _i32), ("lam", _f32), ("seed", _u32)]
+
+
+class GenParams(ctypes.Structure):
+    _fields_ = [("seed", _u32), ("width", _f32), ("curl_amp", _f32), ("curl_turns", _f32),
+                ("base_rgb", _f32 * 3)]
+
+
+class RasterParams(ctypes.Structure):
+    _fields_ = [("r_min", _f32), ("algo", _i32), ("tile", _u32), ("chunk", _u32),
+                ("max_tiles_per_seg", _u32), ("block", _u32), ("grid", _u32)]
+
+
+class ShadeParams(ctypes.Structure):
+    _fields_ = [("light_dir", _f32 * 3), ("light_rgb", _f32 * 3), ("ka", _f32), ("kd", _f32),
+                ("ks", _f32), ("spec_squarings", _i32), ("filter_radius", _i32), ("s_par", _f32),
+                ("s_perp", _f32), ("sigma_c", _f32), ("iso_scale", _f32), ("depth_reject", _f32),
+                ("depth_mismatch", _f32), ("strip_half", _f32), ("iso_len", _f32),
+                ("soft_sigma", _f32), ("bg", _f32 * 3), ("mode", _i32)]
+
+
+EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_shade",
+           "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
+           "hm_version"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libhm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libhm.so not built at {path}; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    L.hm_lod_select.argtypes = [P(HairMesh), _vp, P(Frame), P(LodParams), _vp, _vp, _vp, _vp,
+                                _sz, _vp]
+    L.hm_generate_strands.argtypes = [P(HairMesh), _vp, _vp, _vp, P(GenParams), P(Strands), _vp]
+    L.hm_raster_vis.argtypes = [P(Strands), _vp, P(Frame), P(RasterParams), _vp, _vp, _vp, _sz,
+                                _vp]
+    L.hm_resolve_shade.argtypes = [P(Strands), _vp, _vp, P(Frame), P(ShadeParams), _vp, _vp, _sz,
+                                   _vp]
+    L.hm_resolve_shade_bwd.argtypes = [P(Strands), _vp, _vp, P(Frame), P(ShadeParams), _vp, _vp,
+                                       _vp, _vp]
+    L.hm_workspace_size.argtypes = [_i32, P(Frame), _u32, _u32, P(RasterParams), P(_sz)]
+    L.hm_raster_defaults.argtypes = [P(Frame), P(RasterParams)]
+    L.hm_last_error.restype = ctypes.c_char_p
+    L.hm_last_error.argtypes = []
+    L.hm_version.restype = _i32
+    for name in EXPORTS:
+        if name not in ("hm_last_error", "hm_version"):
+            getattr(L, name).restype = _i32
+    _lib = L
+    return L
+
+
+def _check(rc: int, what: str):
+    if rc != HM_OK:
+        msg = load().hm_last_error().decode()
+        raise RuntimeError(f"{what} failed (status {rc}): {msg}")
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise RuntimeError("libhm takes device tensors only")
+    if not t.is_contiguous():
+        raise RuntimeError("libhm takes contiguous tensors only")
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ----------------------------------------------------------------- descriptors
+def frame(n_scenes: int, width: int, height: int) -> Frame:
+    return Frame(n_scenes, width, height)
+
+
+def hair_mesh(d: dict) -> HairMesh:
+    lp = d["layer_pos"]
+    return HairMesh(_ptr(lp), _ptr(d["quads"]), _ptr(d["bundle_key"]), _ptr(d["bundle_nstrands"]),
+                    _ptr(d["bundle_cmax"]), _ptr(d["bundle_scene"]), d["quads"].shape[0],
+                    lp.shape[0], lp.shape[1])
+
+
+def strands(pos_w, rgb, flags, scene_off, cap: int) -> Strands:
+    return Strands(_ptr(pos_w), _ptr(rgb), _ptr(flags), _ptr(scene_off), scene_off.shape[0] - 1,
+                   cap)
+
+
+def raster_defaults(fr: Frame) -> RasterParams:
+    p = RasterParams()
+    _check(load().hm_raster_defaults(ctypes.byref(fr), ctypes.byref(p)), "hm_raster_defaults")
+    return p
+
+
+def shade_params(rp, mode: int, bg=(0.0, 0.0, 0.0)) -> ShadeParams:
+    s = ShadeParams()
+    s.light_dir[:] = list(rp.light_dir)
+    s.light_rgb[:] = list(rp.light_rgb)
+    s.ka, s.kd, s.ks = rp.ka, rp.kd, rp.ks
+    s.spec_squarings = rp.spec_squarings
+    s.filter_radius = rp.filter_radius
+    s.s_par, s.s_perp, s.sigma_c, s.iso_scale = rp.s_par, rp.s_perp, rp.sigma_c, rp.iso_scale
+    s.depth_reject, s.depth_mismatch = rp.depth_reject, rp.depth_mismatch
+    s.strip_half, s.iso_len, s.soft_sigma = rp.strip_half, rp.iso_len, rp.soft_sigma
+    s.bg[:] = list(bg)
+    s.mode = mode
+    return s
+
+
+def workspace_size(call: int, fr: Frame, n_bundles: int = 0, cap: int = 0,
+                   rparams: Optional[RasterParams] = None) -> int:
+    out = ctypes.c_size_t()
+    rc = load().hm_workspace_size(call, ctypes.byref(fr), n_bundles, cap,
+                                  ctypes.byref(rparams) if rparams is not None else None,
+                                  ctypes.byref(out))
+    _check(rc, "hm_workspace_size")
+    return int(out.value)
+
+
+# ----------------------------------------------------------------- calls
+def lod_select(mesh: HairMesh, cams, fr: Frame, mode: int, lam: float, seed: int, table,
+               scene_off, totals, ws):
+    p = LodParams(mode, lam, seed)
+    rc = load().hm_lod_select(ctypes.byref(mesh), _ptr(cams), ctypes.byref(fr), ctypes.byref(p),
+                              _ptr(table), _ptr(scene_off), _ptr(totals), _ptr(ws),
+                              ws.numel() * ws.element_size(), _stream())
+    _check(rc, "hm_lod_select")
+
+
+def generate_strands(mesh: HairMesh, table, strand_base, strand_rgb, gp: GenParams,
+                     st: Strands):
+    rc = load().hm_generate_strands(ctypes.byref(mesh), _ptr(table), _ptr(strand_base),
+                                    _ptr(strand_rgb), ctypes.byref(gp), ctypes.byref(st),
+                                    _stream())
+    _check(rc, "hm_generate_strands")
+
+
+def raster_vis(st: Strands, cams, fr: Frame, rp: RasterParams, scene_z, vis, ws):
+    rc = load().hm_raster_vis(ctypes.byref(st), _ptr(cams), ctypes.byref(fr), ctypes.byref(rp),
+                              _ptr(scene_z), _ptr(vis), _ptr(ws), ws.numel() * ws.element_size(),
+                              _stream())
+    _check(rc, "hm_raster_vis")
+
+
+def resolve_shade(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, out, ws):
+    rc = load().hm_resolve_shade(ctypes.byref(st), _ptr(vis), _ptr(cams), ctypes.byref(fr),
+                                 ctypes.byref(sp), _ptr(out), _ptr(ws),
+                                 ws.numel() * ws.element_size(), _stream())
+    _check(rc, "hm_resolve_shade")
+
+
+def resolve_shade_bwd(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, d_out, grad_pos,
+                      grad_rgb):
+    rc = load().hm_resolve_shade_bwd(ctypes.byref(st), _ptr(vis), _ptr(cams), ctypes.byref(fr),
+                                     ctypes.byref(sp), _ptr(d_out), _ptr(grad_pos),
+                                     _ptr(grad_rgb), _stream())
+    _check(rc, "hm_resolve_shade_bwd")

@@ -1,0 +1,118 @@
+"""Device buffers and call sequence for one frame (PyTorch = memory + streams only).
+
+DeviceScene uploads a scenes.Scene once, sizes every output and workspace from
+host-known upper bounds (no device readbacks), and enqueues
+hm_lod_select -> hm_generate_strands -> hm_raster_vis -> hm_resolve_shade on
+the current torch stream.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import hm
+from .scenes import ResolveParams, Scene
+
+
+def _u32(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.uint32).view(np.int32)).cuda()
+
+
+def _f32(a: np.ndarray):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+class DeviceScene:
+    def __init__(self, sc: Scene, rparams: Optional[hm.RasterParams] = None,
+                 resolve: Optional[ResolveParams] = None, cap: Optional[int] = None,
+                 mode: Optional[int] = None):
+        import torch
+        self.sc = sc
+        self.S, self.W, self.H = sc.n_scenes, sc.width, sc.height
+        self.fr = hm.frame(self.S, self.W, self.H)
+        self.mesh_t = dict(layer_pos=_f32(sc.layer_pos), quads=_u32(sc.quads),
+                           bundle_key=_u32(sc.bundle_key), bundle_nstrands=_u32(sc.bundle_nstrands),
+                           bundle_cmax=_u32(sc.bundle_cmax), bundle_scene=_u32(sc.bundle_scene))
+        self.mesh = hm.hair_mesh(self.mesh_t)
+        self.cams = _f32(sc.cams)
+        self.scene_z = None if sc.scene_z is None else _f32(sc.scene_z)
+        self.strand_base = _u32(sc.strand_base)
+        self.strand_rgb = None if sc.strand_rgb is None else _f32(sc.strand_rgb)
+        self.cap = int(cap or max(sc.n_cp_full, 2))
+        B = sc.n_bundles
+        dev = "cuda"
+        self.table = torch.zeros((B, 4), dtype=torch.int32, device=dev)
+        self.scene_off = torch.zeros(self.S + 1, dtype=torch.int32, device=dev)
+        self.totals = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.pos_w = torch.zeros((self.cap, 4), dtype=torch.float32, device=dev)
+        self.rgb = torch.zeros((self.cap, 4), dtype=torch.float32, device=dev)
+        self.flags = torch.zeros(self.cap, dtype=torch.uint8, device=dev)
+        self.vis = torch.zeros((self.S, 2, self.H, self.W), dtype=torch.int64, device=dev)
+        self.out = torch.zeros((self.S, self.H, self.W, 4), dtype=torch.float32, device=dev)
+        self.rparams = rparams or hm.raster_defaults(self.fr)
+        self.rparams.r_min = sc.r_min
+        self.resolve_params = resolve or ResolveParams()
+        self.mode = sc.mode if mode is None else mode
+        self.sp = hm.shade_params(self.resolve_params, self.mode, sc.bg)
+        self.gp = hm.GenParams(sc.seed, sc.strand_width, sc.curl_amp, sc.curl_turns,
+                               (ctypes_f3(sc.base_rgb)))
+        self.ws_lod = torch.zeros(hm.workspace_size(hm.CALL_LOD, self.fr, n_bundles=B),
+                                  dtype=torch.uint8, device=dev)
+        self.ws_raster = torch.zeros(
+            hm.workspace_size(hm.CALL_RASTER, self.fr, cap=self.cap, rparams=self.rparams),
+            dtype=torch.uint8, device=dev)
+        self.ws_resolve = torch.zeros(max(hm.workspace_size(hm.CALL_RESOLVE, self.fr), 1),
+                                      dtype=torch.uint8, device=dev)
+        self.st = hm.strands(self.pos_w, self.rgb, self.flags, self.scene_off, self.cap)
+
+    def set_raster_params(self, rp: hm.RasterParams):
+        import torch
+        rp.r_min = self.sc.r_min
+        need = hm.workspace_size(hm.CALL_RASTER, self.fr, cap=self.cap, rparams=rp)
+        if need > self.ws_raster.numel():
+            self.ws_raster = torch.zeros(need, dtype=torch.uint8, device="cuda")
+        self.rparams = rp
+
+    # ------------------------------------------------------------ steps
+    def lod(self):
+        hm.lod_select(self.mesh, self.cams, self.fr, self.sc.lod_mode, self.sc.lod_lambda,
+                      self.sc.seed, self.table, self.scene_off, self.totals, self.ws_lod)
+
+    def generate(self):
+        hm.generate_strands(self.mesh, self.table, self.strand_base, self.strand_rgb, self.gp,
+                            self.st)
+
+    def raster(self):
+        hm.raster_vis(self.st, self.cams, self.fr, self.rparams, self.scene_z, self.vis,
+                      self.ws_raster)
+
+    def resolve(self, out=None):
+        hm.resolve_shade(self.st, self.vis, self.cams, self.fr, self.sp,
+                         self.out if out is None else out, self.ws_resolve)
+
+    def render(self):
+        self.lod()
+        self.generate()
+        self.raster()
+        self.resolve()
+        return self.out
+
+    # ------------------------------------------------------------ host views
+    def n_cp(self) -> int:
+        return int(self.totals[1].item())
+
+    def host_stream(self):
+        n = min(self.n_cp(), self.cap)
+        return (self.pos_w[:n].cpu().numpy(), self.rgb[:n].cpu().numpy(),
+                self.flags[:n].cpu().numpy())
+
+    def host_vis(self) -> np.ndarray:
+        return self.vis.cpu().numpy().view(np.uint64)
+
+
+def ctypes_f3(v):
+    import ctypes
+    return (ctypes.c_float * 3)(*[float(x) for x in v])
