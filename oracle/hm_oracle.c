@@ -740,7 +740,7 @@ int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                     const double *CP = cc + 3 * p;
                     int colour_sim = hc && !mism;
                     double S[3] = {0, 0, 0}, W = 0.0;
-                    int Hc = 0, Ha = 0;
+                    int Hc = 0, Ha = 0, nacc = 0;
                     for (int oy = -r; oy <= r; ++oy) {
                         int jq = j + oy;
                         if (jq < 0 || jq >= height) continue;
@@ -782,6 +782,7 @@ int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                             double w = ws * wc;
                             S[0] += w * CQ[0]; S[1] += w * CQ[1]; S[2] += w * CQ[2];
                             W += w;
+                            nacc++;
                         }
                     }
                     double aP = Ha > 0 ? (double)Hc / (double)Ha : 1.0;
@@ -790,11 +791,12 @@ int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                         alpha = aP;
                     } else if (mism) {
                         for (int ch = 0; ch < 3; ++ch) {
-                            double rec = W > 0.0 ? S[ch] / W : CP[ch];
+                            double rec = nacc > 0 ? S[ch] / W : CP[ch];
                             rgbv[ch] = aP * rec + (1.0 - aP) * CP[ch];
                         }
                         alpha = 1.0;
-                    } else if (W > 0.0) {
+                    } else if (nacc > 0) {
+                        /* promoted: a reconstruction exists iff a centre neighbour was accepted */
                         for (int ch = 0; ch < 3; ++ch) rgbv[ch] = S[ch] / W;
                         alpha = aP;
                     }

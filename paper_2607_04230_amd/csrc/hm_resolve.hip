@@ -182,8 +182,10 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     }
     const float4 CP = tile[(lj + r) * E + (li + r)];
     const bool colour_sim = hc && !mism;
-    float Sx = 0.f, Sy = 0.f, Sz = 0.f, Wsum = 0.f;
-    int Hc = 0, Ha = 0;
+    // normalised sum with a running exponent shift: sum_q exp(e_q - m) C_q /
+    // sum_q exp(e_q - m), m = max e_q so far (no underflow of the weight sum)
+    float Sx = 0.f, Sy = 0.f, Sz = 0.f, Wsum = 0.f, emax = -INFINITY;
+    int Hc = 0, Ha = 0, nacc = 0;
     for (int oy = -r; oy <= r; ++oy) {
         const float4 *row = tile + (lj + r + oy) * E + (li + r);
         const float fy = (float)oy;
@@ -214,32 +216,35 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
                 const float d0 = CP.x - Q.x, d1 = CP.y - Q.y, d2 = CP.z - Q.z;
                 e -= (d0 * d0 + d1 * d1 + d2 * d2) * k.inv_sc2;
             }
-            const float w = expf(e);
+            if (e > emax) {
+                const float sc = expf(emax - e);
+                Sx *= sc; Sy *= sc; Sz *= sc; Wsum *= sc;
+                emax = e;
+            }
+            const float w = expf(e - emax);
             Sx += w * Q.x;
             Sy += w * Q.y;
             Sz += w * Q.z;
             Wsum += w;
+            ++nacc;
         }
     }
     const float aP = Ha > 0 ? (float)Hc / (float)Ha : 1.0f;
     float rr = 0.f, gg = 0.f, bb = 0.f, alpha = 0.f;
     if (hc && !mism) {
-        const float iw = 1.0f / Wsum;
-        rr = Sx * iw; gg = Sy * iw; bb = Sz * iw;
+        rr = Sx / Wsum; gg = Sy / Wsum; bb = Sz / Wsum;
         alpha = aP;
     } else if (mism) {
         float cr = CP.x, cg = CP.y, cb = CP.z;
-        if (Wsum > 0.0f) {
-            const float iw = 1.0f / Wsum;
-            cr = Sx * iw; cg = Sy * iw; cb = Sz * iw;
+        if (nacc > 0) {
+            cr = Sx / Wsum; cg = Sy / Wsum; cb = Sz / Wsum;
         }
         rr = aP * cr + (1.0f - aP) * CP.x;
         gg = aP * cg + (1.0f - aP) * CP.y;
         bb = aP * cb + (1.0f - aP) * CP.z;
         alpha = 1.0f;
-    } else if (Wsum > 0.0f) {
-        const float iw = 1.0f / Wsum;
-        rr = Sx * iw; gg = Sy * iw; bb = Sz * iw;
+    } else if (nacc > 0) {
+        rr = Sx / Wsum; gg = Sy / Wsum; bb = Sz / Wsum;
         alpha = aP;
     }
     *o = make_float4(alpha * rr + (1.0f - alpha) * k.bgr, alpha * gg + (1.0f - alpha) * k.bgg,
