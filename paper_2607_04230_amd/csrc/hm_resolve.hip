@@ -33,19 +33,36 @@ __device__ __forceinline__ bool is_hit(uint64_t k)
 
 // Everything the shading of one pixel needs about its segment.
 struct SegShade {
-    float ts, t3;           // closest screen parameter, segment parameter
+    double ts;              // closest screen-space parameter
+    float t3;               // matching segment parameter (perspective-correct)
     V3 X, T;                // shading point and unit tangent
     V3 alb;
 };
 
-// Closest screen-space parameter of pixel centre (px, py) on segment a -> b.
-__device__ __forceinline__ float closest_t(float4 a, float4 b, float px, float py)
+// Screen position and 1/z in binary64.  Continuous resolve quantities (the
+// closest-point parameter, pixel distance, screen tangent of the filter
+// weights) are ill-conditioned for segments nearly parallel to the view ray:
+// binary32 pixel coordinates around 10^3 px carry ~1e-4 px of rounding.
+struct DProj { double x, y, iz; };
+
+__device__ __forceinline__ DProj project_d(const Cam &c, float4 p)
 {
-    const float dx = b.x - a.x, dy = b.y - a.y;
-    const float len2 = dx * dx + dy * dy;
-    if (!(len2 > 0.0f)) return 0.0f;
-    float t = ((px - a.x) * dx + (py - a.y) * dy) / len2;
-    return fminx(fmaxx(t, 0.0f), 1.0f);
+    const double dx = (double)p.x - c.ex, dy = (double)p.y - c.ey, dz = (double)p.z - c.ez;
+    const double X = (double)c.R[0] * dx + (double)c.R[1] * dy + (double)c.R[2] * dz;
+    const double Y = (double)c.R[3] * dx + (double)c.R[4] * dy + (double)c.R[5] * dz;
+    const double Z = (double)c.R[6] * dx + (double)c.R[7] * dy + (double)c.R[8] * dz;
+    const double iz = 1.0 / Z;
+    return {(double)c.cx + (double)c.fx * X * iz, (double)c.cy - (double)c.fy * Y * iz, iz};
+}
+
+// Closest screen-space parameter of pixel centre (px, py) on segment a -> b.
+__device__ __forceinline__ double closest_t(DProj a, DProj b, double px, double py)
+{
+    const double dx = b.x - a.x, dy = b.y - a.y;
+    const double len2 = dx * dx + dy * dy;
+    if (!(len2 > 0.0)) return 0.0;
+    const double t = ((px - a.x) * dx + (py - a.y) * dy) / len2;
+    return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
 }
 
 __device__ __forceinline__ V3 cp_tangent(const float4 *pos, const uint8_t *flags, uint32_t v)
@@ -59,13 +76,13 @@ __device__ __forceinline__ V3 cp_tangent(const float4 *pos, const uint8_t *flags
 }
 
 __device__ __forceinline__ SegShade seg_shade_point(const float4 *pos, const float4 *rgb,
-                                                    const uint8_t *flags, float4 a, float4 b,
-                                                    uint32_t v, float px, float py)
+                                                    const uint8_t *flags, DProj a, DProj b,
+                                                    uint32_t v, double px, double py)
 {
     SegShade r;
     r.ts = closest_t(a, b, px, py);
-    const float iz = a.w + r.ts * (b.w - a.w);
-    r.t3 = r.ts * b.w / iz;
+    const double iz = a.iz + r.ts * (b.iz - a.iz);
+    r.t3 = (float)(r.ts * b.iz / iz);
     const V3 P0 = xyz(pos[v]), P1 = xyz(pos[v + 1]);
     r.X = P0 + (P1 - P0) * r.t3;
     const V3 T0 = cp_tangent(pos, flags, v), T1 = cp_tangent(pos, flags, v + 1);
@@ -109,10 +126,10 @@ __global__ __launch_bounds__(256) void k_shade(const float4 *pos, const float4 *
         if (hc) {
             const Cam c = load_cam(cams + s);
             const uint32_t v = (uint32_t)(kc & HM_ID_MASK);
-            const float4 a = project(c, pos[v]), b = project(c, pos[v + 1]);
+            const DProj a = project_d(c, pos[v]), b = project_d(c, pos[v + 1]);
             const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
-            const SegShade g = seg_shade_point(pos, rgb, flags, a, b, v, (float)i + 0.5f,
-                                               (float)j + 0.5f);
+            const SegShade g = seg_shade_point(pos, rgb, flags, a, b, v, (double)i + 0.5,
+                                               (double)j + 0.5);
             col = shade(g, c, k);
         }
         const uint32_t bits = (hc ? (uint32_t)(kc >> HM_ID_BITS) : 0u) | (hc ? 1u << 24 : 0u) |
@@ -174,11 +191,18 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     const float tdx = pb.x - pa.x, tdy = pb.y - pa.y;
     const float tlen = sqrtf(tdx * tdx + tdy * tdy);
     const bool iso = !(tlen >= k.iso_len);
-    float Tx = 0.0f, Ty = 0.0f;
+    // binary32 tangent: strip membership decision (same bits as any IEEE
+    // evaluation); binary64 tangent: the continuous filter weights
+    float Tx = 0.0f, Ty = 0.0f, Twx = 0.0f, Twy = 0.0f;
     if (!iso) {
         const float il = 1.0f / tlen;
         Tx = tdx * il;
         Ty = tdy * il;
+        const DProj da = project_d(c, pos[vs]), db = project_d(c, pos[vs + 1]);
+        const double ddx = db.x - da.x, ddy = db.y - da.y;
+        const double dl = sqrt(ddx * ddx + ddy * ddy);
+        Twx = (float)(ddx / dl);
+        Twy = (float)(ddy / dl);
     }
     const float4 CP = tile[(lj + r) * E + (li + r)];
     const bool colour_sim = hc && !mism;
@@ -211,7 +235,14 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
             const uint32_t qq = bits & 0xFFFFFFu;
             const uint32_t dq = qq > qP ? qq - qP : qP - qq;
             if (dq > k.dq_rej) continue;
-            float e = iso ? -(perp2 * k.inv_siso2) : -(par * par * k.inv_spar2) - perp2 * k.inv_sperp2;
+            float e;
+            if (iso) {
+                e = -(perp2 * k.inv_siso2);
+            } else {
+                const float pw = fx * Twx + fy * Twy;        // d_par with the accurate tangent
+                const float cw = fx * Twy - fy * Twx;        // signed d_perp
+                e = -(pw * pw * k.inv_spar2) - cw * cw * k.inv_sperp2;
+            }
             if (colour_sim) {
                 const float d0 = CP.x - Q.x, d1 = CP.y - Q.y, d2 = CP.z - Q.z;
                 e -= (d0 * d0 + d1 * d1 + d2 * d2) * k.inv_sc2;
@@ -276,14 +307,15 @@ __global__ __launch_bounds__(256) void k_soft(const float4 *pos, const float4 *r
         }
         const Cam c = load_cam(cams + s);
         const uint32_t v = (uint32_t)(src & HM_ID_MASK);
-        const float4 a = project(c, pos[v]), b = project(c, pos[v + 1]);
+        const float4 P0 = pos[v], P1 = pos[v + 1];
+        const DProj a = project_d(c, P0), b = project_d(c, P1);
         const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
-        const float px = (float)i + 0.5f, py = (float)j + 0.5f;
+        const double px = (double)i + 0.5, py = (double)j + 0.5;
         const SegShade g = seg_shade_point(pos, rgb, flags, a, b, v, px, py);
-        const float qx = a.x + g.ts * (b.x - a.x), qy = a.y + g.ts * (b.y - a.y);
-        const float ex = px - qx, ey = py - qy;
-        const float d = sqrtf(ex * ex + ey * ey);
-        const float wt = a.z + g.ts * (b.z - a.z);
+        const double ex = px - (a.x + g.ts * (b.x - a.x)), ey = py - (a.y + g.ts * (b.y - a.y));
+        const float d = (float)sqrt(ex * ex + ey * ey);
+        const double w0 = (double)P0.w * c.fy * a.iz, w1 = (double)P1.w * c.fy * b.iz;
+        const float wt = (float)(w0 + g.ts * (w1 - w0));
         const float alpha = 0.5f * (erff((d + 0.5f * wt) * k.soft_k) - erff((d - 0.5f * wt) * k.soft_k));
         const V3 Sc = shade(g, c, k);
         out[p] = make_float4(alpha * Sc.x + (1.0f - alpha) * k.bgr,

@@ -38,14 +38,31 @@ def _compare_stream(ds, ref):
     assert np.array_equal(rgb.view(np.uint32), ref["rgb"].view(np.uint32))
 
 
+def _rgba_err(out_gpu, ref_out, vis, label=""):
+    """Max |gpu - oracle| over RGBA; prints the worst pixels (with their layer
+    hits) so that a failure names its cause."""
+    out = out_gpu.astype(np.float64)
+    d = np.abs(out - ref_out).max(-1)
+    err = float(d.max())
+    if err > TOL:
+        E = np.uint64(0xFFFFFFFFFFFFFFFF)
+        flat = np.argsort(d.ravel())[::-1][:8]
+        for f in flat:
+            s, j, i = np.unravel_index(f, d.shape)
+            kc, ka = vis[s, 0, j, i], vis[s, 1, j, i]
+            print(f"{label} worst s={s} j={j} i={i} err={d[s, j, i]:.3e} centre={kc != E} "
+                  f"cons={ka != E} gpu={out[s, j, i]} ref={ref_out[s, j, i]}")
+        print(f"{label} pixels over tol: {(d > TOL).sum()} of {d.size}")
+    return err
+
+
 def test_tiny_end_to_end(O, torch):
     sc = scenes.config_tiny()
     ref = O.render(sc)
     ds = _gpu(sc, torch)
     _compare_stream(ds, ref)
     assert np.array_equal(ds.host_vis(), ref["vis"])
-    out = ds.out.cpu().numpy().astype(np.float64)
-    assert np.abs(out - ref["out"]).max() <= TOL
+    assert _rgba_err(ds.out.cpu().numpy(), ref["out"], ref["vis"], "tiny") <= TOL
 
 
 @pytest.mark.parametrize("algo,tile,chunk,K,block", [
@@ -82,9 +99,7 @@ def test_head_1080p_full(O, torch):
     ds = _gpu(sc, torch)
     _compare_stream(ds, ref)
     assert np.array_equal(ds.host_vis(), ref["vis"])
-    out = ds.out.cpu().numpy().astype(np.float64)
-    err = np.abs(out - ref["out"]).max()
-    assert err <= TOL, err
+    assert _rgba_err(ds.out.cpu().numpy(), ref["out"], ref["vis"], "head") <= TOL
 
 
 def test_center_mode(O, torch):
@@ -92,8 +107,7 @@ def test_center_mode(O, torch):
     sc.mode = scenes.MODE_CENTER
     ref = O.render(sc)
     ds = _gpu(sc, torch)
-    out = ds.out.cpu().numpy().astype(np.float64)
-    assert np.abs(out - ref["out"]).max() <= TOL
+    assert _rgba_err(ds.out.cpu().numpy(), ref["out"], ref["vis"], "centre") <= TOL
 
 
 def test_soft_forward_diff_config(O, torch):
@@ -101,5 +115,4 @@ def test_soft_forward_diff_config(O, torch):
     ref = O.render(sc)
     ds = _gpu(sc, torch)
     assert np.array_equal(ds.host_vis(), ref["vis"])
-    out = ds.out.cpu().numpy().astype(np.float64)
-    assert np.abs(out - ref["out"]).max() <= TOL
+    assert _rgba_err(ds.out.cpu().numpy(), ref["out"], ref["vis"], "soft") <= TOL
