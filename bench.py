@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the deferred strand-hair rasterizer on one MI355X.
+
+One step = one whole frame of the hot path on the full-head workload
+(2000 quads x 6 layers, 64 strands per quad, 17 control points = 16
+segments per strand, width 0.0008, 1920x1080, filtered resolve):
+  hm_lod_select -> hm_generate_strands -> hm_raster_vis -> hm_resolve_shade.
+Inputs (hair mesh, cameras, occluder depth) are resident in HBM before the
+timed region; nothing is skipped inside it.
+
+Prints one JSON line: segments rasterized per second for the whole frame,
+ms per frame, the roofline of the dominant kernel (timed with HIP events on
+the library's launch stream over the timed region) and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32
+
+# Algorithmic work of each kernel per unit (see the design notes):
+#   bytes per control point / segment / pixel, or flops per filter tap.
+GEN_BYTES_PER_CP = 16 + 16 + 1            # pos_w + rgb + flags written
+PROJ_BYTES_PER_CP = 16 + 16               # pos_w read, screen record written
+RASTER_BYTES_PER_SEG = 17                 # 16 B screen record + 1 B flags per CP
+FILTER_FLOPS_PER_TAP = 30
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(sc, seconds: float):
+    """The CPU oracle (single-threaded C) on whole frames of the same workload,
+    repeated until `seconds` of work have run (at least one frame)."""
+    from oracle import oracle as O
+    from paper_2607_04230_amd.scenes import ResolveParams
+    rp = ResolveParams()
+    frames, segs = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        table, soff, (ns, ncp) = O.lod_select(sc)
+        pos, rgb, fl = O.generate(sc, table, ncp)
+        vis = O.raster(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+        O.resolve(pos, rgb, fl, vis, sc.cams, sc.width, sc.height, rp, sc.mode, sc.bg)
+        frames += 1
+        segs += ncp - ns
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return {"value": segs / el, "unit": "segments/s", "cores": 1, "kind": "oracle",
+            "sample": f"{frames} whole frame(s) of the full-head 1080p workload "
+                      f"(LOD table, generation, raster, filtered resolve), {el:.1f} s",
+            "ms_per_frame": 1e3 * el / frames, "cpu": _cpu_model()}
+
+
+def _traffic(kernel: str):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
+    were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    rec = tab.get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src):
+        return None
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    if sha != rec.get("source_sha"):
+        return None
+    return rec["bytes_per_launch"]
+
+
+def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, hair_px: int,
+             taps: int):
+    s = avg_ms * 1e-3
+    if kernel == "k_filter":
+        flops = hair_px * taps * FILTER_FLOPS_PER_TAP
+        ach = flops / s / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / PEAK_FP32_TFLOPS, "traffic": _traffic(kernel)}
+    if kernel == "k_generate":
+        b = n_cp * GEN_BYTES_PER_CP
+    elif kernel == "k_project":
+        b = n_cp * PROJ_BYTES_PER_CP
+    elif kernel in ("k_raster_tiles", "k_raster_direct"):
+        b = n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes
+    elif kernel == "k_prefill":
+        b = vis_bytes
+    else:
+        b = n_cp * 16
+    ach = b / s / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": ach / PEAK_HBM_GBS, "traffic": _traffic(kernel)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design in the notes, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2607_04230_amd import hm, scenes
+    from paper_2607_04230_amd.render import DeviceScene
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    sc = scenes.config_head()
+    ds = DeviceScene(sc)
+    print(f"[bench] workload built: {sc.n_full_strands} strands, {sc.n_seg_full} segments, "
+          f"{sc.width}x{sc.height}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        ds.render()
+    torch.cuda.synchronize()
+
+    hm.timing_enable(True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        ds.render()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    hm.timing_enable(False)
+    kt = hm.timing_collect()
+    ms = e0.elapsed_time(e1) / args.steps
+    tot = ds.totals.cpu().numpy()
+    n_strands, n_cp = int(tot[0]), int(tot[1])
+    n_seg = n_cp - n_strands
+    vis_np = ds.host_vis()
+    E = np.uint64(0xFFFFFFFFFFFFFFFF)
+    hair_px = int(((vis_np[:, 0] != E) | (vis_np[:, 1] != E)).sum())
+    vis_bytes = int(vis_np.nbytes)
+    r = ds.resolve_params.filter_radius
+    per_kernel = {k: {"avg_ms": v[0] / max(v[1], 1), "launches_per_step": v[1] / args.steps}
+                  for k, v in kt.items()}
+    # dominant kernel: largest total time per step
+    dom = max(kt.items(), key=lambda kv: kv[1][0])[0]
+    dom_avg = kt[dom][0] / kt[dom][1]
+    roof = roofline(dom, dom_avg, n_cp, n_seg, vis_bytes, hair_px, (2 * r + 1) ** 2)
+    roof["kernel"] = dom
+    raster_ms = sum(kt.get(k, (0.0, 0))[0] for k in
+                    ("k_prefill", "k_project", "k_bin", "k_tile_items", "k_fill_u32",
+                     "k_raster_tiles", "k_raster_long", "k_raster_direct",
+                     "k_scan_blocks", "k_scan_partials", "k_scan_add")) / args.steps
+    line = {
+        "metric": "segments rasterized/s and ms/frame at 1080p",
+        "value": n_seg / (ms * 1e-3),
+        "unit": "segments/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded cube-sphere head groom, no dataset)",
+        "config": {"workload": "full head: 2000 quads x 6 layers, 64 strands/quad, 16 segments, "
+                               "width 0.0008, 1920x1080, filtered resolve",
+                   "strands": n_strands, "segments": n_seg, "width": sc.width,
+                   "height": sc.height},
+        "roofline": roof,
+        "raster_ms": raster_ms,
+        "raster_segments_per_s": n_seg / (raster_ms * 1e-3) if raster_ms > 0 else None,
+        "kernels": per_kernel,
+        "hair_pixels": hair_px,
+    }
+    if not args.no_cpu:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

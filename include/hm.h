@@ -237,6 +237,15 @@ hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bund
 /* Default raster parameters for a frame. */
 hm_status hm_raster_defaults(const hm_frame *frame, hm_raster_params *p);
 
+/* ------------------------------------------------------------------ profiling */
+/* Opt-in kernel timing for benchmarks: while enabled, every kernel the
+ * library launches is bracketed by two HIP events on its stream (do not
+ * enable while capturing a graph).  hm_timing_collect waits for the recorded
+ * events, writes one line "kernel total_ms launches" per kernel into buf
+ * (host, len bytes, NUL-terminated, truncated if short) and forgets them. */
+hm_status hm_timing_enable(int32_t on);
+hm_status hm_timing_collect(char *buf, size_t len);
+
 /* Message of the last error on this host thread ("" if none). */
 const char *hm_last_error(void);
 

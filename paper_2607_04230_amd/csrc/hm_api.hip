@@ -6,6 +6,11 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
 
@@ -20,6 +25,33 @@ uint32_t stride_grid(size_t n, uint32_t block)
     if (g > cap) g = cap;
     if (g < 1) g = 1;
     return (uint32_t)g;
+}
+
+// ------------------------------------------------------------------ kernel timing
+struct TimedRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+static std::mutex g_tmu;
+static bool g_timing = false;
+static std::vector<TimedRec> g_recs;
+
+KTimer::KTimer(const char *name, hipStream_t st) : name_(name), st_(st)
+{
+    if (!g_timing) return;
+    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
+        a_ = b_ = nullptr;
+        return;
+    }
+    hipEventRecord(a_, st_);
+}
+
+KTimer::~KTimer()
+{
+    if (!a_) return;
+    hipEventRecord(b_, st_);
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_recs.push_back({name_, a_, b_});
 }
 
 }  // namespace hm
@@ -154,6 +186,43 @@ static hm_status make_shade(const hm_shade_params *p, ShadeK &k)
 extern "C" {
 
 const char *hm_last_error(void) { return g_err; }
+
+hm_status hm_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_timing = on != 0;
+    return ok();
+}
+
+hm_status hm_timing_collect(char *buf, size_t len)
+{
+    REQUIRE(buf && len > 0, HM_ERR_INVALID, "buffer is NULL");
+    std::vector<TimedRec> recs;
+    {
+        std::lock_guard<std::mutex> g(g_tmu);
+        recs.swap(g_recs);
+    }
+    std::map<std::string, std::pair<double, unsigned long>> acc;
+    for (auto &r : recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto &e = acc[r.name];
+            e.first += ms;
+            e.second += 1;
+        }
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    size_t o = 0;
+    buf[0] = 0;
+    for (auto &kv : acc) {
+        int n = snprintf(buf + o, len - o, "%s %.6f %lu\n", kv.first.c_str(), kv.second.first,
+                         kv.second.second);
+        if (n < 0 || (size_t)n >= len - o) break;
+        o += (size_t)n;
+    }
+    return ok();
+}
 
 int32_t hm_version(void) { return 100; }
 

@@ -56,3 +56,26 @@ void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camer
 uint32_t stride_grid(size_t n, uint32_t block);
 
 }  // namespace hm
+
+namespace hm {
+
+// Opt-in per-kernel timing (hm_timing_enable): when on, a KTimer records a
+// pair of HIP events around one launch on its stream.
+struct KTimer {
+    KTimer(const char *name, hipStream_t st);
+    ~KTimer();
+    const char *name_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+}  // namespace hm
+
+// Every kernel launch of the library goes through this macro, so that the
+// opt-in timer can bracket it with events on the launch stream.
+#undef hipLaunchKernelGGL
+#define hipLaunchKernelGGL(kernelName, numBlocks, numThreads, memPerBlock, streamId, ...)      \
+    do {                                                                                      \
+        ::hm::KTimer hm_kt_(#kernelName, (streamId));                                         \
+        kernelName<<<(numBlocks), (numThreads), (memPerBlock), (streamId)>>>(__VA_ARGS__);    \
+    } while (0)

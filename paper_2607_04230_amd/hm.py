@@ -69,7 +69,7 @@ class ShadeParams(ctypes.Structure):
 
 EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_shade",
            "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
-           "hm_version"]
+           "hm_version", "hm_timing_enable", "hm_timing_collect"]
 
 _lib = None
 
@@ -203,6 +203,28 @@ def resolve_shade(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, out, ws):
                                  ctypes.byref(sp), _ptr(out), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream())
     _check(rc, "hm_resolve_shade")
+
+
+def timing_enable(on: bool):
+    L = load()
+    L.hm_timing_enable.argtypes = [_i32]
+    L.hm_timing_enable.restype = _i32
+    _check(L.hm_timing_enable(1 if on else 0), "hm_timing_enable")
+
+
+def timing_collect() -> dict:
+    """{kernel: (total_ms, launches)} for launches recorded since the last call."""
+    L = load()
+    L.hm_timing_collect.argtypes = [ctypes.c_char_p, _sz]
+    L.hm_timing_collect.restype = _i32
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(L.hm_timing_collect(buf, len(buf)), "hm_timing_collect")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, ms, n = line.rsplit(" ", 2)
+        out[name.split("<")[0]] = (out.get(name.split("<")[0], (0.0, 0))[0] + float(ms),
+                                   out.get(name.split("<")[0], (0.0, 0))[1] + int(n))
+    return out
 
 
 def resolve_shade_bwd(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, d_out, grad_pos,
