@@ -237,6 +237,51 @@ hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bund
 /* Default raster parameters for a frame. */
 hm_status hm_raster_defaults(const hm_frame *frame, hm_raster_params *p);
 
+/* ------------------------------------------------------------------ whole frames */
+/* Everything one frame needs: the arguments of the four calls above.  Several
+ * scenes (views / characters of uneven strand counts and LOD levels) are one
+ * frame with frame.n_scenes > 1: every kernel then covers all scenes in one
+ * launch, and the raster's persistent workgroups pull (scene tile, chunk)
+ * work items from one device queue (the paper renders grooms one after the
+ * other, Sec. 4; batching is an extension). */
+typedef struct {
+    hm_hair_mesh mesh;
+    const hm_camera *cams;             /* [n_scenes] */
+    hm_frame frame;
+    hm_lod_params lod;
+    uint32_t *table;                   /* [n_bundles][4] */
+    void *ws_lod;
+    size_t ws_lod_bytes;
+    const uint32_t *strand_base;
+    const float *strand_rgb;
+    hm_gen_params gen;
+    hm_strands strands;                /* strands.scene_off must be the LOD call's scene_off */
+    uint64_t *totals;                  /* [2] */
+    hm_raster_params raster;
+    const float *scene_z;
+    uint64_t *vis;
+    void *ws_raster;
+    size_t ws_raster_bytes;
+    hm_shade_params shade;
+    float *out_rgba;
+    void *ws_resolve;
+    size_t ws_resolve_bytes;
+} hm_frame_desc;
+
+/* Enqueue hm_lod_select, hm_generate_strands, hm_raster_vis and
+ * hm_resolve_shade for one frame on `stream`. */
+hm_status hm_render_frame(const hm_frame_desc *d, void *stream);
+
+/* A frame captured once into a HIP graph and replayed with one launch.  The
+ * graph records the descriptor's device pointers: the buffers must outlive it
+ * and keep their addresses; their contents may change between launches.
+ * `stream` must not be the null stream.  hm_graph_create captures (it
+ * enqueues nothing); hm_graph_launch replays on any stream. */
+typedef struct hm_graph_s *hm_graph;
+hm_status hm_graph_create(const hm_frame_desc *d, void *stream, hm_graph *out);
+hm_status hm_graph_launch(hm_graph g, void *stream);
+hm_status hm_graph_destroy(hm_graph g);
+
 /* ------------------------------------------------------------------ profiling */
 /* Opt-in kernel timing for benchmarks: while enabled, every kernel the
  * library launches is bracketed by two HIP events on its stream (do not

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <map>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -336,6 +337,81 @@ hm_status hm_resolve_shade_bwd(const hm_strands *s, const uint64_t *vis, const h
     launch_resolve_bwd(*s, vis, cams, *frame, k, d_out, grad_pos_w, grad_rgb,
                        (hipStream_t)stream);
     return check_launch("hm_resolve_shade_bwd");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ whole frames
+struct hm_graph_s {
+    hipGraphExec_t exec;
+};
+
+extern "C" {
+
+hm_status hm_render_frame(const hm_frame_desc *d, void *stream)
+{
+    REQUIRE(d, HM_ERR_INVALID, "frame descriptor is NULL");
+    hm_status st;
+    if ((st = hm_lod_select(&d->mesh, d->cams, &d->frame, &d->lod, d->table,
+                            (uint32_t *)d->strands.scene_off, d->totals, d->ws_lod,
+                            d->ws_lod_bytes, stream)))
+        return st;
+    if ((st = hm_generate_strands(&d->mesh, d->table, d->strand_base, d->strand_rgb, &d->gen,
+                                  &d->strands, stream)))
+        return st;
+    if ((st = hm_raster_vis(&d->strands, d->cams, &d->frame, &d->raster, d->scene_z, d->vis,
+                            d->ws_raster, d->ws_raster_bytes, stream)))
+        return st;
+    return hm_resolve_shade(&d->strands, d->vis, d->cams, &d->frame, &d->shade, d->out_rgba,
+                            d->ws_resolve, d->ws_resolve_bytes, stream);
+}
+
+hm_status hm_graph_create(const hm_frame_desc *d, void *stream, hm_graph *out)
+{
+    REQUIRE(d && out, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(stream, HM_ERR_INVALID, "graph capture needs a non-null stream");
+    *out = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return fail(HM_ERR_HIP, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    hm_status rs = hm_render_frame(d, stream);
+    char msg[512];
+    snprintf(msg, sizeof msg, "%s", g_err);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(st, &graph);
+    if (rs != HM_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return fail(rs, "%s", msg);
+    }
+    if (e != hipSuccess || !graph)
+        return fail(HM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(HM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    hm_graph g = new (std::nothrow) hm_graph_s{exec};
+    if (!g) {
+        hipGraphExecDestroy(exec);
+        return fail(HM_ERR_INVALID, "out of host memory");
+    }
+    *out = g;
+    return ok();
+}
+
+hm_status hm_graph_launch(hm_graph g, void *stream)
+{
+    REQUIRE(g, HM_ERR_INVALID, "graph is NULL");
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(HM_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+    return ok();
+}
+
+hm_status hm_graph_destroy(hm_graph g)
+{
+    if (!g) return ok();
+    hipGraphExecDestroy(g->exec);
+    delete g;
+    return ok();
 }
 
 }  // extern "C"

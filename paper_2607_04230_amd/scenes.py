@@ -322,9 +322,13 @@ def config_batched(seed=1004, n_scenes=64, res=512, n_min=1e3, n_max=2e5) -> Sce
 
 
 def config_diff(seed=1005, res=512, strands_per_quad=16) -> Scene:
-    """32k strands x 16 segments at 512x512, soft-coverage resolve."""
-    return config_head(seed=seed, width=res, height=res, strands_per_quad=strands_per_quad,
-                       n_cp=17, strand_width=0.002, occluder=True, mode=MODE_SOFT)
+    """32k strands x 16 segments at 512x512, soft-coverage resolve.  The
+    coverage tests use a 1 px minimum half width so the visibility buffer
+    reaches the Gaussian footprint of the soft coverage (3.5 sigma)."""
+    sc = config_head(seed=seed, width=res, height=res, strands_per_quad=strands_per_quad,
+                     n_cp=17, strand_width=0.002, occluder=False, mode=MODE_SOFT)
+    sc.r_min = 1.0
+    return sc
 
 
 def perturb_stream(pos_w: np.ndarray, rgb: np.ndarray, seed: int, sigma=0.01):
