@@ -470,7 +470,7 @@ int orc_cover_export(const float a[4], const float b[4], int i, int j, float r_m
 int orc_raster(const float *pos_w, const uint8_t *flags, const uint32_t *scene_off,
                const float *cams, uint32_t n_scenes, int width, int height, float r_min,
                const float *scene_z, int brute, const uint32_t *order, uint64_t n_order,
-               uint64_t *vis)
+               const int *win, uint64_t *vis)
 {
     size_t npix = (size_t)width * (size_t)height;
     for (uint32_t s = 0; s < n_scenes; ++s) {
@@ -518,6 +518,12 @@ int orc_raster(const float *pos_w, const uint8_t *flags, const uint32_t *scene_o
             if (ymn > 0.0f) j0 = (int)ymn;
             if (xmx < (float)(width - 1)) i1 = (int)xmx;
             if (ymx < (float)(height - 1)) j1 = (int)ymx;
+        }
+        if (win) {   /* only the pixels of window [win0, win2] x [win1, win3] */
+            i0 = i0 > win[0] ? i0 : win[0];
+            j0 = j0 > win[1] ? j0 : win[1];
+            i1 = i1 < win[2] ? i1 : win[2];
+            j1 = j1 < win[3] ? j1 : win[3];
         }
         for (int j = j0; j <= j1; ++j) {
             for (int i = i0; i <= i1; ++i) {
@@ -681,21 +687,28 @@ static int orc_is_hit(uint64_t k)
  * center_rgb (optional, [S][H][W][3]) receives the raw centre shading. */
 int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                 const uint64_t *vis, const float *cams, uint32_t n_scenes, int width,
-                int height, const orc_shade_params *sp, double *out_rgba, double *center_rgb)
+                int height, const orc_shade_params *sp, const int *win, double *out_rgba,
+                double *center_rgb)
 {
     size_t npix = (size_t)width * height;
     if (sp->mode == 1) return -2;   /* soft coverage lives in the binary64 torch oracle */
-    double *cc = (double *)malloc(sizeof(double) * 3 * npix);
+    double *cc = (double *)calloc(3 * npix, sizeof(double));
     if (!cc) return -1;
     int r = sp->filter_radius;
     double spar = r * sp->s_par, sperp = r * sp->s_perp, siso = sp->iso_scale * r;
+    /* output window (inclusive) and the centre-shading window it depends on */
+    int oi0 = 0, oj0 = 0, oi1 = width - 1, oj1 = height - 1;
+    if (win) { oi0 = win[0]; oj0 = win[1]; oi1 = win[2]; oj1 = win[3]; }
+    int ci0 = oi0 - r < 0 ? 0 : oi0 - r, cj0 = oj0 - r < 0 ? 0 : oj0 - r;
+    int ci1 = oi1 + r > width - 1 ? width - 1 : oi1 + r;
+    int cj1 = oj1 + r > height - 1 ? height - 1 : oj1 + r;
     for (uint32_t s = 0; s < n_scenes; ++s) {
         const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)s);
         const uint64_t *g = vis + (size_t)s * 2 * npix, *a = g + npix;
         double *out = out_rgba + (size_t)s * 4 * npix;
         /* pass 1: centre shading of every centre-sample hit */
-        for (int j = 0; j < height; ++j)
-            for (int i = 0; i < width; ++i) {
+        for (int j = cj0; j <= cj1; ++j)
+            for (int i = ci0; i <= ci1; ++i) {
                 size_t p = (size_t)j * width + i;
                 double *o = cc + 3 * p;
                 o[0] = o[1] = o[2] = 0.0;
@@ -707,8 +720,8 @@ int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                 }
             }
         /* pass 2: reconstruction */
-        for (int j = 0; j < height; ++j)
-            for (int i = 0; i < width; ++i) {
+        for (int j = oj0; j <= oj1; ++j)
+            for (int i = oi0; i <= oi1; ++i) {
                 size_t p = (size_t)j * width + i;
                 double *o = out + 4 * p;
                 int hc = orc_is_hit(g[p]), ha = orc_is_hit(a[p]);

@@ -73,11 +73,11 @@ def lib():
         L.orc_generate.argtypes = [P, P, u32, u32, u32, P, P, P, P, u32, f32, f32, f32, P,
                                    P, P, P]
         L.orc_raster.restype = i32
-        L.orc_raster.argtypes = [P, P, P, P, u32, i32, i32, f32, P, i32, P, u64, P]
+        L.orc_raster.argtypes = [P, P, P, P, u32, i32, i32, f32, P, i32, P, u64, P, P]
         L.orc_cover_counts.restype = i32
         L.orc_cover_counts.argtypes = [P, P, P, P, u32, i32, i32, f32, P]
         L.orc_resolve.restype = i32
-        L.orc_resolve.argtypes = [P, P, P, P, P, u32, i32, i32, P, P, P]
+        L.orc_resolve.argtypes = [P, P, P, P, P, u32, i32, i32, P, P, P, P]
         _lib = L
     return _lib
 
@@ -182,7 +182,9 @@ def generate(sc, table: np.ndarray, n_cp: int):
 
 
 def raster(pos_w, flags, scene_off, cams, width, height, r_min=0.0, scene_z=None,
-           brute=False, order=None):
+           brute=False, order=None, window=None):
+    """window (i0, j0, i1, j1), inclusive: compute only those pixels (others keep
+    the prefill)."""
     """Visibility buffer [S][2][H][W] uint64 (layer 0 centre, 1 conservative)."""
     S = int(np.asarray(cams).reshape(-1, 18).shape[0])
     vis = np.zeros((S, 2, height, width), np.uint64)
@@ -193,7 +195,8 @@ def raster(pos_w, flags, scene_off, cams, width, height, r_min=0.0, scene_z=None
     sz = None if scene_z is None else _c(scene_z, np.float32)
     od = None if order is None else _c(order, np.uint32)
     lib().orc_raster(_p(pos_w), _p(flags), _p(soff), _p(cams), S, width, height, r_min, _p(sz),
-                     1 if brute else 0, _p(od), 0 if od is None else od.shape[0], _p(vis))
+                     1 if brute else 0, _p(od), 0 if od is None else od.shape[0],
+                     _p(None if window is None else np.asarray(window, np.int32)), _p(vis))
     return vis
 
 
@@ -245,16 +248,18 @@ def _shade_struct(rp, mode, bg):
 
 
 def resolve(pos_w, rgb, flags, vis, cams, width, height, rp, mode=0, bg=(0.0, 0.0, 0.0),
-            want_center=False):
-    """Filtered (mode 0) or centre-only (mode 2) RGBA [S][H][W][4] in float64."""
+            want_center=False, window=None):
+    """Filtered (mode 0) or centre-only (mode 2) RGBA [S][H][W][4] in float64.
+    window (i0, j0, i1, j1), inclusive: compute only those output pixels."""
     S = int(np.asarray(cams).reshape(-1, 18).shape[0])
     out = np.zeros((S, height, width, 4), np.float64)
     cc = np.zeros((S, height, width, 3), np.float64) if want_center else None
     sp = _shade_struct(rp, mode, bg)
+    win = None if window is None else np.asarray(window, np.int32)
     rc = lib().orc_resolve(_p(_c(pos_w, np.float32)), _p(_c(rgb, np.float32)),
                            _p(_c(flags, np.uint8)), _p(_c(vis, np.uint64)),
                            _p(_c(cams, np.float32)), S, width, height, ctypes.byref(sp),
-                           _p(out), _p(cc))
+                           _p(win), _p(out), _p(cc))
     if rc != 0:
         raise ValueError(f"oracle resolve failed ({rc})")
     return (out, cc) if want_center else out

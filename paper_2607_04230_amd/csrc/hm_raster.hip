@@ -179,74 +179,124 @@ __device__ __forceinline__ bool seg_hits_box(const Seg &sg, float px0, float px1
     return lo <= slack && hi >= -slack;
 }
 
-// pass 0: count per tile (+ long list); pass 1: scatter ids into the lists.
+// Tiles of one segment: the box [tx0, tx1] x [ty0, ty1] of tiles its candidate
+// pixels fall in (nt = 0: nothing to draw; nt > K: a long segment).
+struct SegTiles {
+    Seg sg;
+    uint32_t s, tx0, ty0, bw, nt;
+};
+
+__device__ __forceinline__ bool seg_tiles(const float4 *proj, const uint8_t *flags,
+                                          const uint32_t *scene_off, const RasterK &rk, uint32_t v,
+                                          uint32_t n, SegTiles &st)
+{
+    st.nt = 0;
+    if (v >= n || !load_seg(proj, flags, v, n, rk.r_min, st.sg)) return false;
+    int i0, i1, j0, j1;
+    if (!seg_box(st.sg, rk.W, rk.H, i0, i1, j0, j1)) return false;
+    st.s = scene_of(scene_off, rk.S, v);
+    st.tx0 = (uint32_t)i0 / rk.T;
+    st.ty0 = (uint32_t)j0 / rk.T;
+    st.bw = (uint32_t)i1 / rk.T - st.tx0 + 1;
+    st.nt = st.bw * ((uint32_t)j1 / rk.T - st.ty0 + 1);
+    return true;
+}
+
+// k-th tile of the segment's tile box; returns false when the segment cannot
+// reach it.
+__device__ __forceinline__ bool seg_tile_k(const SegTiles &st, const RasterK &rk, uint32_t k,
+                                           uint32_t &tile)
+{
+    const uint32_t tx = st.tx0 + k % st.bw, ty = st.ty0 + k / st.bw;
+    const float px0 = (float)(tx * rk.T), py0 = (float)(ty * rk.T);
+    tile = (st.s * rk.nty + ty) * rk.ntx + tx;
+    return seg_hits_box(st.sg, px0, px0 + (float)rk.T, py0, py0 + (float)rk.T);
+}
+
+constexpr uint32_t BIN_SLOTS = 1024;      // LDS hash slots per workgroup
+constexpr uint32_t BIN_FREE = 0xFFFFFFFFu;
+
+// Slot of `tile` in the workgroup's LDS table (linear probing), -1 if full.
+__device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
+{
+    const uint32_t h = (tile * 2654435761u) >> 22;          // 10 bits
+    for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
+        const uint32_t sl = (h + i) & (BIN_SLOTS - 1);
+        const uint32_t prev = atomicCAS(&keys[sl], BIN_FREE, tile);
+        if (prev == BIN_FREE || prev == tile) return (int)sl;
+    }
+    return -1;
+}
+
+// Per-tile segment lists.  Each workgroup takes blockDim consecutive segments
+// (consecutive segments belong to the same few strands, so they fall in a few
+// tiles) and aggregates its (segment, tile) pairs per tile in an LDS table:
+//   pass 0: counts per tile, flushed with one non-returning global add per
+//           (workgroup, tile); segments spanning more than K tiles go to the
+//           long list;
+//   pass 1: one returning global add per (workgroup, tile) reserves a range
+//           of the tile's list; pairs then take LDS-atomic ranks inside it.
 __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const uint8_t *flags,
                                              const uint32_t *scene_off, RasterK rk, uint32_t cap,
                                              uint32_t *tile_cnt, const uint32_t *tile_off,
                                              uint32_t *tile_cur, uint32_t *entries,
                                              uint32_t *long_list, uint32_t *counters)
 {
+    __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t total = scene_off[rk.S];
     const uint32_t n = total < cap ? total : cap;
-    const int lane = lane_id();
-    const uint64_t lt_mask = (1ull << lane) - 1ull;
-    // uniform trip count per wave: every lane of the wave runs the ballots
-    const uint32_t stride = gridDim.x * blockDim.x;
-    const uint32_t base0 = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
-    for (uint32_t base = base0; base < n; base += stride) {
-        const uint32_t v = base + lane;
-        Seg sg;
-        bool ok = v < n && load_seg(proj, flags, v, n, rk.r_min, sg);
-        int i0 = 0, i1 = -1, j0 = 0, j1 = -1;
-        if (ok) ok = seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
-        uint32_t s = 0, tx0 = 0, tx1 = 0, ty0 = 0, ty1 = 0, nt = 0;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+            keys[x] = BIN_FREE;
+            cnt[x] = 0;
+        }
+        __syncthreads();
+        const uint32_t v = base + threadIdx.x;
+        SegTiles st;
+        bool ok = seg_tiles(proj, flags, scene_off, rk, v, n, st);
+        if (ok && st.nt > rk.K) {
+            if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
+            ok = false;
+        }
         if (ok) {
-            s = scene_of(scene_off, rk.S, v);
-            tx0 = (uint32_t)i0 / rk.T; tx1 = (uint32_t)i1 / rk.T;
-            ty0 = (uint32_t)j0 / rk.T; ty1 = (uint32_t)j1 / rk.T;
-            nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-            if (nt > rk.K) {
-                if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
-                ok = false;
-                nt = 0;
+            for (uint32_t k = 0; k < st.nt; ++k) {
+                uint32_t tile;
+                if (!seg_tile_k(st, rk, k, tile)) continue;
+                const int sl = bin_slot(keys, tile);
+                if (sl >= 0) atomicAdd(&cnt[sl], 1u);
+                else if (pass == 0) atomicAdd(&tile_cnt[tile], 1u);
+                else entries[tile_off[tile] + atomicAdd(&tile_cur[tile], 1u)] = v;
             }
         }
-        // iterate the k-th tile of every lane's box; aggregate equal tiles per wave
-        uint32_t maxnt = nt;
-        for (int d = 32; d >= 1; d >>= 1) {
-            uint32_t o = __shfl_xor(maxnt, d, 64);
-            maxnt = o > maxnt ? o : maxnt;
-        }
-        const uint32_t bw = tx1 - tx0 + 1;
-        for (uint32_t k = 0; k < maxnt; ++k) {
-            bool has = ok && k < nt;
-            uint32_t tile = 0;
-            if (has) {
-                const uint32_t tx = tx0 + k % bw, ty = ty0 + k / bw;
-                const float px0 = (float)(tx * rk.T), py0 = (float)(ty * rk.T);
-                has = seg_hits_box(sg, px0, px0 + (float)rk.T, py0, py0 + (float)rk.T);
-                tile = (s * rk.nty + ty) * rk.ntx + tx;
+        __syncthreads();
+        for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+            const uint32_t t = keys[x];
+            if (t == BIN_FREE) continue;
+            if (pass == 0) {
+                atomicAdd(&tile_cnt[t], cnt[x]);
+            } else {
+                basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], cnt[x]);
+                cnt[x] = 0;
             }
-            uint64_t active = __ballot(has);
-            while (active) {
-                const int leader = __ffsll((unsigned long long)active) - 1;
-                const uint32_t lt = __shfl(tile, leader, 64);
-                const bool mine = has && tile == lt;
-                const uint64_t same = __ballot(mine);
-                uint32_t b = 0;
-                if (lane == leader) {
-                    const uint32_t cnt = (uint32_t)__popcll(same);
-                    b = pass == 0 ? atomicAdd(&tile_cnt[lt], cnt) : atomicAdd(&tile_cur[lt], cnt);
+        }
+        __syncthreads();
+        if (pass == 1 && ok) {
+            for (uint32_t k = 0; k < st.nt; ++k) {
+                uint32_t tile;
+                if (!seg_tile_k(st, rk, k, tile)) continue;
+                // the slot exists already: the same pairs were inserted above
+                const uint32_t h = (tile * 2654435761u) >> 22;
+                int sl = -1;
+                for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
+                    const uint32_t q = (h + i) & (BIN_SLOTS - 1);
+                    const uint32_t kq = keys[q];
+                    if (kq == tile) { sl = (int)q; break; }
+                    if (kq == BIN_FREE) break;
                 }
-                b = __shfl(b, leader, 64);
-                if (mine) {
-                    if (pass == 1)
-                        entries[tile_off[lt] + b + (uint32_t)__popcll(same & lt_mask)] = v;
-                    has = false;
-                }
-                active &= ~same;
+                if (sl >= 0) entries[basev[sl] + atomicAdd(&cnt[sl], 1u)] = v;
             }
         }
+        __syncthreads();
     }
 }
 
@@ -311,6 +361,21 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
         const int py1 = min(py0 + (int)rk.T, (int)rk.H) - 1;
         float zn, inv_range;
         scene_depth_consts(cams, s, zn, inv_range);
+        uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
+        const uint32_t tw = (uint32_t)(px1 - px0 + 1), th = (uint32_t)(py1 - py0 + 1);
+        // a tile that is one work item owns its pixels: start from the
+        // prefilled values and write back without atomics
+        const bool whole = tend - tile_off[t] <= rk.chunk;
+        if (whole) {
+            for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
+                const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+                if (lx >= tw || ly >= th) continue;
+                const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
+                lc[x] = vc[p];
+                la[x] = va[p];
+            }
+            __syncthreads();
+        }
 
         for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
             const uint32_t v = entries[e];
@@ -337,15 +402,18 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             }
         }
         __syncthreads();
-        uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
-        const uint32_t tw = (uint32_t)(px1 - px0 + 1);
         for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
             const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
-            if (lx >= tw || (int)ly > py1 - py0) continue;
+            if (lx >= tw || ly >= th) continue;
             const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
             const uint64_t kc = lc[x], ka = la[x];
-            if (kc != HM_EMPTY) atomicMin((unsigned long long *)(vc + p), (unsigned long long)kc);
-            if (ka != HM_EMPTY) atomicMin((unsigned long long *)(va + p), (unsigned long long)ka);
+            if (whole) {
+                vc[p] = kc;
+                va[p] = ka;
+            } else {
+                if (kc != HM_EMPTY) atomicMin((unsigned long long *)(vc + p), (unsigned long long)kc);
+                if (ka != HM_EMPTY) atomicMin((unsigned long long *)(va + p), (unsigned long long)ka);
+            }
         }
         __syncthreads();
     }
@@ -458,7 +526,7 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.r_min = 0.0f;
     p.algo = HM_RASTER_TILED;
     p.tile = 32;
-    p.chunk = 256;
+    p.chunk = 8192;
     p.max_tiles_per_seg = 4;
     p.block = 256;
     p.grid = 0;

@@ -69,7 +69,57 @@ class ShadeParams(ctypes.Structure):
 
 EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_shade",
            "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
-           "hm_version", "hm_timing_enable", "hm_timing_collect"]
+           "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
+           "hm_graph_create", "hm_graph_launch", "hm_graph_destroy"]
+
+
+class FrameDesc(ctypes.Structure):
+    _fields_ = [("mesh", HairMesh), ("cams", _vp), ("frame", Frame), ("lod", LodParams),
+                ("table", _vp), ("ws_lod", _vp), ("ws_lod_bytes", _sz), ("strand_base", _vp),
+                ("strand_rgb", _vp), ("gen", GenParams), ("strands", Strands), ("totals", _vp),
+                ("raster", RasterParams), ("scene_z", _vp), ("vis", _vp), ("ws_raster", _vp),
+                ("ws_raster_bytes", _sz), ("shade", ShadeParams), ("out_rgba", _vp),
+                ("ws_resolve", _vp), ("ws_resolve_bytes", _sz)]
+
+
+def render_frame(d: "FrameDesc"):
+    L = load()
+    L.hm_render_frame.argtypes = [ctypes.POINTER(FrameDesc), _vp]
+    L.hm_render_frame.restype = _i32
+    _check(L.hm_render_frame(ctypes.byref(d), _stream()), "hm_render_frame")
+
+
+class Graph:
+    """A frame captured once into a HIP graph (hm_graph_create) and replayed
+    with hm_graph_launch; the descriptor's buffers must stay alive."""
+
+    def __init__(self, d: "FrameDesc", stream_handle: int):
+        L = load()
+        L.hm_graph_create.argtypes = [ctypes.POINTER(FrameDesc), _vp, ctypes.POINTER(_vp)]
+        L.hm_graph_create.restype = _i32
+        L.hm_graph_launch.argtypes = [_vp, _vp]
+        L.hm_graph_launch.restype = _i32
+        L.hm_graph_destroy.argtypes = [_vp]
+        L.hm_graph_destroy.restype = _i32
+        self._d = d
+        h = _vp()
+        _check(L.hm_graph_create(ctypes.byref(d), stream_handle, ctypes.byref(h)), "hm_graph_create")
+        self.handle = h
+
+    def launch(self, stream_handle: int = None):
+        _check(load().hm_graph_launch(self.handle, _stream() if stream_handle is None
+                                      else stream_handle), "hm_graph_launch")
+
+    def close(self):
+        if self.handle:
+            load().hm_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 _lib = None
 

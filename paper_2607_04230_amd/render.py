@@ -100,6 +100,42 @@ class DeviceScene:
         self.resolve()
         return self.out
 
+    # ------------------------------------------------------------ whole frame
+    def frame_desc(self) -> hm.FrameDesc:
+        d = hm.FrameDesc()
+        d.mesh = self.mesh
+        d.cams = hm._ptr(self.cams)
+        d.frame = self.fr
+        d.lod = hm.LodParams(self.sc.lod_mode, self.sc.lod_lambda, self.sc.seed)
+        d.table = hm._ptr(self.table)
+        d.ws_lod, d.ws_lod_bytes = hm._ptr(self.ws_lod), self.ws_lod.numel()
+        d.strand_base = hm._ptr(self.strand_base)
+        d.strand_rgb = hm._ptr(self.strand_rgb)
+        d.gen = self.gp
+        d.strands = self.st
+        d.totals = hm._ptr(self.totals)
+        d.raster = self.rparams
+        d.scene_z = hm._ptr(self.scene_z)
+        d.vis = hm._ptr(self.vis)
+        d.ws_raster, d.ws_raster_bytes = hm._ptr(self.ws_raster), self.ws_raster.numel()
+        d.shade = self.sp
+        d.out_rgba = hm._ptr(self.out)
+        d.ws_resolve, d.ws_resolve_bytes = hm._ptr(self.ws_resolve), self.ws_resolve.numel()
+        return d
+
+    def render_native(self):
+        """The whole frame through one C call (hm_render_frame)."""
+        hm.render_frame(self.frame_desc())
+        return self.out
+
+    def capture_graph(self) -> hm.Graph:
+        """Capture the frame into a HIP graph on the current (non-default) stream."""
+        import torch
+        h = torch.cuda.current_stream().cuda_stream
+        if not h:
+            raise RuntimeError("capture needs a non-default stream (use torch.cuda.stream)")
+        return hm.Graph(self.frame_desc(), h)
+
     # ------------------------------------------------------------ host views
     def n_cp(self) -> int:
         return int(self.totals[1].item())

@@ -81,6 +81,7 @@ class Scene:
     r_min: float = 0.0
     mode: int = MODE_FILTER
     bg: tuple = (0.0, 0.0, 0.0)
+    meta: dict = dataclasses.field(default_factory=dict)   # builder facts (e.g. head centres)
 
     @property
     def n_scenes(self) -> int:
@@ -287,7 +288,7 @@ def config_lod(seed=1003, width=2560, height=1440, n_heads=32, lod_lambda=3.0) -
     sz = sphere_depth(cam, width, height, centers)
     return Scene("lod", lp, quads_all, ky, ns, cm, sc, base, rgb, cam, width, height, sz,
                  seed=seed, strand_width=0.0008, lod_mode=LOD_ON, lod_lambda=lod_lambda,
-                 mode=MODE_FILTER)
+                 mode=MODE_FILTER, meta={"centers": np.array(centers)})
 
 
 def config_batched(seed=1004, n_scenes=64, res=512, n_min=1e3, n_max=2e5) -> Scene:
@@ -341,6 +342,25 @@ def perturb_stream(pos_w: np.ndarray, rgb: np.ndarray, seed: int, sigma=0.01):
     p[:, 3] *= 1.0 + rng.normal(0.0, sigma, p.shape[0])
     c[:, :3] += rng.normal(0.0, sigma, (c.shape[0], 3))
     return p.astype(np.float32), c.astype(np.float32)
+
+
+def select_scene(sc: Scene, s: int) -> Scene:
+    """Scene s of a multi-scene frame as a frame of its own."""
+    sel = np.nonzero(sc.bundle_scene == s)[0]
+    ns = sc.bundle_nstrands[sel].copy()
+    base = np.zeros(sel.size, np.uint32)
+    if sel.size > 1:
+        base[1:] = np.cumsum(ns.astype(np.int64))[:-1].astype(np.uint32)
+    rgb = None
+    if sc.strand_rgb is not None and sel.size:
+        a = int(sc.strand_base[sel[0]])
+        rgb = sc.strand_rgb[a:a + int(ns.astype(np.int64).sum())].copy()
+    return dataclasses.replace(
+        sc, name=f"{sc.name}[{s}]", quads=sc.quads[sel].copy(), bundle_key=sc.bundle_key[sel].copy(),
+        bundle_nstrands=ns, bundle_cmax=sc.bundle_cmax[sel].copy(),
+        bundle_scene=np.zeros(sel.size, np.uint32), strand_base=base, strand_rgb=rgb,
+        cams=sc.cams[s:s + 1].copy(),
+        scene_z=None if sc.scene_z is None else sc.scene_z[s:s + 1].copy(), meta={})
 
 
 CONFIGS = {
