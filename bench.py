@@ -114,6 +114,117 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
             "frac": ach / PEAK_HBM_GBS, "traffic": _traffic(kernel)}
 
 
+def _time_ms(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def extra_batched(steps):
+    """64 scenes of uneven size: one multi-scene frame (every kernel covers all
+    scenes; one persistent raster launch) eager and as a replayed HIP graph, vs
+    one frame per scene."""
+    import torch
+    from paper_2607_04230_amd import autotune, scenes
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_batched()
+    ds = DeviceScene(sc)
+    p, _ = autotune.tune(ds, autotune.QUICK_CANDIDATES, reps=3)
+    res = {"scenes": sc.n_scenes, "strands": sc.n_full_strands, "segments": sc.n_seg_full,
+           "raster_params": {"algo": p.algo, "tile": p.tile, "chunk": p.chunk, "block": p.block,
+                             "max_tiles_per_seg": p.max_tiles_per_seg}}
+    res["batched_ms"] = _time_ms(ds.render, steps, 2)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g = ds.capture_graph()
+        res["graph_ms"] = _time_ms(g.launch, steps, 2)
+        g.close()
+    singles = []
+    for s in range(sc.n_scenes):
+        d1 = DeviceScene(scenes.select_scene(sc, s), rparams=hm_params_copy(p))
+        singles.append(d1)
+
+    def per_scene():
+        for d1 in singles:
+            d1.render()
+    res["per_scene_ms"] = _time_ms(per_scene, max(steps // 4, 2), 1)
+    res["segments_per_s_graph"] = sc.n_seg_full / (res["graph_ms"] * 1e-3)
+    del singles
+    torch.cuda.empty_cache()
+    return res
+
+
+def hm_params_copy(p):
+    from paper_2607_04230_amd import hm
+    return hm.RasterParams(p.r_min, p.algo, p.tile, p.chunk, p.max_tiles_per_seg, p.block, p.grid)
+
+
+def extra_lod(steps):
+    """32 heads at geometric distances, 2560x1440, LOD on."""
+    import torch
+    from paper_2607_04230_amd import scenes
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_lod()
+    ds = DeviceScene(sc)
+    ms = _time_ms(ds.render, steps, 2)
+    tot = ds.totals.cpu().numpy()
+    seg = int(tot[1]) - int(tot[0])
+    r = {"ms_per_frame": ms, "strands_full": sc.n_full_strands, "strands_after_lod": int(tot[0]),
+         "segments_after_lod": seg, "segments_full": sc.n_seg_full,
+         "segments_per_s": seg / (ms * 1e-3)}
+    del ds
+    torch.cuda.empty_cache()
+    return r
+
+
+def extra_diff(steps):
+    """Soft-coverage forward vs forward + backward (visibility recomputed)."""
+    import numpy as np
+    import torch
+    from paper_2607_04230_amd import scenes
+    from paper_2607_04230_amd.diff import SoftContext, soft_render
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_diff()
+    ds = DeviceScene(sc)
+    ds.lod()
+    ds.generate()
+    torch.cuda.synchronize()
+    n = ds.n_cp()
+    pos = ds.pos_w[:n].clone()
+    rgb = ds.rgb[:n].clone()
+    ctx = SoftContext(ds.flags[:n].clone(), ds.scene_off.clone(), ds.cams, sc.width, sc.height,
+                      r_min=sc.r_min)
+    tp, tc = scenes.perturb_stream(pos.cpu().numpy(), rgb.cpu().numpy(), seed=sc.seed + 1)
+    with torch.no_grad():
+        target = soft_render(torch.from_numpy(tp).cuda(), torch.from_numpy(tc).cuda(), ctx).clone()
+    p = pos.clone().requires_grad_(True)
+    c = rgb.clone().requires_grad_(True)
+
+    def fwd():
+        with torch.no_grad():
+            out = soft_render(p, c, ctx)
+            ((out - target) ** 2).sum()
+
+    def fwd_bwd():
+        out = soft_render(p, c, ctx)
+        loss = ((out - target) ** 2).sum()
+        loss.backward()
+
+    f = _time_ms(fwd, steps, 3)
+    fb = _time_ms(fwd_bwd, steps, 3)
+    return {"fwd_ms": f, "fwd_bwd_ms": fb, "ratio": fb / f, "segments": n - sc.n_full_strands,
+            "params": int(n)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +232,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the LOD, batched and differentiable workloads")
+    ap.add_argument("--profile", action="store_true",
+                    help="counter-collection mode: the main frames plus one 256 MiB device "
+                         "copy of known size (counter calibration); prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -137,6 +253,15 @@ def main():
     torch.cuda.set_device(0)
     sc = scenes.config_head()
     ds = DeviceScene(sc)
+    if args.profile:
+        for _ in range(args.warmup + args.steps):
+            ds.render()
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] profile mode done: frames + one 256 MiB copy", file=sys.stderr)
+        return
     print(f"[bench] workload built: {sc.n_full_strands} strands, {sc.n_seg_full} segments, "
           f"{sc.width}x{sc.height}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
@@ -197,6 +322,12 @@ def main():
         "kernels": per_kernel,
         "hair_pixels": hair_px,
     }
+    if not args.no_extras:
+        del ds
+        torch.cuda.empty_cache()
+        for name, fn in (("lod", extra_lod), ("batched", extra_batched), ("diff", extra_diff)):
+            print(f"[bench] extra workload: {name}", file=sys.stderr, flush=True)
+            line[name] = fn(max(args.steps // 2, 5))
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)

@@ -87,12 +87,16 @@ __device__ __forceinline__ bool seg_box(const Seg &sg, uint32_t W, uint32_t H, i
     return i0 <= i1 && j0 <= j1;
 }
 
-// Column range of candidate pixels in row j: the part of the segment whose y
-// lies within the row band widened by ra + 1.5 px, widened by ra + 1.5 px in x.
+// Column range of candidate pixels in row j.  Pixel (i, j) can pass either
+// test only if the segment has a point with y in [j - ra, j + 1 + ra] and x in
+// [i - ra, i + 1 + ra] (the centre test's disc of radius r <= ra around the
+// pixel centre lies inside that square).  So: clip the segment to the row band
+// widened by ra, and take i in [x_lo - 1 - ra, x_hi + ra]; a 0.05 px slack
+// absorbs binary32 rounding of the clip.
 __device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
 {
-    const float m = sg.ra + 1.5f;
-    const float ylo = (float)j - m, yhi = ((float)j + 1.0f) + m;
+    const float e = 0.05f;
+    const float ylo = ((float)j - sg.ra) - e, yhi = (((float)j + 1.0f) + sg.ra) + e;
     float xlo = sg.sxmn, xhi = sg.sxmx;
     if (fabsf(sg.dy) > 1e-3f) {
         float ta = (ylo - sg.y0) / sg.dy, tb = (yhi - sg.y0) / sg.dy;
@@ -101,10 +105,13 @@ __device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
         float xa = sg.x0 + t0 * sg.dx, xb = sg.x0 + t1 * sg.dx;
         xlo = fminx(xa, xb);
         xhi = fmaxx(xa, xb);
+    } else if (sg.symx < ylo || sg.symn > yhi) {
+        i0 = 1; i1 = 0;
+        return;
     }
-    const float flo = xlo - m, fhi = xhi + m;
-    i0 = flo > -1.0e9f ? (int)floorf(flo) : -1000000000;
-    i1 = fhi < 1.0e9f ? (int)ceilf(fhi) : 1000000000;
+    const float flo = ((xlo - 1.0f) - sg.ra) - e, fhi = (xhi + sg.ra) + e;
+    i0 = flo > -1.0e9f ? (int)ceilf(flo) : -1000000000;
+    i1 = fhi < 1.0e9f ? (int)floorf(fhi) : 1000000000;
 }
 
 __device__ __forceinline__ bool load_seg(const float4 *proj, const uint8_t *flags, uint32_t v,
