@@ -256,9 +256,10 @@ def main():
     if args.profile:
         for _ in range(args.warmup + args.steps):
             ds.render()
-        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+        # known-size reference for the byte counters: reads 256 MiB, writes 256 MiB
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print("[bench] profile mode done: frames + one 256 MiB copy", file=sys.stderr)
         return

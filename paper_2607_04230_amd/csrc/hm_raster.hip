@@ -334,6 +334,9 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
 {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t sh_item;
+    __shared__ uint32_t sh_pre[1024], sh_v[1024];
+    __shared__ int sh_j0[1024];
+    __shared__ uint32_t sh_scan[1024 / 64 + 1];
     const uint32_t TT = rk.T * rk.T;
     uint64_t *lc = lds, *la = lds + TT;
     const uint32_t total = scene_off[rk.S];
@@ -384,15 +387,47 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             __syncthreads();
         }
 
-        for (uint32_t e = beg + threadIdx.x; e < end; e += blockDim.x) {
-            const uint32_t v = entries[e];
-            Seg sg;
-            if (!load_seg(proj, flags, v, n, rk.r_min, sg)) continue;
-            int i0, i1, j0, j1;
-            if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
-            i0 = max(i0, px0); i1 = min(i1, px1);
-            j0 = max(j0, py0); j1 = min(j1, py1);
-            for (int j = j0; j <= j1; ++j) {
+        // Batches of blockDim segments; their (segment, row) pairs are spread
+        // evenly over the workgroup by a prefix scan of the row counts, so a
+        // long segment does not hold up the lanes that drew short ones.
+        for (uint32_t e0 = beg; e0 < end; e0 += blockDim.x) {
+            const uint32_t e = e0 + threadIdx.x;
+            uint32_t nr = 0, v = 0;
+            int jr0 = 0;
+            if (e < end) {
+                v = entries[e];
+                Seg sg;
+                int i0, i1, j0, j1;
+                if (load_seg(proj, flags, v, n, rk.r_min, sg) &&
+                    seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
+                    j0 = max(j0, py0);
+                    j1 = min(j1, py1);
+                    if (max(i0, px0) <= min(i1, px1) && j0 <= j1) {
+                        nr = (uint32_t)(j1 - j0 + 1);
+                        jr0 = j0;
+                    }
+                }
+            }
+            uint32_t tot;
+            const uint32_t pre = block_exclusive_scan(nr, sh_scan, tot);
+            sh_pre[threadIdx.x] = pre;
+            sh_v[threadIdx.x] = v;
+            sh_j0[threadIdx.x] = jr0;
+            __syncthreads();
+            for (uint32_t rr = threadIdx.x; rr < tot; rr += blockDim.x) {
+                // owner: last lane whose first row slot is <= rr
+                uint32_t lo = 0, hi = blockDim.x;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (sh_pre[mid] <= rr) lo = mid; else hi = mid;
+                }
+                const uint32_t vo = sh_v[lo];
+                const Seg sg = make_seg(proj[vo], proj[vo + 1], rk.r_min);
+                int i0, i1, j0, j1;
+                seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
+                i0 = max(i0, px0);
+                i1 = min(i1, px1);
+                const int j = sh_j0[lo] + (int)(rr - sh_pre[lo]);
                 int a0, a1;
                 row_span(sg, j, a0, a1);
                 a0 = max(a0, i0);
@@ -401,14 +436,14 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     uint32_t q;
                     const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
                     if (!msk) continue;
-                    const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | v;
+                    const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | vo;
                     const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
                     if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
                     if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
         for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
             const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
             if (lx >= tw || ly >= th) continue;
