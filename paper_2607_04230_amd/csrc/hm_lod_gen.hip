@@ -326,15 +326,145 @@ __global__ __launch_bounds__(256) void k_generate(hm_hair_mesh m, const uint32_t
     }
 }
 
+// Cooperative assembly, one wave per bundle (the paper assigns a subgroup per
+// strand and shares control points through shuffles; on gfx950 a 64-lane wave
+// shares a bundle's strands through LDS): the strands' (u, v, phase), base
+// layer points and layer tangents are computed once into LDS, then every lane
+// evaluates control points (Hermite + curl) from LDS and stores them
+// coalesced.  Strands are processed in chunks that fit the LDS budget.
+constexpr uint32_t GEN_LDS_FLOATS = 6144;   // 24 KB
+
+__global__ __launch_bounds__(64) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
+                                                        const uint32_t *strand_base,
+                                                        const float *strand_rgb, GenK g,
+                                                        float4 *pos_w, float4 *rgb,
+                                                        uint8_t *flags, const uint32_t *scene_off,
+                                                        uint32_t S, uint32_t cap)
+{
+    __shared__ float sm[GEN_LDS_FLOATS];
+    const uint32_t b = blockIdx.x;
+    const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
+    const uint32_t n = tb.x, C = tb.y, cp0 = tb.w;
+    if (n == 0) return;
+    const uint32_t total = scene_off[S];
+    const uint32_t limit = total < cap ? total : cap;
+    const uint32_t NL = m.n_layers;
+    const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
+    const uint32_t chunk = GEN_LDS_FLOATS / stride;        // >= 15 strands for L <= 64
+    const uint4 q4 = reinterpret_cast<const uint4 *>(m.quads)[b];
+    const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
+    const uint32_t hb = bundle_hash(g.seed, m.bundle_key[b]);
+
+    // bundle styling frame from the first layer interval
+    F3 s0 = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+        const F3 a0 = ld3(m.layer_pos + 3 * (size_t)q[k2]);
+        const F3 a1 = ld3(m.layer_pos + ((size_t)m.n_verts + q[k2]) * 3);
+        const F3 d = f3sub(a1, a0);
+        s0.x = s0.x + d.x; s0.y = s0.y + d.y; s0.z = s0.z + d.z;
+    }
+    const F3 nb = f3norm(s0);
+    F3 ax = {0.0f, 0.0f, 1.0f};
+    if (fabsf(nb.z) > 0.9f) { ax.x = 1.0f; ax.z = 0.0f; }
+    const F3 e1 = f3norm(f3cross(nb, ax));
+    const F3 e2 = f3cross(nb, e1);
+
+    for (uint32_t k0 = 0; k0 < n; k0 += chunk) {
+        const uint32_t nk = (n - k0) < chunk ? (n - k0) : chunk;
+        // strand hashes
+        for (uint32_t kk = threadIdx.x; kk < nk; kk += blockDim.x) {
+            const uint32_t h1 = pcg(hb + (k0 + kk));
+            const uint32_t h2 = pcg(h1);
+            const uint32_t h3 = pcg(h2);
+            float *o = sm + kk * stride + 6u * NL;
+            o[0] = unit24(h1);
+            o[1] = unit24(h2);
+            o[2] = unit24(h3);
+        }
+        __syncthreads();
+        // base layer points
+        for (uint32_t x = threadIdx.x; x < nk * NL; x += blockDim.x) {
+            const uint32_t kk = x / NL, l = x - kk * NL;
+            float *o = sm + kk * stride;
+            const F3 P = layer_point(m.layer_pos, m.n_verts, l, q, o[6u * NL], o[6u * NL + 1]);
+            o[6 * l + 0] = P.x; o[6 * l + 1] = P.y; o[6 * l + 2] = P.z;
+        }
+        __syncthreads();
+        // finite-difference layer tangents
+        for (uint32_t x = threadIdx.x; x < nk * NL; x += blockDim.x) {
+            const uint32_t kk = x / NL, l = x - kk * NL;
+            float *o = sm + kk * stride;
+            const uint32_t la = l == 0 ? 1u : (l == NL - 1 ? l : l + 1);
+            const uint32_t lb = l == 0 ? 0u : l - 1;
+            const F3 T = f3norm(f3sub(ld3(o + 6 * la), ld3(o + 6 * lb)));
+            o[6 * l + 3] = T.x; o[6 * l + 4] = T.y; o[6 * l + 5] = T.z;
+        }
+        __syncthreads();
+        // control points of strands k0 .. k0+nk-1 (contiguous in the stream)
+        for (uint32_t r = threadIdx.x; r < nk * C; r += blockDim.x) {
+            const uint32_t kk = r / C, j = r - kk * C;
+            const uint32_t c = cp0 + (k0 + kk) * C + j;
+            if (c >= limit) continue;
+            const float *o = sm + kk * stride;
+            const float w = (float)j / (float)(C - 1u);
+            const float x = w * (float)(NL - 1u);
+            int i = (int)x;
+            i = i > (int)NL - 2 ? (int)NL - 2 : i;
+            const float t = x - (float)i;
+            const F3 Pi = ld3(o + 6 * i), Pj = ld3(o + 6 * (i + 1));
+            const F3 Ti = ld3(o + 6 * i + 3), Tj = ld3(o + 6 * (i + 1) + 3);
+            const F3 ch = f3sub(Pj, Pi);
+            const float chord = sqrtf((ch.x * ch.x + ch.y * ch.y) + ch.z * ch.z);
+            const float t2 = t * t, t3 = t2 * t;
+            const float h00 = (2.0f * t3 - 3.0f * t2) + 1.0f;
+            const float h10 = (t3 - 2.0f * t2) + t;
+            const float h01 = 3.0f * t2 - 2.0f * t3;
+            const float h11 = t3 - t2;
+            const float pi3[3] = {Pi.x, Pi.y, Pi.z}, pj3[3] = {Pj.x, Pj.y, Pj.z};
+            const float ti3[3] = {Ti.x, Ti.y, Ti.z}, tj3[3] = {Tj.x, Tj.y, Tj.z};
+            float X[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const float m0 = chord * ti3[d], m1 = chord * tj3[d];
+                X[d] = ((h00 * pi3[d] + h10 * m0) + h01 * pj3[d]) + h11 * m1;
+            }
+            float f = g.curl_turns * w + o[6u * NL + 2];
+            f = f - floorf(f);
+            const float a = (f - 0.5f) * 0x1.921fb6p+2f;
+            const float cth = -tcos(a), sth = -tsin(a);
+            const float amp = g.curl_amp * w;
+            float4 pw;
+            pw.x = X[0] + amp * (cth * e1.x + sth * e2.x);
+            pw.y = X[1] + amp * (cth * e1.y + sth * e2.y);
+            pw.z = X[2] + amp * (cth * e1.z + sth * e2.z);
+            pw.w = g.width;
+            pos_w[c] = pw;
+            float4 col;
+            if (strand_rgb) {
+                const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k0 + kk);
+                col = make_float4(sr[0], sr[1], sr[2], 1.0f);
+            } else {
+                col = make_float4(g.br, g.bg, g.bb, 1.0f);
+            }
+            rgb[c] = col;
+            uint8_t fl = 0;
+            if (j == 0) fl |= (uint8_t)HM_ROOT;
+            if (j == C - 1u) fl |= (uint8_t)HM_TIP;
+            flags[c] = fl;
+        }
+        __syncthreads();
+    }
+}
+
 void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
                      const float *strand_rgb, const hm_gen_params &p, const hm_strands &s,
                      hipStream_t st)
 {
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    const uint32_t grid = stride_grid(s.cap, 256);
-    hipLaunchKernelGGL(k_generate, dim3(grid), dim3(256), 0, st, m, table, strand_base,
-                       strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
+    hipLaunchKernelGGL(k_generate_bundle, dim3(m.n_bundles), dim3(64), 0, st, m, table,
+                       strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
                        reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
                        s.cap);
 }

@@ -248,11 +248,11 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
                 e -= (d0 * d0 + d1 * d1 + d2 * d2) * k.inv_sc2;
             }
             if (e > emax) {
-                const float sc = expf(emax - e);
+                const float sc = __expf(emax - e);   // weights: ~1e-6 relative suffices
                 Sx *= sc; Sy *= sc; Sz *= sc; Wsum *= sc;
                 emax = e;
             }
-            const float w = expf(e - emax);
+            const float w = __expf(e - emax);
             Sx += w * Q.x;
             Sy += w * Q.y;
             Sz += w * Q.z;
