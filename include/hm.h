@@ -160,6 +160,9 @@ typedef struct {
     uint32_t max_tiles_per_seg; /* segments touching more tiles take the direct path (1..64) */
     uint32_t block;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
     uint32_t grid;            /* persistent workgroups (0 = auto) */
+    uint32_t shared_views;    /* 0: scene s draws its own stream range scene_off[s..s+1];
+                                 1: multiview -- one stream (strands.n_scenes = 1) drawn
+                                 into every scene of the frame, each with its camera */
 } hm_raster_params;
 
 /* Visibility buffer (Sec. 3.1.2).  vis[s][0] = centre-sample layer,

@@ -136,6 +136,7 @@ static hm_status check_raster_params(const hm_raster_params *p)
     REQUIRE(p->block >= 64 && p->block <= 1024 && p->block % 64 == 0, HM_ERR_RANGE,
             "block must be a multiple of 64 in [64, 1024]");
     REQUIRE(p->grid <= 65536, HM_ERR_RANGE, "grid outside [0, 65536]");
+    REQUIRE(p->shared_views <= 1, HM_ERR_INVALID, "shared_views must be 0 or 1");
     REQUIRE(isfinite(p->r_min) && p->r_min >= 0.0f && p->r_min <= 64.0f, HM_ERR_RANGE,
             "r_min outside [0, 64]");
     return HM_OK;
@@ -298,11 +299,18 @@ hm_status hm_raster_vis(const hm_strands *s, const hm_camera *cams, const hm_fra
     if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = check_raster_params(p)))
         return st;
     REQUIRE(cams && vis, HM_ERR_INVALID, "NULL argument");
-    REQUIRE(s->n_scenes == frame->n_scenes, HM_ERR_INVALID, "strands.n_scenes != frame.n_scenes");
+    if (p->shared_views) {
+        REQUIRE(s->n_scenes == 1, HM_ERR_INVALID, "shared views need a single-scene stream");
+    } else {
+        REQUIRE(s->n_scenes == frame->n_scenes, HM_ERR_INVALID,
+                "strands.n_scenes != frame.n_scenes");
+    }
     const double tiles = (double)((frame->width + p->tile - 1) / p->tile) *
                          ((frame->height + p->tile - 1) / p->tile) * frame->n_scenes;
     REQUIRE(tiles < 1.0e9, HM_ERR_RANGE, "too many tiles");
-    REQUIRE((double)s->cap * p->max_tiles_per_seg < 4.0e9, HM_ERR_RANGE,
+    const double units = (double)s->cap * (p->shared_views ? frame->n_scenes : 1u);
+    REQUIRE(units < 4.0e9, HM_ERR_RANGE, "cap * views exceeds 32-bit segment units");
+    REQUIRE(units * p->max_tiles_per_seg < 4.0e9, HM_ERR_RANGE,
             "cap * max_tiles_per_seg exceeds 32-bit bin offsets");
     if ((st = check_ws(ws, ws_bytes, raster_workspace(*frame, s->cap, *p)))) return st;
     launch_raster(*s, cams, *frame, *p, scene_z, vis, ws, (hipStream_t)stream);

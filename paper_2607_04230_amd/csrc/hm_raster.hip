@@ -29,7 +29,37 @@ struct RasterK {
     float r_min;
     uint32_t T, ntx, nty, n_tiles;
     uint32_t chunk, K;
+    uint32_t views;     // 0: scene s draws stream range scene_off[s..s+1];
+                        // 1: every scene (view) draws the whole stream
 };
+
+// Segment space.  A unit u names (scene, stream control point v); screen
+// records, bin entries and long-list entries are indexed by u, keys carry v.
+//   views == 0: u = v, scene from the scene offsets;
+//   views == 1: u = s * n + v over S views of one stream of n points.
+__device__ __forceinline__ uint32_t stream_len(const uint32_t *scene_off, const RasterK &rk,
+                                               uint32_t cap)
+{
+    const uint32_t total = rk.views ? scene_off[1] : scene_off[rk.S];
+    return total < cap ? total : cap;
+}
+
+__device__ __forceinline__ uint32_t unit_count(uint32_t n, const RasterK &rk)
+{
+    return rk.views ? n * rk.S : n;
+}
+
+__device__ __forceinline__ void unit_map(const uint32_t *scene_off, const RasterK &rk, uint32_t n,
+                                         uint32_t u, uint32_t &s, uint32_t &v)
+{
+    if (rk.views) {
+        s = u / n;
+        v = u - s * n;
+    } else {
+        v = u;
+        s = scene_of(scene_off, rk.S, u);
+    }
+}
 
 // ------------------------------------------------------------------ prefill
 __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *scene_z,
@@ -59,15 +89,17 @@ __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *sce
 
 // ------------------------------------------------------------------ projection
 __global__ __launch_bounds__(256) void k_project(const float4 *pos_w, const uint32_t *scene_off,
-                                                 uint32_t S, const hm_camera *cams, uint32_t cap,
+                                                 RasterK rk, const hm_camera *cams, uint32_t cap,
                                                  float4 *proj)
 {
-    const uint32_t total = scene_off[S];
-    const uint32_t n = total < cap ? total : cap;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
-        const uint32_t s = scene_of(scene_off, S, c);
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    const uint32_t nu = unit_count(n, rk);
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nu;
+         u += gridDim.x * blockDim.x) {
+        uint32_t s, v;
+        unit_map(scene_off, rk, n, u, s, v);
         const Cam cam = load_cam(cams + s);
-        proj[c] = project(cam, pos_w[c]);
+        proj[u] = project(cam, pos_w[v]);
     }
 }
 
@@ -114,11 +146,13 @@ __device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
     i1 = fhi < 1.0e9f ? (int)floorf(fhi) : 1000000000;
 }
 
-__device__ __forceinline__ bool load_seg(const float4 *proj, const uint8_t *flags, uint32_t v,
-                                         uint32_t n_cp, float r_min, Seg &sg)
+// Segment of unit u (stream point v): v must not be a tip; both screen
+// records must be inside the depth range.
+__device__ __forceinline__ bool load_seg(const float4 *proj, const uint8_t *flags, uint32_t u,
+                                         uint32_t v, uint32_t n_cp, float r_min, Seg &sg)
 {
     if (v + 1 >= n_cp || (flags[v] & HM_TIP)) return false;
-    const float4 a = proj[v], b = proj[v + 1];
+    const float4 a = proj[u], b = proj[u + 1];
     if (a.w == 0.0f || b.w == 0.0f) return false;
     sg = make_seg(a, b, r_min);
     return true;
@@ -137,15 +171,17 @@ __global__ __launch_bounds__(256) void k_raster_direct(const float4 *proj, const
                                                        const hm_camera *cams, RasterK rk,
                                                        uint32_t cap, uint64_t *vis)
 {
-    const uint32_t total = scene_off[rk.S];
-    const uint32_t n = total < cap ? total : cap;
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    const uint32_t nu = unit_count(n, rk);
     const size_t hw = (size_t)rk.W * rk.H;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < nu;
+         u += gridDim.x * blockDim.x) {
+        uint32_t s, v;
+        unit_map(scene_off, rk, n, u, s, v);
         Seg sg;
-        if (!load_seg(proj, flags, v, n, rk.r_min, sg)) continue;
+        if (!load_seg(proj, flags, u, v, n, rk.r_min, sg)) continue;
         int i0, i1, j0, j1;
         if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
-        const uint32_t s = scene_of(scene_off, rk.S, v);
         float zn, inv_range;
         scene_depth_consts(cams, s, zn, inv_range);
         uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
@@ -194,14 +230,16 @@ struct SegTiles {
 };
 
 __device__ __forceinline__ bool seg_tiles(const float4 *proj, const uint8_t *flags,
-                                          const uint32_t *scene_off, const RasterK &rk, uint32_t v,
+                                          const uint32_t *scene_off, const RasterK &rk, uint32_t u,
                                           uint32_t n, SegTiles &st)
 {
     st.nt = 0;
-    if (v >= n || !load_seg(proj, flags, v, n, rk.r_min, st.sg)) return false;
+    if (u >= unit_count(n, rk)) return false;
+    uint32_t v;
+    unit_map(scene_off, rk, n, u, st.s, v);
+    if (!load_seg(proj, flags, u, v, n, rk.r_min, st.sg)) return false;
     int i0, i1, j0, j1;
     if (!seg_box(st.sg, rk.W, rk.H, i0, i1, j0, j1)) return false;
-    st.s = scene_of(scene_off, rk.S, v);
     st.tx0 = (uint32_t)i0 / rk.T;
     st.ty0 = (uint32_t)j0 / rk.T;
     st.bw = (uint32_t)i1 / rk.T - st.tx0 + 1;
@@ -250,9 +288,10 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
                                              uint32_t *long_list, uint32_t *counters)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
-    const uint32_t total = scene_off[rk.S];
-    const uint32_t n = total < cap ? total : cap;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    const uint32_t nu = unit_count(n, rk);
+    // v below is a segment unit (see unit_map); lists store units
+    for (uint32_t base = blockIdx.x * blockDim.x; base < nu; base += gridDim.x * blockDim.x) {
         for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
             keys[x] = BIN_FREE;
             cnt[x] = 0;
@@ -339,8 +378,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
     __shared__ uint32_t sh_scan[1024 / 64 + 1];
     const uint32_t TT = rk.T * rk.T;
     uint64_t *lc = lds, *la = lds + TT;
-    const uint32_t total = scene_off[rk.S];
-    const uint32_t n = total < cap ? total : cap;
+    const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_items = item_off[rk.n_tiles];
     const size_t hw = (size_t)rk.W * rk.H;
     const uint32_t tiles_per_scene = rk.ntx * rk.nty;
@@ -395,10 +433,12 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             uint32_t nr = 0, v = 0;
             int jr0 = 0;
             if (e < end) {
-                v = entries[e];
+                v = entries[e];                      // segment unit
+                uint32_t sv, vv;
+                unit_map(scene_off, rk, n, v, sv, vv);
                 Seg sg;
                 int i0, i1, j0, j1;
-                if (load_seg(proj, flags, v, n, rk.r_min, sg) &&
+                if (load_seg(proj, flags, v, vv, n, rk.r_min, sg) &&
                     seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
                     j0 = max(j0, py0);
                     j1 = min(j1, py1);
@@ -421,8 +461,10 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     const uint32_t mid = (lo + hi) >> 1;
                     if (sh_pre[mid] <= rr) lo = mid; else hi = mid;
                 }
-                const uint32_t vo = sh_v[lo];
-                const Seg sg = make_seg(proj[vo], proj[vo + 1], rk.r_min);
+                const uint32_t uo = sh_v[lo];
+                uint32_t so, vo;
+                unit_map(scene_off, rk, n, uo, so, vo);
+                const Seg sg = make_seg(proj[uo], proj[uo + 1], rk.r_min);
                 int i0, i1, j0, j1;
                 seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
                 i0 = max(i0, px0);
@@ -468,20 +510,20 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
                                                      uint32_t cap, const uint32_t *long_list,
                                                      const uint32_t *counters, uint64_t *vis)
 {
-    const uint32_t total = scene_off[rk.S];
-    const uint32_t n = total < cap ? total : cap;
+    const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_long = counters[0];
     const uint32_t waves = gridDim.x * (blockDim.x >> 6);
     const uint32_t wid = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int lane = lane_id();
     const size_t hw = (size_t)rk.W * rk.H;
     for (uint32_t e = wid; e < n_long; e += waves) {
-        const uint32_t v = long_list[e];
+        const uint32_t u = long_list[e];
+        uint32_t s, v;
+        unit_map(scene_off, rk, n, u, s, v);
         Seg sg;
-        if (!load_seg(proj, flags, v, n, rk.r_min, sg)) continue;
+        if (!load_seg(proj, flags, u, v, n, rk.r_min, sg)) continue;
         int i0, i1, j0, j1;
         if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
-        const uint32_t s = scene_of(scene_off, rk.S, v);
         float zn, inv_range;
         scene_depth_consts(cams, s, zn, inv_range);
         uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
@@ -517,7 +559,14 @@ static RasterK make_rk(const hm_frame &f, const hm_raster_params &p)
     rk.n_tiles = rk.ntx * rk.nty * f.n_scenes;
     rk.chunk = p.chunk;
     rk.K = p.max_tiles_per_seg;
+    rk.views = p.shared_views ? 1u : 0u;
     return rk;
+}
+
+// segment units per stream control point: one, or one per view
+static size_t units_per_cp(const hm_frame &f, const hm_raster_params &p)
+{
+    return p.shared_views ? (size_t)f.n_scenes : 1u;
 }
 
 struct RasterWs {
@@ -540,15 +589,16 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
     size_t o = 0;
     RasterWs w;
     auto take = [&](size_t bytes) { char *r = b ? b + o : nullptr; o += align_up(bytes); return r; };
-    w.proj = (float4 *)take(sizeof(float4) * (size_t)cap);
+    const size_t units = (size_t)cap * units_per_cp(f, p);
+    w.proj = (float4 *)take(sizeof(float4) * units);
     w.tile_cnt = (uint32_t *)take(sizeof(uint32_t) * (nt + 1));
     w.tile_cur = (uint32_t *)take(sizeof(uint32_t) * nt);
     w.items = (uint32_t *)take(sizeof(uint32_t) * (nt + 1));
     w.partials = (uint32_t *)take(sizeof(uint32_t) * (scan_blocks((uint32_t)nt) + 1));
     w.counters = (uint32_t *)take(sizeof(uint32_t) * 64);
     if (p.algo == HM_RASTER_TILED) {
-        w.long_list = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap);
-        w.entries = (uint32_t *)take(sizeof(uint32_t) * (size_t)cap * p.max_tiles_per_seg);
+        w.long_list = (uint32_t *)take(sizeof(uint32_t) * units);
+        w.entries = (uint32_t *)take(sizeof(uint32_t) * units * p.max_tiles_per_seg);
     } else {
         w.long_list = nullptr;
         w.entries = nullptr;
@@ -572,6 +622,7 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.max_tiles_per_seg = 4;
     p.block = 256;
     p.grid = 0;
+    p.shared_views = 0;
 }
 
 void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,
@@ -584,10 +635,11 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
                        cams, f.n_scenes, f.width, f.height);
     const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
-    hipLaunchKernelGGL(k_project, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st, pos,
-                       s.scene_off, s.n_scenes, cams, s.cap, w.proj);
+    const size_t units = (size_t)s.cap * units_per_cp(f, p);
+    hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
+                       s.scene_off, rk, cams, s.cap, w.proj);
     if (p.algo == HM_RASTER_DIRECT) {
-        hipLaunchKernelGGL(k_raster_direct, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_raster_direct, dim3(stride_grid(units, 256)), dim3(256), 0, st,
                            (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
                            rk, s.cap, vis);
         return;
@@ -596,7 +648,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     hipLaunchKernelGGL(k_fill_u32, dim3(stride_grid(nt + 1, 256)), dim3(256), 0, st, w.tile_cnt,
                        nt + 1, 0u);
     hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, w.counters, 64u, 0u);
-    const uint32_t gb = stride_grid(s.cap, 256);
+    const uint32_t gb = stride_grid(units, 256);
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 0, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);

@@ -56,7 +56,8 @@ class GenParams(ctypes.Structure):
 
 class RasterParams(ctypes.Structure):
     _fields_ = [("r_min", _f32), ("algo", _i32), ("tile", _u32), ("chunk", _u32),
-                ("max_tiles_per_seg", _u32), ("block", _u32), ("grid", _u32)]
+                ("max_tiles_per_seg", _u32), ("block", _u32), ("grid", _u32),
+                ("shared_views", _u32)]
 
 
 class ShadeParams(ctypes.Structure):

@@ -80,6 +80,22 @@ def test_tiny_vis_invariant_to_launch_shape(O, torch, algo, tile, chunk, K, bloc
     assert np.array_equal(ds.host_vis(), ref["vis"])
 
 
+def test_every_autotune_candidate_gives_the_same_buffer(O, torch):
+    from paper_2607_04230_amd import autotune
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_head(width=480, height=270, strands_per_quad=8)
+    ref = O.render(sc, want=("vis",))
+    ds = DeviceScene(sc)
+    ds.lod()
+    ds.generate()
+    for c in autotune.DEFAULT_CANDIDATES:
+        ds.set_raster_params(autotune.params_of(c, sc.r_min))
+        ds.vis.fill_(0)
+        ds.raster()
+        torch.cuda.synchronize()
+        assert np.array_equal(ds.host_vis(), ref["vis"]), c
+
+
 @pytest.mark.parametrize("seed", range(6))
 @pytest.mark.parametrize("r_min", [0.0, 0.5, 1.5])
 def test_micro_scenes_brute_force(O, torch, seed, r_min):

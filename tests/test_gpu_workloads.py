@@ -144,3 +144,39 @@ def test_graph_replays_match_eager(torch):
             x = torch.randn(1000, device="cuda").sum()          # eager work in between
             torch.cuda.synchronize()
     g.close()
+
+
+def test_multiview_one_stream_many_views(O, torch):
+    """Strands assembled once, projected into several views (stereo pair plus a
+    side view): each view equals the oracle's single-view render of the same
+    stream."""
+    from paper_2607_04230_amd.render import DeviceScene
+    base = scenes.config_head(width=640, height=360, strands_per_quad=16, occluder=False)
+    views = np.stack([base.cams[0],
+                      scenes.look_at_camera((0.065, 0.4, 4.0), (0.0, 0.4, 0.0), 640, 360)[0],
+                      scenes.look_at_camera((3.0, 1.2, 2.5), (0.0, 0.4, 0.0), 640, 360)[0]])
+    ds = DeviceScene(base)
+    ds.lod()
+    ds.generate()
+    rp = hm.raster_defaults(hm.frame(3, 640, 360))
+    rp.shared_views = 1
+    fr = hm.frame(3, 640, 360)
+    cams = torch.from_numpy(views.copy()).cuda()
+    vis = torch.empty((3, 2, 360, 640), dtype=torch.int64, device="cuda")
+    ws = torch.empty(hm.workspace_size(hm.CALL_RASTER, fr, cap=ds.cap, rparams=rp),
+                     dtype=torch.uint8, device="cuda")
+    hm.raster_vis(ds.st, cams, fr, rp, None, vis, ws)
+    out = torch.empty((3, 360, 640, 4), dtype=torch.float32, device="cuda")
+    wsr = torch.empty(hm.workspace_size(hm.CALL_RESOLVE, fr), dtype=torch.uint8, device="cuda")
+    hm.resolve_shade(ds.st, vis, cams, fr, ds.sp, out, wsr)
+    torch.cuda.synchronize()
+    pos, rgb, fl = ds.host_stream()
+    soff = np.array([0, pos.shape[0]], np.uint32)
+    gvis = vis.cpu().numpy().view(np.uint64)
+    gout = out.cpu().numpy().astype(np.float64)
+    rp_ = ResolveParams()
+    for v in range(3):
+        ref = O.raster(pos, fl, soff, views[v:v + 1], 640, 360, 0.0)
+        assert np.array_equal(gvis[v], ref[0]), v
+        o = O.resolve(pos, rgb, fl, ref, views[v:v + 1], 640, 360, rp_, base.mode, base.bg)
+        assert np.abs(gout[v] - o[0]).max() <= TOL, v
