@@ -153,8 +153,8 @@ def test_multiview_one_stream_many_views(O, torch):
     from paper_2607_04230_amd.render import DeviceScene
     base = scenes.config_head(width=640, height=360, strands_per_quad=16, occluder=False)
     views = np.stack([base.cams[0],
-                      scenes.look_at_camera((0.065, 0.4, 4.0), (0.0, 0.4, 0.0), 640, 360)[0],
-                      scenes.look_at_camera((3.0, 1.2, 2.5), (0.0, 0.4, 0.0), 640, 360)[0]])
+                      scenes.look_at_camera((0.065, 0.4, 4.0), (0.0, 0.4, 0.0), 640, 360),
+                      scenes.look_at_camera((3.0, 1.2, 2.5), (0.0, 0.4, 0.0), 640, 360)])
     ds = DeviceScene(base)
     ds.lod()
     ds.generate()
