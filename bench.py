@@ -265,6 +265,11 @@ def main():
         return
     print(f"[bench] workload built: {sc.n_full_strands} strands, {sc.n_seg_full} segments, "
           f"{sc.width}x{sc.height}", file=sys.stderr, flush=True)
+    from paper_2607_04230_amd import autotune
+    ds.render()
+    tuned, _ = autotune.tune(ds, autotune.QUICK_CANDIDATES, reps=3)
+    print(f"[bench] raster launch shape: tile {tuned.tile}, chunk {tuned.chunk}, block "
+          f"{tuned.block}, K {tuned.max_tiles_per_seg}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ds.render()
     torch.cuda.synchronize()
@@ -322,6 +327,8 @@ def main():
         "raster_segments_per_s": n_seg / (raster_ms * 1e-3) if raster_ms > 0 else None,
         "kernels": per_kernel,
         "hair_pixels": hair_px,
+        "raster_params": {"algo": tuned.algo, "tile": tuned.tile, "chunk": tuned.chunk,
+                          "block": tuned.block, "max_tiles_per_seg": tuned.max_tiles_per_seg},
     }
     if not args.no_extras:
         del ds

@@ -104,6 +104,7 @@ struct Seg {
     float dx, dy, dw, diz;
     float len2, ilen2, ra;
     float sxmn, sxmx, symn, symx;
+    float idy;              // 1/dy for candidate enumeration (0 when |dy| <= 1e-3)
 };
 
 __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
@@ -120,6 +121,7 @@ __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
     s.ra = fmaxx(ra, r_min);
     s.sxmn = fminx(a.x, b.x); s.sxmx = fmaxx(a.x, b.x);
     s.symn = fminx(a.y, b.y); s.symx = fmaxx(a.y, b.y);
+    s.idy = fabsf(s.dy) > 1e-3f ? 1.0f / s.dy : 0.0f;
     return s;
 }
 

@@ -130,8 +130,8 @@ __device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
     const float e = 0.05f;
     const float ylo = ((float)j - sg.ra) - e, yhi = (((float)j + 1.0f) + sg.ra) + e;
     float xlo = sg.sxmn, xhi = sg.sxmx;
-    if (fabsf(sg.dy) > 1e-3f) {
-        float ta = (ylo - sg.y0) / sg.dy, tb = (yhi - sg.y0) / sg.dy;
+    if (sg.idy != 0.0f) {
+        float ta = (ylo - sg.y0) * sg.idy, tb = (yhi - sg.y0) * sg.idy;
         float t0 = fmaxx(fminx(ta, tb), 0.0f), t1 = fminx(fmaxx(ta, tb), 1.0f);
         if (t0 > t1) { i0 = 1; i1 = 0; return; }
         float xa = sg.x0 + t0 * sg.dx, xb = sg.x0 + t1 * sg.dx;
@@ -454,21 +454,35 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             sh_v[threadIdx.x] = v;
             sh_j0[threadIdx.x] = jr0;
             __syncthreads();
-            for (uint32_t rr = threadIdx.x; rr < tot; rr += blockDim.x) {
-                // owner: last lane whose first row slot is <= rr
-                uint32_t lo = 0, hi = blockDim.x;
+            // each lane takes a contiguous run of row slots; consecutive slots
+            // mostly belong to the same segment, whose record stays in registers
+            const uint32_t per = (tot + blockDim.x - 1) / blockDim.x;
+            const uint32_t r_beg = threadIdx.x * per;
+            const uint32_t r_end = min(r_beg + per, tot);
+            uint32_t lo = 0;
+            if (r_beg < r_end) {            // owner of the first slot: binary search
+                uint32_t hi = blockDim.x;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
-                    if (sh_pre[mid] <= rr) lo = mid; else hi = mid;
+                    if (sh_pre[mid] <= r_beg) lo = mid; else hi = mid;
                 }
-                const uint32_t uo = sh_v[lo];
-                uint32_t so, vo;
-                unit_map(scene_off, rk, n, uo, so, vo);
-                const Seg sg = make_seg(proj[uo], proj[uo + 1], rk.r_min);
-                int i0, i1, j0, j1;
-                seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
-                i0 = max(i0, px0);
-                i1 = min(i1, px1);
+            }
+            uint32_t cur = 0xFFFFFFFFu, vo = 0;
+            Seg sg;
+            int i0 = 0, i1 = -1;
+            for (uint32_t rr = r_beg; rr < r_end; ++rr) {
+                while (lo + 1 < blockDim.x && sh_pre[lo + 1] <= rr) ++lo;
+                if (lo != cur) {
+                    cur = lo;
+                    const uint32_t uo = sh_v[lo];
+                    uint32_t so;
+                    unit_map(scene_off, rk, n, uo, so, vo);
+                    sg = make_seg(proj[uo], proj[uo + 1], rk.r_min);
+                    int j0, j1;
+                    seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
+                    i0 = max(i0, px0);
+                    i1 = min(i1, px1);
+                }
                 const int j = sh_j0[lo] + (int)(rr - sh_pre[lo]);
                 int a0, a1;
                 row_span(sg, j, a0, a1);
@@ -618,9 +632,9 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.r_min = 0.0f;
     p.algo = HM_RASTER_TILED;
     p.tile = 32;
-    p.chunk = 8192;
+    p.chunk = 512;
     p.max_tiles_per_seg = 4;
-    p.block = 256;
+    p.block = 512;
     p.grid = 0;
     p.shared_views = 0;
 }
