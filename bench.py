@@ -274,18 +274,33 @@ def main():
         ds.render()
     torch.cuda.synchronize()
 
-    hm.timing_enable(True)
+    def timed(fn, stream):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
     stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ds.render()
-    e1.record(stream)
-    torch.cuda.synchronize()
+    # (a) eager frames, no instrumentation
+    ms_eager = timed(ds.render, stream)
+    # (b) eager frames with every library kernel bracketed by HIP events on the
+    #     launch stream: per-kernel durations over this timed region
+    hm.timing_enable(True)
+    ms_instr = timed(ds.render, stream)
     hm.timing_enable(False)
     kt = hm.timing_collect()
-    ms = e0.elapsed_time(e1) / args.steps
+    # (c) the same frame captured once as a HIP graph and replayed
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        graph = ds.capture_graph()
+        graph.launch()
+        ms_graph = timed(graph.launch, side)
+        graph.close()
+    ms = min(ms_eager, ms_graph)
     tot = ds.totals.cpu().numpy()
     n_strands, n_cp = int(tot[0]), int(tot[1])
     n_seg = n_cp - n_strands
@@ -313,6 +328,10 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "frame_mode": "hip_graph_replay" if ms_graph <= ms_eager else "eager",
+        "ms_per_step_eager": ms_eager,
+        "ms_per_step_graph": ms_graph,
+        "ms_per_step_instrumented": ms_instr,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

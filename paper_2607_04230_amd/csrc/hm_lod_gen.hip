@@ -29,12 +29,11 @@ __device__ __forceinline__ void lod_counts(float L, uint32_t N, float delta, uin
     cps = c > cmax ? cmax : c;
 }
 
-__global__ __launch_bounds__(256) void k_lod(hm_hair_mesh m, const hm_camera *cams, uint32_t W,
-                                             uint32_t H, int mode, float lambda, uint32_t seed,
-                                             uint32_t *table, uint64_t *cnt_s, uint64_t *cnt_c)
+// Strand and control-point counts of bundle b (0 strands = culled).
+__device__ __forceinline__ void lod_entry(const hm_hair_mesh &m, const hm_camera *cams, uint32_t W,
+                                          uint32_t H, int mode, float lambda, uint32_t seed,
+                                          uint32_t b, uint32_t &n_out, uint32_t &cp_out)
 {
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= m.n_bundles) return;
     const uint32_t N = m.bundle_nstrands[b];
     const uint32_t cmax = m.bundle_cmax[b] < 2u ? 2u : m.bundle_cmax[b];   // C >= 2 always
     uint32_t n = N, cp = cmax;
@@ -83,10 +82,67 @@ __global__ __launch_bounds__(256) void k_lod(hm_hair_mesh m, const hm_camera *ca
         }
     }
     if (n == 0) cp = 0;
+    n_out = n;
+    cp_out = cp;
+}
+
+__global__ __launch_bounds__(256) void k_lod(hm_hair_mesh m, const hm_camera *cams, uint32_t W,
+                                             uint32_t H, int mode, float lambda, uint32_t seed,
+                                             uint32_t *table, uint64_t *cnt_s, uint64_t *cnt_c)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= m.n_bundles) return;
+    uint32_t n, cp;
+    lod_entry(m, cams, W, H, mode, lambda, seed, b, n, cp);
     table[4 * (size_t)b + 0] = n;
     table[4 * (size_t)b + 1] = cp;
     cnt_s[b] = n;
     cnt_c[b] = (uint64_t)n * cp;
+}
+
+// Whole LOD pass in one workgroup (meshes of up to LOD_SMALL bundles): counts,
+// both exclusive prefix sums, scene offsets and totals in a single launch.
+constexpr uint32_t LOD_SMALL = 8192;
+
+__global__ __launch_bounds__(1024) void k_lod_small(hm_hair_mesh m, const hm_camera *cams,
+                                                    uint32_t W, uint32_t H, int mode, float lambda,
+                                                    uint32_t seed, uint32_t S, uint32_t *table,
+                                                    uint32_t *scene_off, uint64_t *totals)
+{
+    __shared__ uint64_t lds_s[1024 / 64 + 1], lds_c[1024 / 64 + 1];
+    const uint32_t B = m.n_bundles;
+    const uint64_t lim = 0xFFFFFFFFull;
+    uint64_t carry_s = 0, carry_c = 0;
+    for (uint32_t base = 0; base < B; base += blockDim.x) {
+        const uint32_t b = base + threadIdx.x;
+        uint32_t n = 0, cp = 0;
+        if (b < B) lod_entry(m, cams, W, H, mode, lambda, seed, b, n, cp);
+        uint64_t ts, tc;
+        const uint64_t os = block_exclusive_scan<uint64_t>(n, lds_s, ts) + carry_s;
+        const uint64_t oc = block_exclusive_scan<uint64_t>((uint64_t)n * cp, lds_c, tc) + carry_c;
+        if (b < B) {
+            table[4 * (size_t)b + 0] = n;
+            table[4 * (size_t)b + 1] = cp;
+            table[4 * (size_t)b + 2] = (uint32_t)(os < lim ? os : lim);
+            table[4 * (size_t)b + 3] = (uint32_t)(oc < lim ? oc : lim);
+        }
+        carry_s += ts;
+        carry_c += tc;
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t <= S; t += blockDim.x) {
+        uint32_t lo = 0, hi = B;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (m.bundle_scene[mid] < t) lo = mid + 1; else hi = mid;
+        }
+        const uint64_t o = lo < B ? (uint64_t)table[4 * (size_t)lo + 3] : carry_c;
+        scene_off[t] = (uint32_t)(o < lim ? o : lim);
+    }
+    if (threadIdx.x == 0) {
+        totals[0] = carry_s;
+        totals[1] = carry_c;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_lod_finish(uint32_t *table, const uint64_t *off_s,
@@ -127,6 +183,11 @@ void launch_lod(const hm_hair_mesh &m, const hm_camera *cams, const hm_frame &f,
                 void *ws, hipStream_t st)
 {
     const uint32_t B = m.n_bundles;
+    if (B <= LOD_SMALL) {
+        hipLaunchKernelGGL(k_lod_small, dim3(1), dim3(1024), 0, st, m, cams, f.width, f.height,
+                           (int)p.mode, p.lambda, p.seed, f.n_scenes, table, scene_off, totals);
+        return;
+    }
     char *w = (char *)ws;
     uint64_t *cs = (uint64_t *)w;
     w += align_up(sizeof(uint64_t) * ((size_t)B + 1));

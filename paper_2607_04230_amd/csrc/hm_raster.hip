@@ -64,8 +64,15 @@ __device__ __forceinline__ void unit_map(const uint32_t *scene_off, const Raster
 // ------------------------------------------------------------------ prefill
 __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *scene_z,
                                                  const hm_camera *cams, uint32_t S, uint32_t W,
-                                                 uint32_t H)
+                                                 uint32_t H, uint32_t *clr0, uint32_t n0,
+                                                 uint32_t *clr1, uint32_t n1)
 {
+    // also zero the binning counters of this call (saves separate fill launches)
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n0 || i < n1;
+         i += gridDim.x * blockDim.x) {
+        if (i < n0) clr0[i] = 0u;
+        if (i < n1) clr1[i] = 0u;
+    }
     const size_t hw = (size_t)W * H;
     const size_t n = hw * S;
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
@@ -358,6 +365,38 @@ __global__ __launch_bounds__(256) void k_tile_items(const uint32_t *tile_off, ui
     tile_cur[t] = 0;
 }
 
+// Frames with few tiles: one workgroup turns the tile counts into list offsets
+// (in place, total at [nt]), computes the work items of each tile and their
+// offsets (total at [nt]) and resets the scatter cursors.
+constexpr uint32_t PLAN_SMALL = 8192;
+
+__global__ __launch_bounds__(1024) void k_plan_small(uint32_t *tile_cnt, uint32_t nt,
+                                                     uint32_t chunk, uint32_t *items,
+                                                     uint32_t *tile_cur)
+{
+    __shared__ uint32_t l1[1024 / 64 + 1], l2[1024 / 64 + 1];
+    uint32_t cs = 0, ci = 0;
+    for (uint32_t base = 0; base < nt; base += blockDim.x) {
+        const uint32_t t = base + threadIdx.x;
+        const uint32_t c = t < nt ? tile_cnt[t] : 0u;
+        const uint32_t it = (c + chunk - 1) / chunk;
+        uint32_t s1, s2;
+        const uint32_t o1 = block_exclusive_scan<uint32_t>(c, l1, s1) + cs;
+        const uint32_t o2 = block_exclusive_scan<uint32_t>(it, l2, s2) + ci;
+        if (t < nt) {
+            tile_cnt[t] = o1;
+            items[t] = o2;
+            tile_cur[t] = 0u;
+        }
+        cs += s1;
+        ci += s2;
+    }
+    if (threadIdx.x == 0) {
+        tile_cnt[nt] = cs;
+        items[nt] = ci;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint32_t val)
 {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
@@ -646,8 +685,10 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     const RasterK rk = make_rk(f, p);
     RasterWs w = carve(ws, f, s.cap, p);
     const size_t npix = (size_t)f.width * f.height * f.n_scenes;
+    const bool tiled = p.algo == HM_RASTER_TILED;
     hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
-                       cams, f.n_scenes, f.width, f.height);
+                       cams, f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
+                       tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
     const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
     const size_t units = (size_t)s.cap * units_per_cp(f, p);
     hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
@@ -659,21 +700,24 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         return;
     }
     const uint32_t nt = rk.n_tiles;
-    hipLaunchKernelGGL(k_fill_u32, dim3(stride_grid(nt + 1, 256)), dim3(256), 0, st, w.tile_cnt,
-                       nt + 1, 0u);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, w.counters, 64u, 0u);
     const uint32_t gb = stride_grid(units, 256);
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 0, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);
-    scan_exclusive<uint32_t>(w.tile_cnt, w.tile_cnt, nt, w.partials, st);
-    hipLaunchKernelGGL(k_tile_items, dim3((nt + 255) / 256), dim3(256), 0, st,
-                       (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
+    const bool small = nt <= PLAN_SMALL;
+    if (small) {
+        hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), 0, st, w.tile_cnt, nt, rk.chunk,
+                           w.items, w.tile_cur);
+    } else {
+        scan_exclusive<uint32_t>(w.tile_cnt, w.tile_cnt, nt, w.partials, st);
+        hipLaunchKernelGGL(k_tile_items, dim3((nt + 255) / 256), dim3(256), 0, st,
+                           (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
+    }
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 1, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
                        w.counters);
-    scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
+    if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
     const uint32_t lds = 2u * p.tile * p.tile * (uint32_t)sizeof(uint64_t);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
     hipLaunchKernelGGL(k_raster_tiles, dim3(grid), dim3(p.block), lds, st,
