@@ -137,6 +137,9 @@ static hm_status check_raster_params(const hm_raster_params *p)
             "block must be a multiple of 64 in [64, 1024]");
     REQUIRE(p->grid <= 65536, HM_ERR_RANGE, "grid outside [0, 65536]");
     REQUIRE(p->shared_views <= 1, HM_ERR_INVALID, "shared_views must be 0 or 1");
+    REQUIRE(p->algo != HM_RASTER_TILED || raster_lds_bytes(*p) <= 65536u, HM_ERR_RANGE,
+            "tile %u with %u threads needs %u B of LDS (limit 65536)", p->tile, p->block,
+            raster_lds_bytes(*p));
     REQUIRE(isfinite(p->r_min) && p->r_min >= 0.0f && p->r_min <= 64.0f, HM_ERR_RANGE,
             "r_min outside [0, 64]");
     return HM_OK;

@@ -39,6 +39,7 @@ void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_
 
 // rasterization
 size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p);
+uint32_t raster_lds_bytes(const hm_raster_params &p);   // dynamic LDS of the tile kernel
 void raster_defaults(const hm_frame &f, hm_raster_params &p);
 void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,
                    const hm_raster_params &p, const float *scene_z, uint64_t *vis, void *ws,

@@ -404,19 +404,53 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint3
 }
 
 // ------------------------------------------------------------------ tiled raster
+constexpr uint32_t SEG_FIELDS = 16;
+
+__device__ __forceinline__ void seg_store(float *sf, uint32_t nb, uint32_t k, const Seg &s)
+{
+    const float f[SEG_FIELDS] = {s.x0, s.y0, s.w0, s.iz0, s.dx, s.dy, s.dw, s.diz,
+                                 s.len2, s.ilen2, s.ra, s.sxmn, s.sxmx, s.symn, s.symx, s.idy};
+#pragma unroll
+    for (uint32_t i = 0; i < SEG_FIELDS; ++i) sf[i * nb + k] = f[i];
+}
+
+__device__ __forceinline__ Seg seg_load(const float *sf, uint32_t nb, uint32_t k)
+{
+    Seg s;
+    s.x0 = sf[0 * nb + k]; s.y0 = sf[1 * nb + k]; s.w0 = sf[2 * nb + k]; s.iz0 = sf[3 * nb + k];
+    s.dx = sf[4 * nb + k]; s.dy = sf[5 * nb + k]; s.dw = sf[6 * nb + k]; s.diz = sf[7 * nb + k];
+    s.len2 = sf[8 * nb + k]; s.ilen2 = sf[9 * nb + k]; s.ra = sf[10 * nb + k];
+    s.sxmn = sf[11 * nb + k]; s.sxmx = sf[12 * nb + k]; s.symn = sf[13 * nb + k];
+    s.symx = sf[14 * nb + k]; s.idy = sf[15 * nb + k];
+    return s;
+}
+
+// dynamic LDS bytes of k_raster_tiles for tile edge T and `block` threads
+static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block)
+{
+    return 2u * T * T * 8u + block * 4u * (SEG_FIELDS + 5u);
+}
 // Dynamic LDS: two layers of T*T keys.  Work items are pulled from counters[1].
 __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
                                uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
                                const uint32_t *entries, uint32_t *counters, uint64_t *vis)
 {
+    // dynamic LDS: the tile's two layers, then per-lane segment records
+    // (struct of arrays: SEG_FIELDS floats, stream id, first row, columns,
+    // row-slot prefix), nb = blockDim entries each
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t sh_item;
-    __shared__ uint32_t sh_pre[1024], sh_v[1024];
-    __shared__ int sh_j0[1024];
     __shared__ uint32_t sh_scan[1024 / 64 + 1];
     const uint32_t TT = rk.T * rk.T;
+    const uint32_t nb = blockDim.x;
     uint64_t *lc = lds, *la = lds + TT;
+    float *sf = reinterpret_cast<float *>(lds + 2 * TT);
+    uint32_t *sv = reinterpret_cast<uint32_t *>(sf + SEG_FIELDS * nb);
+    int *sj0 = reinterpret_cast<int *>(sv + nb);
+    int *si0 = sj0 + nb;
+    int *si1 = si0 + nb;
+    uint32_t *spre = reinterpret_cast<uint32_t *>(si1 + nb);
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_items = item_off[rk.n_tiles];
     const size_t hw = (size_t)rk.W * rk.H;
@@ -464,37 +498,40 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             __syncthreads();
         }
 
-        // Batches of blockDim segments; their (segment, row) pairs are spread
-        // evenly over the workgroup by a prefix scan of the row counts, so a
-        // long segment does not hold up the lanes that drew short ones.
+        // Batches of blockDim segments.  Each lane builds its segment's record
+        // once (screen geometry, clipped columns, first row, stream id) into
+        // LDS; a prefix scan of the row counts then spreads the (segment, row)
+        // pairs evenly, each lane taking a contiguous run of row slots and
+        // reading the owning segment's record from LDS.
         for (uint32_t e0 = beg; e0 < end; e0 += blockDim.x) {
             const uint32_t e = e0 + threadIdx.x;
-            uint32_t nr = 0, v = 0;
-            int jr0 = 0;
+            uint32_t nr = 0;
             if (e < end) {
-                v = entries[e];                      // segment unit
-                uint32_t sv, vv;
-                unit_map(scene_off, rk, n, v, sv, vv);
+                const uint32_t u = entries[e];                  // segment unit
+                uint32_t su, vu;
+                unit_map(scene_off, rk, n, u, su, vu);
                 Seg sg;
                 int i0, i1, j0, j1;
-                if (load_seg(proj, flags, v, vv, n, rk.r_min, sg) &&
+                if (load_seg(proj, flags, u, vu, n, rk.r_min, sg) &&
                     seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
                     j0 = max(j0, py0);
                     j1 = min(j1, py1);
-                    if (max(i0, px0) <= min(i1, px1) && j0 <= j1) {
+                    i0 = max(i0, px0);
+                    i1 = min(i1, px1);
+                    if (i0 <= i1 && j0 <= j1) {
                         nr = (uint32_t)(j1 - j0 + 1);
-                        jr0 = j0;
+                        seg_store(sf, nb, threadIdx.x, sg);
+                        sv[threadIdx.x] = vu;
+                        sj0[threadIdx.x] = j0;
+                        si0[threadIdx.x] = i0;
+                        si1[threadIdx.x] = i1;
                     }
                 }
             }
             uint32_t tot;
             const uint32_t pre = block_exclusive_scan(nr, sh_scan, tot);
-            sh_pre[threadIdx.x] = pre;
-            sh_v[threadIdx.x] = v;
-            sh_j0[threadIdx.x] = jr0;
+            spre[threadIdx.x] = pre;
             __syncthreads();
-            // each lane takes a contiguous run of row slots; consecutive slots
-            // mostly belong to the same segment, whose record stays in registers
             const uint32_t per = (tot + blockDim.x - 1) / blockDim.x;
             const uint32_t r_beg = threadIdx.x * per;
             const uint32_t r_end = min(r_beg + per, tot);
@@ -503,26 +540,25 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                 uint32_t hi = blockDim.x;
                 while (hi - lo > 1) {
                     const uint32_t mid = (lo + hi) >> 1;
-                    if (sh_pre[mid] <= r_beg) lo = mid; else hi = mid;
+                    if (spre[mid] <= r_beg) lo = mid; else hi = mid;
                 }
             }
             uint32_t cur = 0xFFFFFFFFu, vo = 0;
             Seg sg;
-            int i0 = 0, i1 = -1;
+            int i0 = 0, i1 = -1, jb = 0;
+            uint32_t pb = 0;
             for (uint32_t rr = r_beg; rr < r_end; ++rr) {
-                while (lo + 1 < blockDim.x && sh_pre[lo + 1] <= rr) ++lo;
+                while (lo + 1 < blockDim.x && spre[lo + 1] <= rr) ++lo;
                 if (lo != cur) {
                     cur = lo;
-                    const uint32_t uo = sh_v[lo];
-                    uint32_t so;
-                    unit_map(scene_off, rk, n, uo, so, vo);
-                    sg = make_seg(proj[uo], proj[uo + 1], rk.r_min);
-                    int j0, j1;
-                    seg_box(sg, rk.W, rk.H, i0, i1, j0, j1);
-                    i0 = max(i0, px0);
-                    i1 = min(i1, px1);
+                    sg = seg_load(sf, nb, lo);
+                    vo = sv[lo];
+                    jb = sj0[lo];
+                    i0 = si0[lo];
+                    i1 = si1[lo];
+                    pb = spre[lo];
                 }
-                const int j = sh_j0[lo] + (int)(rr - sh_pre[lo]);
+                const int j = jb + (int)(rr - pb);
                 int a0, a1;
                 row_span(sg, j, a0, a1);
                 a0 = max(a0, i0);
@@ -660,6 +696,8 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
     return w;
 }
 
+uint32_t raster_lds_bytes(const hm_raster_params &p) { return tile_lds_bytes(p.tile, p.block); }
+
 size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p)
 {
     return carve(nullptr, f, cap, p).bytes;
@@ -718,7 +756,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
                        w.counters);
     if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
-    const uint32_t lds = 2u * p.tile * p.tile * (uint32_t)sizeof(uint64_t);
+    const uint32_t lds = tile_lds_bytes(p.tile, p.block);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
     hipLaunchKernelGGL(k_raster_tiles, dim3(grid), dim3(p.block), lds, st,
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,
