@@ -125,6 +125,16 @@ hm_status hm_lod_select(const hm_hair_mesh *mesh, const hm_camera *cams, const h
                         const hm_lod_params *p, uint32_t *table, uint32_t *scene_off,
                         uint64_t *totals, void *ws, size_t ws_bytes, void *stream);
 
+/* Depth correction of Sec. 3.2.3: after stochastic strand removal the
+ * remaining fraction beta = N_LOD / N_b of a bundle attenuates like a medium
+ * of density sigma * beta (Beer-Lambert), which equals traversing the depth
+ * beta * d; expressed as an additive shift in log-depth space,
+ * delta = -log(beta).  Writes delta_out[b] (float, device) for every bundle:
+ * 0 when nothing was removed, +inf for culled bundles (beta = 0), and 0 for
+ * bundles with N_b = 0.  table: hm_lod_select's output. */
+hm_status hm_lod_depth_offset(const uint32_t *table, const uint32_t *bundle_nstrands,
+                              uint32_t n_bundles, float *delta_out, void *stream);
+
 /* ------------------------------------------------------------------ generation */
 typedef struct {
     uint32_t seed;        /* strand (u, v) and curl phase hash seed */

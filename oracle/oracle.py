@@ -162,6 +162,20 @@ def lod_select(sc, mode: Optional[int] = None):
     return table, soff, (int(tot[0]), int(tot[1]))
 
 
+def lod_depth_offset(table: np.ndarray, bundle_nstrands: np.ndarray) -> np.ndarray:
+    """Depth correction of the LOD (Sec. 3.2.3, Beer-Lambert): the fraction
+    beta = N_remaining / N_total of a bundle's strands survives, and
+    delta = -log(beta) (binary64); +inf when every strand was removed, 0 for an
+    empty bundle."""
+    n = table[:, 0].astype(np.float64)
+    N = np.asarray(bundle_nstrands, np.float64)
+    out = np.zeros(n.shape[0], np.float64)
+    for b in range(n.shape[0]):
+        if N[b] > 0:
+            out[b] = math.inf if n[b] == 0 else -math.log(n[b] / N[b])
+    return out
+
+
 def generate(sc, table: np.ndarray, n_cp: int):
     pos_w = np.zeros((max(n_cp, 1), 4), np.float32)
     rgb = np.zeros((max(n_cp, 1), 4), np.float32)

@@ -426,3 +426,12 @@ hm_status hm_graph_destroy(hm_graph g)
 }
 
 }  // extern "C"
+
+extern "C" hm_status hm_lod_depth_offset(const uint32_t *table, const uint32_t *bundle_nstrands,
+                                         uint32_t n_bundles, float *delta_out, void *stream)
+{
+    REQUIRE(table && bundle_nstrands && delta_out, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(n_bundles >= 1, HM_ERR_INVALID, "n_bundles must be >= 1");
+    hm::launch_lod_delta(table, bundle_nstrands, n_bundles, delta_out, (hipStream_t)stream);
+    return check_launch("hm_lod_depth_offset");
+}

@@ -33,6 +33,8 @@ void launch_lod(const hm_hair_mesh &m, const hm_camera *cams, const hm_frame &f,
                 const hm_lod_params &p, uint32_t *table, uint32_t *scene_off, uint64_t *totals,
                 void *ws, hipStream_t st);
 size_t lod_workspace(uint32_t n_bundles);
+void launch_lod_delta(const uint32_t *table, const uint32_t *nstr, uint32_t B, float *delta,
+                      hipStream_t st);
 void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
                      const float *strand_rgb, const hm_gen_params &p, const hm_strands &s,
                      hipStream_t st);

@@ -531,3 +531,26 @@ void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_
 }
 
 }  // namespace hm
+
+namespace hm {
+
+// Depth correction of the LOD (Beer-Lambert): delta = -log(N_LOD / N_b).
+__global__ __launch_bounds__(256) void k_lod_delta(const uint32_t *table, const uint32_t *nstr,
+                                                   uint32_t B, float *delta)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const uint32_t n = table[4 * (size_t)b], N = nstr[b];
+    float d = 0.0f;
+    if (N > 0) d = n == 0 ? INFINITY : -logf((float)n / (float)N);
+    delta[b] = d;
+}
+
+void launch_lod_delta(const uint32_t *table, const uint32_t *nstr, uint32_t B, float *delta,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_lod_delta, dim3((B + 255) / 256), dim3(256), 0, st, table, nstr, B,
+                       delta);
+}
+
+}  // namespace hm

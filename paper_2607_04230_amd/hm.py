@@ -71,7 +71,16 @@ class ShadeParams(ctypes.Structure):
 EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_shade",
            "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
            "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
-           "hm_graph_create", "hm_graph_launch", "hm_graph_destroy"]
+           "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset"]
+
+
+def lod_depth_offset(table, bundle_nstrands, delta_out):
+    """Per-bundle depth correction delta = -log(N_LOD / N_b) (float32 tensor out)."""
+    L = load()
+    L.hm_lod_depth_offset.argtypes = [_vp, _vp, _u32, _vp, _vp]
+    L.hm_lod_depth_offset.restype = _i32
+    _check(L.hm_lod_depth_offset(_ptr(table), _ptr(bundle_nstrands), table.shape[0],
+                                 _ptr(delta_out), _stream()), "hm_lod_depth_offset")
 
 
 class FrameDesc(ctypes.Structure):

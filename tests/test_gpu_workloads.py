@@ -76,6 +76,21 @@ def test_lod_workload_windows(O, torch):
         assert np.abs(gout[so] - out[so]).max() <= TOL, f"head {k}"
 
 
+def test_lod_depth_offset_matches_oracle(O, torch):
+    sc = scenes.config_lod()
+    table, _, _ = O.lod_select(sc)
+    ds = _render(sc, torch)
+    delta = torch.empty(sc.n_bundles, dtype=torch.float32, device="cuda")
+    hm.lod_depth_offset(ds.table, ds.mesh_t["bundle_nstrands"], delta)
+    torch.cuda.synchronize()
+    got = delta.cpu().numpy().astype(np.float64)
+    ref = O.lod_depth_offset(table, sc.bundle_nstrands)
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isinf(got), ~fin)
+    assert np.abs(got[fin] - ref[fin]).max() <= 1e-6
+    assert (ref[fin] > 0).any()            # some bundles lost strands
+
+
 @pytest.fixture(scope="module")
 def batched(O, torch):
     sc = scenes.config_batched()

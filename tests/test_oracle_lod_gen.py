@@ -129,6 +129,22 @@ def test_lod_prefix_sums_and_scene_offsets(O):
     assert soff[5] == ncp
 
 
+def test_lod_depth_offset_closed_forms(O):
+    # half the strands kept -> ln 2; nothing removed -> 0 (Sec. 3.2.3); all
+    # removed -> +inf; an empty bundle -> 0
+    table = np.array([[32, 9, 0, 0], [64, 17, 0, 0], [0, 0, 0, 0], [0, 0, 0, 0], [16, 5, 0, 0]],
+                     np.uint32)
+    N = np.array([64, 64, 64, 0, 64], np.uint32)
+    d = O.lod_depth_offset(table, N)
+    assert d[0] == pytest.approx(math.log(2.0), abs=1e-15)
+    assert d[1] == 0.0 and math.isinf(d[2]) and d[3] == 0.0
+    assert d[4] == pytest.approx(2.0 * math.log(2.0), abs=1e-15)
+    # Beer-Lambert: exp(-sigma * beta * d) == exp(-sigma * d) shifted by delta in log-depth
+    beta, sigma, depth = 0.25, 3.0, 0.7
+    assert math.exp(-sigma * beta * depth) == pytest.approx(
+        math.exp(-sigma * math.exp(math.log(depth) - (-math.log(beta)))), rel=1e-12)
+
+
 # ------------------------------------------------------------------ generation
 def test_taylor_sin_cos_match_libm(O):
     for a in np.linspace(-math.pi, math.pi, 2001, endpoint=False):
