@@ -25,7 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, GB/s
-PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32
+PEAK_FP32_TFLOPS = 157.3       # MI355X vector FP32 (FMA = 2 flops, packed dual-lane issue)
+# VALU lane-operation issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one
+# unpacked fp32 / int32 op per lane per cycle)
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # Algorithmic work of each kernel per unit (see the design notes):
 #   bytes per control point / segment / pixel, or flops per filter tap.
@@ -33,6 +36,9 @@ GEN_BYTES_PER_CP = 16 + 16 + 1            # pos_w + rgb + flags written
 PROJ_BYTES_PER_CP = 16 + 16               # pos_w read, screen record written
 RASTER_BYTES_PER_SEG = 17                 # 16 B screen record + 1 B flags per CP
 FILTER_FLOPS_PER_TAP = 30
+# lane operations of one candidate-pixel evaluation of the raster: the centre
+# and conservative predicates, the closest-point depth and its 24-bit code
+RASTER_OPS_PER_PAIR = 64
 
 
 def _cpu_model():
@@ -91,19 +97,44 @@ def _traffic(kernel: str):
     return rec["bytes_per_launch"]
 
 
+def work_counts() -> dict:
+    """Exact raster work of the benchmark workloads (written offline by
+    tests/golden/make_work_counts.py)."""
+    path = os.path.join(ROOT, "tests", "golden", "work_counts.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
 def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, hair_px: int,
-             taps: int):
+             taps: int, workload: str = "head"):
     s = avg_ms * 1e-3
     if kernel == "k_filter":
         flops = hair_px * taps * FILTER_FLOPS_PER_TAP
         ach = flops / s / 1e12
         return {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / PEAK_FP32_TFLOPS, "traffic": _traffic(kernel)}
-    if kernel == "k_generate":
+    if kernel == "k_generate_bundle":
         b = n_cp * GEN_BYTES_PER_CP
     elif kernel == "k_project":
         b = n_cp * PROJ_BYTES_PER_CP
+    elif kernel == "k_bin":
+        b = n_cp * RASTER_BYTES_PER_SEG          # screen records + flags, per pass
+    elif kernel == "k_shade":
+        # both key layers read, one 16 B record written per pixel; per hair
+        # pixel two 16 B control points and two colours gathered
+        b = vis_bytes + vis_bytes + hair_px * 64
     elif kernel in ("k_raster_tiles", "k_raster_direct"):
+        # issue-bound: one predicate evaluation per conservatively covered
+        # (segment, pixel) pair, counted exactly by the oracle offline
+        pairs = work_counts().get(workload, {}).get("conservative_pairs")
+        hbm = (n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes) / s / 1e9
+        if pairs:
+            ach = pairs * RASTER_OPS_PER_PAIR / s / 1e12
+            return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                    "frac": ach / PEAK_VALU_TOPS, "traffic": _traffic(kernel),
+                    "pairs_per_s": pairs / s, "hbm_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
         b = n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes
     elif kernel == "k_prefill":
         b = vis_bytes
@@ -171,16 +202,19 @@ def hm_params_copy(p):
 def extra_lod(steps):
     """32 heads at geometric distances, 2560x1440, LOD on."""
     import torch
-    from paper_2607_04230_amd import scenes
+    from paper_2607_04230_amd import autotune, scenes
     from paper_2607_04230_amd.render import DeviceScene
     sc = scenes.config_lod()
     ds = DeviceScene(sc)
+    p, _ = autotune.tune(ds, autotune.QUICK_CANDIDATES, reps=3)
     ms = _time_ms(ds.render, steps, 2)
     tot = ds.totals.cpu().numpy()
     seg = int(tot[1]) - int(tot[0])
     r = {"ms_per_frame": ms, "strands_full": sc.n_full_strands, "strands_after_lod": int(tot[0]),
          "segments_after_lod": seg, "segments_full": sc.n_seg_full,
-         "segments_per_s": seg / (ms * 1e-3)}
+         "segments_per_s": seg / (ms * 1e-3),
+         "raster_params": {"algo": p.algo, "tile": p.tile, "chunk": p.chunk, "block": p.block,
+                           "max_tiles_per_seg": p.max_tiles_per_seg}}
     del ds
     torch.cuda.empty_cache()
     return r
@@ -316,6 +350,11 @@ def main():
     dom_avg = kt[dom][0] / kt[dom][1]
     roof = roofline(dom, dom_avg, n_cp, n_seg, vis_bytes, hair_px, (2 * r + 1) ** 2)
     roof["kernel"] = dom
+    for k in ("k_generate_bundle", "k_project", "k_bin", "k_raster_tiles", "k_prefill",
+              "k_shade", "k_filter"):
+        if k in per_kernel:
+            per_kernel[k]["roofline"] = roofline(k, per_kernel[k]["avg_ms"], n_cp, n_seg,
+                                                 vis_bytes, hair_px, (2 * r + 1) ** 2)
     raster_ms = sum(kt.get(k, (0.0, 0))[0] for k in
                     ("k_prefill", "k_project", "k_bin", "k_tile_items", "k_fill_u32",
                      "k_raster_tiles", "k_raster_long", "k_raster_direct",

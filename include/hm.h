@@ -159,16 +159,22 @@ hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
                               const hm_gen_params *p, const hm_strands *out, void *stream);
 
 /* ------------------------------------------------------------------ rasterization */
-enum { HM_RASTER_TILED = 0, HM_RASTER_DIRECT = 1 };
+/* HM_RASTER_TILED: screen tiles resolved in LDS, candidate pixels spread one
+ *   per lane (workgroups of at most 256 threads);
+ * HM_RASTER_DIRECT: one thread per segment, 64-bit atomics on the buffer;
+ * HM_RASTER_TILED_ROWS: screen tiles, each lane walks whole pixel rows. */
+enum { HM_RASTER_TILED = 0, HM_RASTER_DIRECT = 1, HM_RASTER_TILED_ROWS = 2 };
 
 typedef struct {
     float r_min;              /* minimum coverage half width (px): the centre sample's
                                  "configurable diameter" / 2 (Sec. 3.1.2); 0 = exact width */
-    int32_t algo;             /* HM_RASTER_TILED (LDS tiles) or HM_RASTER_DIRECT (global atomics) */
-    uint32_t tile;            /* tile edge in pixels: 8, 16, 32 or 64 */
+    int32_t algo;             /* HM_RASTER_TILED, HM_RASTER_DIRECT or HM_RASTER_TILED_ROWS */
+    uint32_t tile;            /* tile edge in pixels: 8, 16 or 32 */
     uint32_t chunk;           /* segments per work item of a tile (>= 1) */
     uint32_t max_tiles_per_seg; /* segments touching more tiles take the direct path (1..64) */
-    uint32_t block;           /* threads per workgroup: 64, 128, 256, 512 or 1024 */
+    uint32_t block;           /* threads per workgroup: a multiple of 64 in [64, 1024]
+                                 (at most 256 for HM_RASTER_TILED); the tile kernel's LDS
+                                 (layers + per-lane records) must stay within 64 KiB */
     uint32_t grid;            /* persistent workgroups (0 = auto) */
     uint32_t shared_views;    /* 0: scene s draws its own stream range scene_off[s..s+1];
                                  1: multiview -- one stream (strands.n_scenes = 1) drawn

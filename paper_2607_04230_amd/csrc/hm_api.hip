@@ -126,8 +126,9 @@ static hm_status check_ws(void *ws, size_t have, size_t need)
 static hm_status check_raster_params(const hm_raster_params *p)
 {
     REQUIRE(p, HM_ERR_INVALID, "raster params NULL");
-    REQUIRE(p->algo == HM_RASTER_TILED || p->algo == HM_RASTER_DIRECT, HM_ERR_INVALID,
-            "unknown raster algo %d", p->algo);
+    REQUIRE(p->algo == HM_RASTER_TILED || p->algo == HM_RASTER_DIRECT ||
+                p->algo == HM_RASTER_TILED_ROWS,
+            HM_ERR_INVALID, "unknown raster algo %d", p->algo);
     REQUIRE(p->tile == 8 || p->tile == 16 || p->tile == 32, HM_ERR_RANGE,
             "tile must be 8, 16 or 32 (got %u)", p->tile);
     REQUIRE(p->chunk >= 1 && p->chunk <= (1u << 20), HM_ERR_RANGE, "chunk outside [1, 2^20]");
@@ -137,7 +138,9 @@ static hm_status check_raster_params(const hm_raster_params *p)
             "block must be a multiple of 64 in [64, 1024]");
     REQUIRE(p->grid <= 65536, HM_ERR_RANGE, "grid outside [0, 65536]");
     REQUIRE(p->shared_views <= 1, HM_ERR_INVALID, "shared_views must be 0 or 1");
-    REQUIRE(p->algo != HM_RASTER_TILED || raster_lds_bytes(*p) <= 65536u, HM_ERR_RANGE,
+    REQUIRE(p->algo != HM_RASTER_TILED || p->block <= 256, HM_ERR_RANGE,
+            "HM_RASTER_TILED takes at most 256 threads per workgroup (got %u)", p->block);
+    REQUIRE(p->algo == HM_RASTER_DIRECT || raster_lds_bytes(*p) <= 65536u, HM_ERR_RANGE,
             "tile %u with %u threads needs %u B of LDS (limit 65536)", p->tile, p->block,
             raster_lds_bytes(*p));
     REQUIRE(isfinite(p->r_min) && p->r_min >= 0.0f && p->r_min <= 64.0f, HM_ERR_RANGE,

@@ -92,9 +92,9 @@ __device__ __forceinline__ uint32_t depth_code(float z, float zn, float inv_rang
 {
     float d = (z - zn) * inv_range;
     float fq = d * 16777216.0f;
-    if (!(fq > 0.0f)) return 0u;
-    if (fq >= 16777215.0f) return HM_QMAX;
-    return (uint32_t)fq;
+    // branch-free: truncation of min(fq, 2^24 - 1) for fq > 0, else 0
+    const float c = fq < 16777215.0f ? fq : 16777215.0f;
+    return fq > 0.0f ? (uint32_t)c : 0u;
 }
 
 // ----------------------------------------------------------------- coverage
@@ -105,7 +105,18 @@ struct Seg {
     float len2, ilen2, ra;
     float sxmn, sxmx, symn, symx;
     float idy;              // 1/dy for candidate enumeration (0 when |dy| <= 1e-3)
+    float e;                // slack of candidate enumeration against binary32 rounding
 };
+
+// Slack of candidate enumeration: 0.05 px, widened by ~8 ulp of the largest
+// magnitude involved so that clips of far off-screen endpoints stay
+// conservative.
+__device__ __forceinline__ float seg_slack(const Seg &s)
+{
+    const float m = fmaxx(fmaxx(fmaxx(fabsf(s.sxmn), fabsf(s.sxmx)),
+                                fmaxx(fabsf(s.symn), fabsf(s.symx))), s.ra);
+    return 0.05f + 1e-6f * m;
+}
 
 __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
 {
@@ -122,6 +133,7 @@ __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
     s.sxmn = fminx(a.x, b.x); s.sxmx = fmaxx(a.x, b.x);
     s.symn = fminx(a.y, b.y); s.symx = fmaxx(a.y, b.y);
     s.idy = fabsf(s.dy) > 1e-3f ? 1.0f / s.dy : 0.0f;
+    s.e = seg_slack(s);
     return s;
 }
 
@@ -130,37 +142,34 @@ __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
 __device__ __forceinline__ uint32_t cover(const Seg &s, int i, int j, float r_min, float zn,
                                           float inv_range, uint32_t &q)
 {
-    float fi = (float)i, fj = (float)j;
-    float ux = (fi + 0.5f) - s.x0;
-    float uy = (fj + 0.5f) - s.y0;
-    float tn = ux * s.dx + uy * s.dy;
-    bool centre;
-    if (s.len2 > 0.0f) {
-        float t = tn * s.ilen2;
-        float wt = s.w0 + t * s.dw;
-        float r = fmaxx(0.5f * wt, r_min);
-        float cr = ux * s.dy - uy * s.dx;
-        centre = (tn >= 0.0f) && (tn < s.len2) && (cr * cr <= (r * r) * s.len2);
-    } else {
-        float r = fmaxx(0.5f * s.w0, r_min);
-        centre = (ux * ux + uy * uy) <= r * r;
-    }
-    float bx0 = fi - s.ra, bx1 = (fi + 1.0f) + s.ra;
-    float by0 = fj - s.ra, by1 = (fj + 1.0f) + s.ra;
-    bool cons = (s.sxmn <= bx1) && (s.sxmx >= bx0) && (s.symn <= by1) && (s.symx >= by0);
-    if (cons) {
-        float fa = (bx0 - s.x0) * s.dy, fb = (bx1 - s.x0) * s.dy;
-        float ga = (by0 - s.y0) * s.dx, gb = (by1 - s.y0) * s.dx;
-        float lo = fminx(fa, fb) - fmaxx(ga, gb);
-        float hi = fmaxx(fa, fb) - fminx(ga, gb);
-        cons = (lo <= 0.0f) && (hi >= 0.0f);
-    }
-    if (!(centre || cons)) return 0u;
-    float ts = tn * s.ilen2;
+    // Evaluated without branches (selects only): the two tests, the closest
+    // point and the depth code are computed for every candidate pixel.  For a
+    // degenerate segment ilen2 = 0, so t = 0 and r is the endpoint radius.
+    const float fi = (float)i, fj = (float)j;
+    const float ux = (fi + 0.5f) - s.x0;
+    const float uy = (fj + 0.5f) - s.y0;
+    const float tn = ux * s.dx + uy * s.dy;
+    const float t = tn * s.ilen2;
+    const float wt = s.w0 + t * s.dw;
+    const float r = fmaxx(0.5f * wt, r_min);
+    const float r2 = r * r;
+    const float cr = ux * s.dy - uy * s.dx;
+    const bool seg_in = (tn >= 0.0f) & (tn < s.len2) & (cr * cr <= r2 * s.len2);
+    const bool disc_in = (ux * ux + uy * uy) <= r2;
+    const bool centre = s.len2 > 0.0f ? seg_in : disc_in;
+    const float bx0 = fi - s.ra, bx1 = (fi + 1.0f) + s.ra;
+    const float by0 = fj - s.ra, by1 = (fj + 1.0f) + s.ra;
+    const float fa = (bx0 - s.x0) * s.dy, fb = (bx1 - s.x0) * s.dy;
+    const float ga = (by0 - s.y0) * s.dx, gb = (by1 - s.y0) * s.dx;
+    const float lo = fminx(fa, fb) - fmaxx(ga, gb);
+    const float hi = fmaxx(fa, fb) - fminx(ga, gb);
+    const bool cons = (s.sxmn <= bx1) & (s.sxmx >= bx0) & (s.symn <= by1) & (s.symx >= by0) &
+                      (lo <= 0.0f) & (hi >= 0.0f);
+    float ts = t;
     ts = fmaxx(ts, 0.0f);
     ts = fminx(ts, 1.0f);
-    float iz = s.iz0 + ts * s.diz;
-    float z = 1.0f / iz;
+    const float iz = s.iz0 + ts * s.diz;
+    const float z = 1.0f / iz;
     q = depth_code(z, zn, inv_range);
     return (centre ? 1u : 0u) | (cons ? 2u : 0u);
 }

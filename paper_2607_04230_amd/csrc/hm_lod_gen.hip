@@ -275,118 +275,6 @@ struct GenK {
     float br, bg, bb;
 };
 
-__global__ __launch_bounds__(256) void k_generate(hm_hair_mesh m, const uint32_t *table,
-                                                  const uint32_t *strand_base,
-                                                  const float *strand_rgb, GenK g,
-                                                  float4 *pos_w, float4 *rgb, uint8_t *flags,
-                                                  const uint32_t *scene_off, uint32_t S,
-                                                  uint32_t cap)
-{
-    const uint32_t total = scene_off[S];
-    const uint32_t n_cp = total < cap ? total : cap;
-    const uint32_t B = m.n_bundles, NL = m.n_layers;
-    for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < n_cp;
-         c += gridDim.x * blockDim.x) {
-        // bundle owning CP c: last b with first-CP offset <= c
-        uint32_t lo = 0, hi = B;
-        while (hi - lo > 1) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (table[4 * (size_t)mid + 3] <= c) lo = mid; else hi = mid;
-        }
-        const uint32_t b = lo;
-        const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
-        const uint32_t C = tb.y;
-        const uint32_t rel = c - tb.w;
-        const uint32_t k = rel / C;
-        const uint32_t j = rel - k * C;
-
-        const uint32_t h1 = pcg(bundle_hash(g.seed, m.bundle_key[b]) + k);
-        const uint32_t h2 = pcg(h1);
-        const uint32_t h3 = pcg(h2);
-        const float u = unit24(h1), v = unit24(h2), ph = unit24(h3);
-
-        const uint4 q4 = reinterpret_cast<const uint4 *>(m.quads)[b];
-        const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
-
-        const float w = (float)j / (float)(C - 1u);
-        const float x = w * (float)(NL - 1u);
-        int i = (int)x;
-        i = i > (int)NL - 2 ? (int)NL - 2 : i;
-        const float t = x - (float)i;
-
-        // base points needed by the interval [i, i+1] and its two tangents
-        const F3 Pi = layer_point(m.layer_pos, m.n_verts, i, q, u, v);
-        const F3 Pj = layer_point(m.layer_pos, m.n_verts, i + 1, q, u, v);
-        F3 Ti, Tj;
-        if (i == 0) {
-            Ti = f3norm(f3sub(Pj, Pi));
-        } else {
-            const F3 Pm = layer_point(m.layer_pos, m.n_verts, i - 1, q, u, v);
-            Ti = f3norm(f3sub(Pj, Pm));
-        }
-        if (i + 1 == (int)NL - 1) {
-            Tj = f3norm(f3sub(Pj, Pi));
-        } else {
-            const F3 Pp = layer_point(m.layer_pos, m.n_verts, i + 2, q, u, v);
-            Tj = f3norm(f3sub(Pp, Pi));
-        }
-        const F3 ch = f3sub(Pj, Pi);
-        const float chord = sqrtf((ch.x * ch.x + ch.y * ch.y) + ch.z * ch.z);
-        const float t2 = t * t, t3 = t2 * t;
-        const float h00 = (2.0f * t3 - 3.0f * t2) + 1.0f;
-        const float h10 = (t3 - 2.0f * t2) + t;
-        const float h01 = 3.0f * t2 - 2.0f * t3;
-        const float h11 = t3 - t2;
-        const float pi3[3] = {Pi.x, Pi.y, Pi.z}, pj3[3] = {Pj.x, Pj.y, Pj.z};
-        const float ti3[3] = {Ti.x, Ti.y, Ti.z}, tj3[3] = {Tj.x, Tj.y, Tj.z};
-        float X[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float m0 = chord * ti3[d], m1 = chord * tj3[d];
-            X[d] = ((h00 * pi3[d] + h10 * m0) + h01 * pj3[d]) + h11 * m1;
-        }
-
-        // bundle styling frame from the first layer interval
-        F3 s0 = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int k2 = 0; k2 < 4; ++k2) {
-            const F3 a0 = ld3(m.layer_pos + 3 * (size_t)q[k2]);
-            const F3 a1 = ld3(m.layer_pos + ((size_t)m.n_verts + q[k2]) * 3);
-            const F3 d = f3sub(a1, a0);
-            s0.x = s0.x + d.x; s0.y = s0.y + d.y; s0.z = s0.z + d.z;
-        }
-        const F3 nb = f3norm(s0);
-        F3 ax = {0.0f, 0.0f, 1.0f};
-        if (fabsf(nb.z) > 0.9f) { ax.x = 1.0f; ax.z = 0.0f; }
-        const F3 e1 = f3norm(f3cross(nb, ax));
-        const F3 e2 = f3cross(nb, e1);
-
-        float f = g.curl_turns * w + ph;
-        f = f - floorf(f);
-        const float a = (f - 0.5f) * 0x1.921fb6p+2f;
-        const float cth = -tcos(a), sth = -tsin(a);
-        const float amp = g.curl_amp * w;
-        float4 o;
-        o.x = X[0] + amp * (cth * e1.x + sth * e2.x);
-        o.y = X[1] + amp * (cth * e1.y + sth * e2.y);
-        o.z = X[2] + amp * (cth * e1.z + sth * e2.z);
-        o.w = g.width;
-        pos_w[c] = o;
-        float4 col;
-        if (strand_rgb) {
-            const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k);
-            col = make_float4(sr[0], sr[1], sr[2], 1.0f);
-        } else {
-            col = make_float4(g.br, g.bg, g.bb, 1.0f);
-        }
-        rgb[c] = col;
-        uint8_t fl = 0;
-        if (j == 0) fl |= (uint8_t)HM_ROOT;
-        if (j == C - 1u) fl |= (uint8_t)HM_TIP;
-        flags[c] = fl;
-    }
-}
-
 // Cooperative assembly, one wave per bundle (the paper assigns a subgroup per
 // strand and shares control points through shuffles; on gfx950 a 64-lane wave
 // shares a bundle's strands through LDS): the strands' (u, v, phase), base

@@ -130,11 +130,13 @@ __device__ __forceinline__ bool seg_box(const Seg &sg, uint32_t W, uint32_t H, i
 // test only if the segment has a point with y in [j - ra, j + 1 + ra] and x in
 // [i - ra, i + 1 + ra] (the centre test's disc of radius r <= ra around the
 // pixel centre lies inside that square).  So: clip the segment to the row band
-// widened by ra, and take i in [x_lo - 1 - ra, x_hi + ra]; a 0.05 px slack
-// absorbs binary32 rounding of the clip.
+// widened by ra, and take i in [x_lo - 1 - ra, x_hi + ra]; the slack sg.e
+// (0.05 px plus ~8 ulp of the coordinates' magnitude) absorbs binary32
+// rounding of the clip: an error of the clip parameter is bounded by the
+// rounding of its numerator over |dy|, far below the band's widening e / |dy|.
 __device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
 {
-    const float e = 0.05f;
+    const float e = sg.e;
     const float ylo = ((float)j - sg.ra) - e, yhi = (((float)j + 1.0f) + sg.ra) + e;
     float xlo = sg.sxmn, xhi = sg.sxmx;
     if (sg.idy != 0.0f) {
@@ -266,6 +268,7 @@ __device__ __forceinline__ bool seg_tile_k(const SegTiles &st, const RasterK &rk
 }
 
 constexpr uint32_t BIN_SLOTS = 1024;      // LDS hash slots per workgroup
+constexpr uint32_t BIN_SUB = 8;           // segments per thread between table flushes
 constexpr uint32_t BIN_FREE = 0xFFFFFFFFu;
 
 // Slot of `tile` in the workgroup's LDS table (linear probing), -1 if full.
@@ -280,9 +283,9 @@ __device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
     return -1;
 }
 
-// Per-tile segment lists.  Each workgroup takes blockDim consecutive segments
-// (consecutive segments belong to the same few strands, so they fall in a few
-// tiles) and aggregates its (segment, tile) pairs per tile in an LDS table:
+// Per-tile segment lists.  Each workgroup takes BIN_SUB * blockDim consecutive
+// segments (consecutive segments belong to the same few strands, so they fall
+// in a few tiles) and aggregates its (segment, tile) pairs per tile in an LDS table:
 //   pass 0: counts per tile, flushed with one non-returning global add per
 //           (workgroup, tile); segments spanning more than K tiles go to the
 //           long list;
@@ -297,21 +300,23 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
+    const uint32_t span = blockDim.x * BIN_SUB;     // segments per table flush
     // v below is a segment unit (see unit_map); lists store units
-    for (uint32_t base = blockIdx.x * blockDim.x; base < nu; base += gridDim.x * blockDim.x) {
+    for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
         for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
             keys[x] = BIN_FREE;
             cnt[x] = 0;
         }
         __syncthreads();
-        const uint32_t v = base + threadIdx.x;
-        SegTiles st;
-        bool ok = seg_tiles(proj, flags, scene_off, rk, v, n, st);
-        if (ok && st.nt > rk.K) {
-            if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
-            ok = false;
-        }
-        if (ok) {
+        for (uint32_t sub = 0; sub < BIN_SUB; ++sub) {
+            const uint32_t v = base + sub * blockDim.x + threadIdx.x;
+            SegTiles st;
+            bool ok = seg_tiles(proj, flags, scene_off, rk, v, n, st);
+            if (ok && st.nt > rk.K) {
+                if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
+                ok = false;
+            }
+            if (!ok) continue;
             for (uint32_t k = 0; k < st.nt; ++k) {
                 uint32_t tile;
                 if (!seg_tile_k(st, rk, k, tile)) continue;
@@ -333,20 +338,26 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
             }
         }
         __syncthreads();
-        if (pass == 1 && ok) {
-            for (uint32_t k = 0; k < st.nt; ++k) {
-                uint32_t tile;
-                if (!seg_tile_k(st, rk, k, tile)) continue;
-                // the slot exists already: the same pairs were inserted above
-                const uint32_t h = (tile * 2654435761u) >> 22;
-                int sl = -1;
-                for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
-                    const uint32_t q = (h + i) & (BIN_SLOTS - 1);
-                    const uint32_t kq = keys[q];
-                    if (kq == tile) { sl = (int)q; break; }
-                    if (kq == BIN_FREE) break;
+        if (pass == 1) {
+            for (uint32_t sub = 0; sub < BIN_SUB; ++sub) {
+                const uint32_t v = base + sub * blockDim.x + threadIdx.x;
+                SegTiles st;
+                if (!seg_tiles(proj, flags, scene_off, rk, v, n, st) || st.nt > rk.K) continue;
+                for (uint32_t k = 0; k < st.nt; ++k) {
+                    uint32_t tile;
+                    if (!seg_tile_k(st, rk, k, tile)) continue;
+                    // the slot exists already unless the table was full when
+                    // the pair was inserted (it was then written directly)
+                    const uint32_t h = (tile * 2654435761u) >> 22;
+                    int sl = -1;
+                    for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
+                        const uint32_t q = (h + i) & (BIN_SLOTS - 1);
+                        const uint32_t kq = keys[q];
+                        if (kq == tile) { sl = (int)q; break; }
+                        if (kq == BIN_FREE) break;
+                    }
+                    if (sl >= 0) entries[basev[sl] + atomicAdd(&cnt[sl], 1u)] = v;
                 }
-                if (sl >= 0) entries[basev[sl] + atomicAdd(&cnt[sl], 1u)] = v;
             }
         }
         __syncthreads();
@@ -404,53 +415,128 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint3
 }
 
 // ------------------------------------------------------------------ tiled raster
-constexpr uint32_t SEG_FIELDS = 16;
+// Per-segment records of a batch, struct of arrays with stride nb (fields a
+// caller does not use are not read: the loads are plain LDS reads): the 16
+// geometric fields of Seg (the slack e is recomputed from them), then the
+// stream id, the segment's first row slot, and its row / column clip inside
+// the tile packed as (j0 - py0) | (i0 - px0) << 8 | (i1 - px0) << 16.
+constexpr uint32_t REC_FLOATS = 16;
+constexpr uint32_t REC_WORDS = REC_FLOATS + 3;
 
-__device__ __forceinline__ void seg_store(float *sf, uint32_t nb, uint32_t k, const Seg &s)
+__device__ __forceinline__ void rec_store(float *rf, uint32_t nb, uint32_t k, const Seg &s)
 {
-    const float f[SEG_FIELDS] = {s.x0, s.y0, s.w0, s.iz0, s.dx, s.dy, s.dw, s.diz,
+    const float f[REC_FLOATS] = {s.x0,    s.y0, s.w0,   s.iz0,  s.dx,   s.dy,   s.dw,   s.diz,
                                  s.len2, s.ilen2, s.ra, s.sxmn, s.sxmx, s.symn, s.symx, s.idy};
 #pragma unroll
-    for (uint32_t i = 0; i < SEG_FIELDS; ++i) sf[i * nb + k] = f[i];
+    for (uint32_t i = 0; i < REC_FLOATS; ++i) rf[i * nb + k] = f[i];
 }
 
-__device__ __forceinline__ Seg seg_load(const float *sf, uint32_t nb, uint32_t k)
+__device__ __forceinline__ Seg rec_load(const float *rf, uint32_t nb, uint32_t k)
 {
     Seg s;
-    s.x0 = sf[0 * nb + k]; s.y0 = sf[1 * nb + k]; s.w0 = sf[2 * nb + k]; s.iz0 = sf[3 * nb + k];
-    s.dx = sf[4 * nb + k]; s.dy = sf[5 * nb + k]; s.dw = sf[6 * nb + k]; s.diz = sf[7 * nb + k];
-    s.len2 = sf[8 * nb + k]; s.ilen2 = sf[9 * nb + k]; s.ra = sf[10 * nb + k];
-    s.sxmn = sf[11 * nb + k]; s.sxmx = sf[12 * nb + k]; s.symn = sf[13 * nb + k];
-    s.symx = sf[14 * nb + k]; s.idy = sf[15 * nb + k];
+    s.x0 = rf[0 * nb + k]; s.y0 = rf[1 * nb + k]; s.w0 = rf[2 * nb + k]; s.iz0 = rf[3 * nb + k];
+    s.dx = rf[4 * nb + k]; s.dy = rf[5 * nb + k]; s.dw = rf[6 * nb + k]; s.diz = rf[7 * nb + k];
+    s.len2 = rf[8 * nb + k]; s.ilen2 = rf[9 * nb + k]; s.ra = rf[10 * nb + k];
+    s.sxmn = rf[11 * nb + k]; s.sxmx = rf[12 * nb + k]; s.symn = rf[13 * nb + k];
+    s.symx = rf[14 * nb + k]; s.idy = rf[15 * nb + k];
+    s.e = seg_slack(s);
     return s;
 }
 
-// dynamic LDS bytes of k_raster_tiles for tile edge T and `block` threads
-static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block)
+// Rows [j0, j1] of a tile that the segment can reach: clip the segment to the
+// tile's column slab widened by ra (+ slack) and keep the rows whose band
+// [j - ra, j + 1 + ra] meets the clipped part's y extent (same argument and
+// slack as row_span, with x and y exchanged).  False if none remain.
+__device__ __forceinline__ bool tile_rows(const Seg &sg, int px0, int px1, int &j0, int &j1)
 {
-    return 2u * T * T * 8u + block * 4u * (SEG_FIELDS + 5u);
+    const float e = sg.e;
+    const float xl = ((float)px0 - sg.ra) - e, xh = (((float)px1 + 1.0f) + sg.ra) + e;
+    float ya = sg.symn, yb = sg.symx;
+    if (fabsf(sg.dx) > 1e-3f) {
+        const float idx = 1.0f / sg.dx;
+        const float ta = (xl - sg.x0) * idx, tb = (xh - sg.x0) * idx;
+        const float t0 = fmaxx(fminx(ta, tb), 0.0f), t1 = fminx(fmaxx(ta, tb), 1.0f);
+        if (t0 > t1) return false;
+        const float y_a = sg.y0 + t0 * sg.dy, y_b = sg.y0 + t1 * sg.dy;
+        ya = fminx(y_a, y_b);
+        yb = fmaxx(y_a, y_b);
+    } else if (sg.sxmx < xl || sg.sxmn > xh) {
+        return false;
+    }
+    const float flo = ((ya - 1.0f) - sg.ra) - e, fhi = (yb + sg.ra) + e;
+    if (flo > -1.0e9f) j0 = max(j0, (int)ceilf(flo));
+    if (fhi < 1.0e9f) j1 = min(j1, (int)floorf(fhi));
+    return j0 <= j1;
 }
-// Dynamic LDS: two layers of T*T keys.  Work items are pulled from counters[1].
+
+// Orders the LDS accesses of one wave around a hand-off between its lanes.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pixel slots of one wave's pixel -> row map (bytes); rows whose candidate
+// pixels exceed it are spread in several windows.
+constexpr uint32_t PIX_WINDOW = 256;
+
+// dynamic LDS bytes of k_raster_tiles for tile edge T and `block` threads:
+// two layers of keys and the segment records; for the per-pixel spread also
+// the row-start bitmap (block * T bits), each wave's pixel -> row window and
+// its 64 row descriptors (2 words each)
+static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat)
+{
+    uint32_t b = 2u * T * T * 8u + block * 4u * REC_WORDS;
+    if (flat) b += block * T / 8u + (block / 64u) * (PIX_WINDOW + 64u * 8u);
+    return b;
+}
+
+// Persistent tile raster.  Work items (a tile and a chunk of its segment
+// list) are pulled from counters[1].  The tile's two layers live in LDS.
+//
+// Segments are taken in batches of nb: each lane builds one segment's record
+// (screen geometry, the rows and columns of the tile it can reach, stream id)
+// and one block scan both compacts the segments that reach the tile and
+// numbers their (segment, row) pairs ("row slots").  Then
+//   FLAT = false: each lane takes a contiguous run of row slots and loops over
+//                 the candidate pixels of each row;
+//   FLAT = true:  (nb <= 256: row owners travel as 8-bit ids) each wave takes
+//                 64 row slots at a time, one per lane, finds each slot's
+//                 segment from a bitmap of first rows (ballot + popcount),
+//                 computes the column spans, and a wave scan spreads the
+//                 candidate pixels of those rows over the lanes, one pixel per
+//                 lane per step, so that lanes stay busy whatever the spans.
+//
+// NBC: the workgroup size when known at compile time (the record fields then
+// sit at fixed LDS offsets), 0 for any blockDim.
+template <bool FLAT, uint32_t NBC>
 __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
                                uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
                                const uint32_t *entries, uint32_t *counters, uint64_t *vis)
 {
-    // dynamic LDS: the tile's two layers, then per-lane segment records
-    // (struct of arrays: SEG_FIELDS floats, stream id, first row, columns,
-    // row-slot prefix), nb = blockDim entries each
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t sh_item;
     __shared__ uint32_t sh_scan[1024 / 64 + 1];
     const uint32_t TT = rk.T * rk.T;
-    const uint32_t nb = blockDim.x;
+    const uint32_t nb = NBC ? NBC : blockDim.x;
     uint64_t *lc = lds, *la = lds + TT;
-    float *sf = reinterpret_cast<float *>(lds + 2 * TT);
-    uint32_t *sv = reinterpret_cast<uint32_t *>(sf + SEG_FIELDS * nb);
-    int *sj0 = reinterpret_cast<int *>(sv + nb);
-    int *si0 = sj0 + nb;
-    int *si1 = si0 + nb;
-    uint32_t *spre = reinterpret_cast<uint32_t *>(si1 + nb);
+    float *rf = reinterpret_cast<float *>(lds + 2 * TT);
+    uint32_t *rw = reinterpret_cast<uint32_t *>(rf);
+    uint32_t *r_sid = rw + REC_FLOATS * nb;          // stream id
+    uint32_t *r_row = r_sid + nb;                    // first row slot
+    uint32_t *r_clip = r_row + nb;                   // packed row / column clip
+    // per-pixel spread only
+    const uint32_t wv = threadIdx.x >> 6;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t nw = nb >> 6;
+    const uint32_t bmp_words = nb * rk.T / 32u;
+    uint32_t *bmp = r_clip + nb;
+    uint8_t *prow = reinterpret_cast<uint8_t *>(bmp + bmp_words) + wv * PIX_WINDOW;
+    uint32_t *rdesc = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(bmp + bmp_words) +
+                                                   nw * PIX_WINDOW) + wv * 128u;
+
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_items = item_off[rk.n_tiles];
     const size_t hw = (size_t)rk.W * rk.H;
@@ -498,79 +584,152 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             __syncthreads();
         }
 
-        // Batches of blockDim segments.  Each lane builds its segment's record
-        // once (screen geometry, clipped columns, first row, stream id) into
-        // LDS; a prefix scan of the row counts then spreads the (segment, row)
-        // pairs evenly, each lane taking a contiguous run of row slots and
-        // reading the owning segment's record from LDS.
-        for (uint32_t e0 = beg; e0 < end; e0 += blockDim.x) {
+        for (uint32_t e0 = beg; e0 < end; e0 += nb) {
             const uint32_t e = e0 + threadIdx.x;
-            uint32_t nr = 0;
+            uint32_t nr = 0, vu = 0;
+            Seg sg;
+            int i0, i1, j0, j1;
             if (e < end) {
                 const uint32_t u = entries[e];                  // segment unit
-                uint32_t su, vu;
+                uint32_t su;
                 unit_map(scene_off, rk, n, u, su, vu);
-                Seg sg;
-                int i0, i1, j0, j1;
                 if (load_seg(proj, flags, u, vu, n, rk.r_min, sg) &&
                     seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
                     j0 = max(j0, py0);
                     j1 = min(j1, py1);
                     i0 = max(i0, px0);
                     i1 = min(i1, px1);
-                    if (i0 <= i1 && j0 <= j1) {
+                    if (i0 <= i1 && j0 <= j1 && tile_rows(sg, px0, px1, j0, j1))
                         nr = (uint32_t)(j1 - j0 + 1);
-                        seg_store(sf, nb, threadIdx.x, sg);
-                        sv[threadIdx.x] = vu;
-                        sj0[threadIdx.x] = j0;
-                        si0[threadIdx.x] = i0;
-                        si1[threadIdx.x] = i1;
+                }
+            }
+            if (FLAT) {
+                for (uint32_t x = threadIdx.x; x < bmp_words; x += blockDim.x) bmp[x] = 0u;
+            }
+            // one scan: low 16 bits number the row slots (at most nb * T),
+            // high 16 bits compact the segments that reach the tile
+            uint32_t totp;
+            const uint32_t pre = block_exclusive_scan((nr ? 0x10000u : 0u) | nr, sh_scan, totp);
+            const uint32_t tot = totp & 0xFFFFu, nseg = totp >> 16;
+            if (nr) {
+                const uint32_t c = pre >> 16, r0 = pre & 0xFFFFu;
+                rec_store(rf, nb, c, sg);
+                r_sid[c] = vu;
+                r_row[c] = r0;
+                r_clip[c] = (uint32_t)(j0 - py0) | ((uint32_t)(i0 - px0) << 8) |
+                            ((uint32_t)(i1 - px0) << 16);
+                if (FLAT) atomicOr(&bmp[r0 >> 5], 1u << (r0 & 31u));
+            }
+            __syncthreads();
+            if (FLAT) {
+                // contiguous 64-slot groups per wave, so that the count of
+                // segments starting before a group carries from one to the next
+                const uint32_t ng = (tot + 63u) >> 6;
+                const uint32_t G = (ng + nw - 1u) / nw;
+                const uint32_t g0 = wv * G, g1 = min(g0 + G, ng);
+                uint32_t before = 0;                 // segments whose first row < 64 * g0
+                if (g0 < g1) {
+                    uint32_t l2 = 0, h2 = nseg;      // first rows increase strictly
+                    while (l2 < h2) {
+                        const uint32_t mid = (l2 + h2) >> 1;
+                        if (r_row[mid] < g0 * 64u) l2 = mid + 1; else h2 = mid;
+                    }
+                    before = l2;
+                }
+                const uint64_t le = (2ull << lane) - 1ull;   // lanes <= this one
+                for (uint32_t g = g0; g < g1; ++g) {
+                    const uint32_t rr = g * 64u + lane;
+                    const bool start = rr < tot && ((bmp[rr >> 5] >> (rr & 31u)) & 1u);
+                    const uint64_t M = __ballot(start);
+                    const uint32_t o = before + (uint32_t)__popcll(M & le) - 1u;
+                    before += (uint32_t)__popcll(M);
+                    uint32_t c = 0, d0 = 0;
+                    if (rr < tot) {
+                        const Seg sr = rec_load(rf, nb, o);
+                        const uint32_t clip = r_clip[o];
+                        const int j = py0 + (int)(clip & 0xFFu) + (int)(rr - r_row[o]);
+                        int a0, a1;
+                        row_span(sr, j, a0, a1);
+                        a0 = max(a0, px0 + (int)((clip >> 8) & 0xFFu));
+                        a1 = min(a1, px0 + (int)(clip >> 16));
+                        if (a1 >= a0) c = (uint32_t)(a1 - a0 + 1);
+                        d0 = o | ((uint32_t)(j - py0) << 8) | ((uint32_t)(a0 - px0) << 16);
+                    }
+                    const uint32_t inc = wave_inclusive_scan(c);
+                    const uint32_t pc = inc - c;
+                    const uint32_t P = __shfl(inc, 63, 64);
+                    rdesc[lane] = d0;
+                    rdesc[64 + lane] = pc;
+                    for (uint32_t w0 = 0; w0 < P; w0 += PIX_WINDOW) {
+                        const uint32_t m0 = pc > w0 ? pc : w0;
+                        const uint32_t m1 = min(pc + c, w0 + PIX_WINDOW);
+                        for (uint32_t m = m0; m < m1; ++m) prow[m - w0] = (uint8_t)lane;
+                        wave_sync();
+                        const uint32_t wl = min(P - w0, PIX_WINDOW);
+                        for (uint32_t p0 = 0; p0 < wl; p0 += 64) {
+                            const uint32_t pl = p0 + lane;
+                            if (pl < wl) {
+                                const uint32_t rl = prow[pl];
+                                const uint32_t d = rdesc[rl], pr = rdesc[64 + rl];
+                                const uint32_t ow = d & 0xFFu;
+                                const int j = py0 + (int)((d >> 8) & 0xFFu);
+                                const int i = px0 + (int)(d >> 16) + (int)(w0 + pl - pr);
+                                const Seg sp = rec_load(rf, nb, ow);
+                                uint32_t q;
+                                const uint32_t msk = cover(sp, i, j, rk.r_min, zn, inv_range, q);
+                                if (msk) {
+                                    const unsigned long long key =
+                                        ((unsigned long long)q << HM_ID_BITS) | r_sid[ow];
+                                    const uint32_t x =
+                                        (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
+                                    if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
+                                    if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
+                                }
+                            }
+                        }
+                        wave_sync();
                     }
                 }
-            }
-            uint32_t tot;
-            const uint32_t pre = block_exclusive_scan(nr, sh_scan, tot);
-            spre[threadIdx.x] = pre;
-            __syncthreads();
-            const uint32_t per = (tot + blockDim.x - 1) / blockDim.x;
-            const uint32_t r_beg = threadIdx.x * per;
-            const uint32_t r_end = min(r_beg + per, tot);
-            uint32_t lo = 0;
-            if (r_beg < r_end) {            // owner of the first slot: binary search
-                uint32_t hi = blockDim.x;
-                while (hi - lo > 1) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (spre[mid] <= r_beg) lo = mid; else hi = mid;
+            } else {
+                const uint32_t per = (tot + nb - 1) / nb;
+                const uint32_t r_beg = threadIdx.x * per;
+                const uint32_t r_end = min(r_beg + per, tot);
+                uint32_t ow = 0;
+                if (r_beg < r_end) {            // owner of the first slot: binary search
+                    uint32_t h2 = nseg;
+                    while (h2 - ow > 1) {
+                        const uint32_t mid = (ow + h2) >> 1;
+                        if (r_row[mid] <= r_beg) ow = mid; else h2 = mid;
+                    }
                 }
-            }
-            uint32_t cur = 0xFFFFFFFFu, vo = 0;
-            Seg sg;
-            int i0 = 0, i1 = -1, jb = 0;
-            uint32_t pb = 0;
-            for (uint32_t rr = r_beg; rr < r_end; ++rr) {
-                while (lo + 1 < blockDim.x && spre[lo + 1] <= rr) ++lo;
-                if (lo != cur) {
-                    cur = lo;
-                    sg = seg_load(sf, nb, lo);
-                    vo = sv[lo];
-                    jb = sj0[lo];
-                    i0 = si0[lo];
-                    i1 = si1[lo];
-                    pb = spre[lo];
-                }
-                const int j = jb + (int)(rr - pb);
-                int a0, a1;
-                row_span(sg, j, a0, a1);
-                a0 = max(a0, i0);
-                a1 = min(a1, i1);
-                for (int i = a0; i <= a1; ++i) {
-                    uint32_t q;
-                    const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
-                    if (!msk) continue;
-                    const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | vo;
-                    const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
-                    if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
-                    if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
+                uint32_t cur = 0xFFFFFFFFu, vo = 0, clip = 0;
+                Seg sr;
+                int jb = 0;
+                uint32_t pb = 0;
+                for (uint32_t rr = r_beg; rr < r_end; ++rr) {
+                    while (ow + 1 < nseg && r_row[ow + 1] <= rr) ++ow;
+                    if (ow != cur) {
+                        cur = ow;
+                        sr = rec_load(rf, nb, ow);
+                        vo = r_sid[ow];
+                        clip = r_clip[ow];
+                        jb = py0 + (int)(clip & 0xFFu);
+                        pb = r_row[ow];
+                    }
+                    const int j = jb + (int)(rr - pb);
+                    int a0, a1;
+                    row_span(sr, j, a0, a1);
+                    a0 = max(a0, px0 + (int)((clip >> 8) & 0xFFu));
+                    a1 = min(a1, px0 + (int)(clip >> 16));
+                    for (int i = a0; i <= a1; ++i) {
+                        uint32_t q;
+                        const uint32_t msk = cover(sr, i, j, rk.r_min, zn, inv_range, q);
+                        if (!msk) continue;
+                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | vo;
+                        const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
+                        if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
+                        if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
+                    }
                 }
             }
             __syncthreads();
@@ -685,7 +844,7 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
     w.items = (uint32_t *)take(sizeof(uint32_t) * (nt + 1));
     w.partials = (uint32_t *)take(sizeof(uint32_t) * (scan_blocks((uint32_t)nt) + 1));
     w.counters = (uint32_t *)take(sizeof(uint32_t) * 64);
-    if (p.algo == HM_RASTER_TILED) {
+    if (p.algo != HM_RASTER_DIRECT) {
         w.long_list = (uint32_t *)take(sizeof(uint32_t) * units);
         w.entries = (uint32_t *)take(sizeof(uint32_t) * units * p.max_tiles_per_seg);
     } else {
@@ -696,7 +855,10 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
     return w;
 }
 
-uint32_t raster_lds_bytes(const hm_raster_params &p) { return tile_lds_bytes(p.tile, p.block); }
+uint32_t raster_lds_bytes(const hm_raster_params &p)
+{
+    return tile_lds_bytes(p.tile, p.block, p.algo == HM_RASTER_TILED);
+}
 
 size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p)
 {
@@ -711,7 +873,7 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.tile = 32;
     p.chunk = 512;
     p.max_tiles_per_seg = 4;
-    p.block = 512;
+    p.block = 256;
     p.grid = 0;
     p.shared_views = 0;
 }
@@ -723,7 +885,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     const RasterK rk = make_rk(f, p);
     RasterWs w = carve(ws, f, s.cap, p);
     const size_t npix = (size_t)f.width * f.height * f.n_scenes;
-    const bool tiled = p.algo == HM_RASTER_TILED;
+    const bool tiled = p.algo != HM_RASTER_DIRECT;
     hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
                        cams, f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
                        tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
@@ -738,7 +900,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         return;
     }
     const uint32_t nt = rk.n_tiles;
-    const uint32_t gb = stride_grid(units, 256);
+    const uint32_t gb = stride_grid((units + BIN_SUB - 1) / BIN_SUB, 256);
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 0, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);
@@ -756,12 +918,23 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
                        w.counters);
     if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
-    const uint32_t lds = tile_lds_bytes(p.tile, p.block);
+    const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
-    hipLaunchKernelGGL(k_raster_tiles, dim3(grid), dim3(p.block), lds, st,
-                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,
-                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
-                       (const uint32_t *)w.entries, w.counters, vis);
+#define HM_TILES_LAUNCH(FL, NB)                                                                \
+    hipLaunchKernelGGL((k_raster_tiles<FL, NB>), dim3(grid), dim3(p.block), lds, st,             \
+                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,  \
+                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,          \
+                       (const uint32_t *)w.entries, w.counters, vis)
+    if (p.algo == HM_RASTER_TILED) {
+        if (p.block == 256) HM_TILES_LAUNCH(true, 256);
+        else if (p.block == 128) HM_TILES_LAUNCH(true, 128);
+        else HM_TILES_LAUNCH(true, 0);
+    } else {
+        if (p.block == 512) HM_TILES_LAUNCH(false, 512);
+        else if (p.block == 256) HM_TILES_LAUNCH(false, 256);
+        else HM_TILES_LAUNCH(false, 0);
+    }
+#undef HM_TILES_LAUNCH
     hipLaunchKernelGGL(k_raster_long, dim3(256), dim3(256), 0, st, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, cams, rk, s.cap,
                        (const uint32_t *)w.long_list, (const uint32_t *)w.counters, vis);

@@ -147,13 +147,78 @@ constexpr int FT = 16;          // output tile edge
 constexpr int RMAX = 8;         // largest supported radius
 constexpr int HALO_MAX = FT + 2 * RMAX;
 
+// Filter state of one output pixel: strip counts for alpha and the
+// exponent-shifted weighted colour sum.
+struct FilterAcc {
+    float Sx, Sy, Sz, Wsum, emax;
+    int Hc, Ha;
+    bool acc;               // some neighbour was accepted (the reconstruction exists)
+};
+
+// Per-pixel constants of the taps.  Exponents are in log2 units: a tap's
+// weight is 2^(e - emax) with
+//   e = -(pw^2 A + cw^2 B) - |C_P - C_Q|^2 Csc,
+// pw, cw the offset's components along / across the weight tangent (for the
+// isotropic fallback the tangent is (1, 0) and A = B).  When the centre sample
+// is a hit whose colour the filter compares against, the centre tap has
+// e = 0 >= every other e, so emax = 0 from the start; otherwise emax follows
+// the running maximum (a far-off strand would underflow every weight).
+struct FilterPix {
+    float Tx, Ty;           // binary32 strip tangent (0, 0 in the isotropic case)
+    float Tw0, Tw1;         // weight tangent
+    float A, B, Csc;
+    float Cx, Cy, Cz;       // centre colour
+    uint32_t qP, dq_rej;
+    float strip2;
+    bool track_max;
+};
+
+__device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, float fx, float fy,
+                                           float4 Q)
+{
+    const uint32_t bits = __float_as_uint(Q.w);
+    const bool qh = (bits >> 24) & 1u, qany = (bits >> 25) & 1u;
+    // strip membership in binary32, evaluated exactly as written (a zero
+    // tangent gives fx^2 + fy^2 bit for bit)
+    const float par = fx * f.Tx + fy * f.Ty;
+    const float ex = fx - par * f.Tx, ey = fy - par * f.Ty;
+    const float perp2 = ex * ex + ey * ey;
+    const bool in_strip = perp2 <= f.strip2;
+    a.Ha += (in_strip & qany) ? 1 : 0;
+    a.Hc += (in_strip & qh) ? 1 : 0;
+    const uint32_t qq = bits & 0xFFFFFFu;
+    const uint32_t dq = qq > f.qP ? qq - f.qP : f.qP - qq;
+    const bool take = qh & (dq <= f.dq_rej);
+    // continuous weight (tolerance-compared): fused multiply-adds are fine here
+    const float pw = fmaf(fx, f.Tw0, fy * f.Tw1);
+    const float cw = fmaf(fx, f.Tw1, -(fy * f.Tw0));
+    const float d0 = f.Cx - Q.x, d1 = f.Cy - Q.y, d2 = f.Cz - Q.z;
+    const float dc = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
+    const float e = -fmaf(pw * pw, f.A, fmaf(cw * cw, f.B, dc * f.Csc));
+    if (f.track_max && take && e > a.emax) {
+        const float sc = __builtin_amdgcn_exp2f(a.emax - e);
+        a.Sx *= sc; a.Sy *= sc; a.Sz *= sc; a.Wsum *= sc;
+        a.emax = e;
+    }
+    const float w = take ? __builtin_amdgcn_exp2f(e - a.emax) : 0.0f;
+    a.Sx = fmaf(w, Q.x, a.Sx);
+    a.Sy = fmaf(w, Q.y, a.Sy);
+    a.Sz = fmaf(w, Q.z, a.Sz);
+    a.Wsum += w;
+    a.acc |= take;
+}
+
+// R > 0: the radius is a compile-time constant (each row of taps unrolls into
+// LDS reads at fixed offsets); R = 0: any radius up to RMAX, read from k.r.
+template <int R>
 __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_t *vis,
                                                 const hm_camera *cams, uint32_t W, uint32_t H,
                                                 ShadeK k, const float4 *rec, float4 *out)
 {
-    __shared__ float4 tile[HALO_MAX * HALO_MAX];
-    const int r = k.r;
-    const int E = FT + 2 * r;
+    constexpr int EMAX = R > 0 ? FT + 2 * R : HALO_MAX;
+    __shared__ float4 tile[EMAX * EMAX];
+    const int r = R > 0 ? R : k.r;
+    const int E = R > 0 ? EMAX : FT + 2 * r;
     const uint32_t tiles_x = (W + FT - 1) / FT;
     const uint32_t tiles_y = (H + FT - 1) / FT;
     const uint32_t s = blockIdx.x / (tiles_x * tiles_y);
@@ -185,97 +250,73 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     const bool mism = hc && ha && qc > qa && (qc - qa) >= k.dq_mis;
     const uint64_t src = (hc && !mism) ? kc : ka;
     const uint32_t vs = (uint32_t)(src & HM_ID_MASK);
-    const uint32_t qP = (uint32_t)(src >> HM_ID_BITS);
     const Cam c = load_cam(cams + s);
     const float4 pa = project(c, pos[vs]), pb = project(c, pos[vs + 1]);
     const float tdx = pb.x - pa.x, tdy = pb.y - pa.y;
     const float tlen = sqrtf(tdx * tdx + tdy * tdy);
     const bool iso = !(tlen >= k.iso_len);
-    // binary32 tangent: strip membership decision (same bits as any IEEE
-    // evaluation); binary64 tangent: the continuous filter weights
-    float Tx = 0.0f, Ty = 0.0f, Twx = 0.0f, Twy = 0.0f;
+    const float4 CP = tile[(lj + r) * E + (li + r)];
+    const bool colour_sim = hc && !mism;
+    constexpr float LOG2E = 1.44269504088896340736f;
+    FilterPix f;
+    f.Tx = 0.0f; f.Ty = 0.0f;
+    f.Tw0 = 1.0f; f.Tw1 = 0.0f;
+    f.A = k.inv_siso2 * LOG2E;
+    f.B = f.A;
     if (!iso) {
+        // binary32 tangent: strip membership decision (same bits as any IEEE
+        // evaluation); binary64 tangent: the continuous filter weights
         const float il = 1.0f / tlen;
-        Tx = tdx * il;
-        Ty = tdy * il;
+        f.Tx = tdx * il;
+        f.Ty = tdy * il;
         const DProj da = project_d(c, pos[vs]), db = project_d(c, pos[vs + 1]);
         const double ddx = db.x - da.x, ddy = db.y - da.y;
         const double dl = sqrt(ddx * ddx + ddy * ddy);
-        Twx = (float)(ddx / dl);
-        Twy = (float)(ddy / dl);
+        f.Tw0 = (float)(ddx / dl);
+        f.Tw1 = (float)(ddy / dl);
+        f.A = k.inv_spar2 * LOG2E;
+        f.B = k.inv_sperp2 * LOG2E;
     }
-    const float4 CP = tile[(lj + r) * E + (li + r)];
-    const bool colour_sim = hc && !mism;
-    // normalised sum with a running exponent shift: sum_q exp(e_q - m) C_q /
-    // sum_q exp(e_q - m), m = max e_q so far (no underflow of the weight sum)
-    float Sx = 0.f, Sy = 0.f, Sz = 0.f, Wsum = 0.f, emax = -INFINITY;
-    int Hc = 0, Ha = 0, nacc = 0;
-    for (int oy = -r; oy <= r; ++oy) {
-        const float4 *row = tile + (lj + r + oy) * E + (li + r);
-        const float fy = (float)oy;
-        for (int ox = -r; ox <= r; ++ox) {
-            const float4 Q = row[ox];
-            const uint32_t bits = __float_as_uint(Q.w);
-            const bool qh = (bits >> 24) & 1u, qany = (bits >> 25) & 1u;
-            const float fx = (float)ox;
-            float par, perp2;
-            if (iso) {
-                par = 0.0f;
-                perp2 = fx * fx + fy * fy;
-            } else {
-                par = fx * Tx + fy * Ty;
-                const float ex = fx - par * Tx, ey = fy - par * Ty;
-                perp2 = ex * ex + ey * ey;
-            }
-            if (perp2 <= k.strip2) {
-                Ha += qany ? 1 : 0;
-                Hc += qh ? 1 : 0;
-            }
-            if (!qh) continue;
-            const uint32_t qq = bits & 0xFFFFFFu;
-            const uint32_t dq = qq > qP ? qq - qP : qP - qq;
-            if (dq > k.dq_rej) continue;
-            float e;
-            if (iso) {
-                e = -(perp2 * k.inv_siso2);
-            } else {
-                const float pw = fx * Twx + fy * Twy;        // d_par with the accurate tangent
-                const float cw = fx * Twy - fy * Twx;        // signed d_perp
-                e = -(pw * pw * k.inv_spar2) - cw * cw * k.inv_sperp2;
-            }
-            if (colour_sim) {
-                const float d0 = CP.x - Q.x, d1 = CP.y - Q.y, d2 = CP.z - Q.z;
-                e -= (d0 * d0 + d1 * d1 + d2 * d2) * k.inv_sc2;
-            }
-            if (e > emax) {
-                const float sc = __expf(emax - e);   // weights: ~1e-6 relative suffices
-                Sx *= sc; Sy *= sc; Sz *= sc; Wsum *= sc;
-                emax = e;
-            }
-            const float w = __expf(e - emax);
-            Sx += w * Q.x;
-            Sy += w * Q.y;
-            Sz += w * Q.z;
-            Wsum += w;
-            ++nacc;
+    f.Csc = colour_sim ? k.inv_sc2 * LOG2E : 0.0f;
+    f.Cx = CP.x; f.Cy = CP.y; f.Cz = CP.z;
+    f.qP = (uint32_t)(src >> HM_ID_BITS);
+    f.dq_rej = k.dq_rej;
+    f.strip2 = k.strip2;
+    f.track_max = !colour_sim;
+    FilterAcc a;
+    a.Sx = a.Sy = a.Sz = a.Wsum = 0.0f;
+    a.emax = colour_sim ? 0.0f : -INFINITY;
+    a.Hc = a.Ha = 0;
+    a.acc = false;
+    const float4 *ctr = tile + (lj + r) * E + (li + r);
+    if (R > 0) {
+#pragma unroll 1
+        for (int oy = -R; oy <= R; ++oy) {
+            const float4 *row = ctr + oy * EMAX;
+#pragma unroll
+            for (int ox = -R; ox <= R; ++ox) filter_tap(f, a, (float)ox, (float)oy, row[ox]);
         }
+    } else {
+        for (int oy = -r; oy <= r; ++oy)
+            for (int ox = -r; ox <= r; ++ox)
+                filter_tap(f, a, (float)ox, (float)oy, ctr[oy * E + ox]);
     }
-    const float aP = Ha > 0 ? (float)Hc / (float)Ha : 1.0f;
+    const float aP = a.Ha > 0 ? (float)a.Hc / (float)a.Ha : 1.0f;
     float rr = 0.f, gg = 0.f, bb = 0.f, alpha = 0.f;
     if (hc && !mism) {
-        rr = Sx / Wsum; gg = Sy / Wsum; bb = Sz / Wsum;
+        rr = a.Sx / a.Wsum; gg = a.Sy / a.Wsum; bb = a.Sz / a.Wsum;
         alpha = aP;
     } else if (mism) {
         float cr = CP.x, cg = CP.y, cb = CP.z;
-        if (nacc > 0) {
-            cr = Sx / Wsum; cg = Sy / Wsum; cb = Sz / Wsum;
+        if (a.acc) {
+            cr = a.Sx / a.Wsum; cg = a.Sy / a.Wsum; cb = a.Sz / a.Wsum;
         }
         rr = aP * cr + (1.0f - aP) * CP.x;
         gg = aP * cg + (1.0f - aP) * CP.y;
         bb = aP * cb + (1.0f - aP) * CP.z;
         alpha = 1.0f;
-    } else if (nacc > 0) {
-        rr = Sx / Wsum; gg = Sy / Wsum; bb = Sz / Wsum;
+    } else if (a.acc) {
+        rr = a.Sx / a.Wsum; gg = a.Sy / a.Wsum; bb = a.Sz / a.Wsum;
         alpha = aP;
     }
     *o = make_float4(alpha * rr + (1.0f - alpha) * k.bgr, alpha * gg + (1.0f - alpha) * k.bgg,
@@ -354,8 +395,13 @@ void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *c
                        (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k, rec,
                        (float4 *)nullptr);
     const uint32_t tiles = ((f.width + FT - 1) / FT) * ((f.height + FT - 1) / FT) * f.n_scenes;
-    hipLaunchKernelGGL(k_filter, dim3(tiles), dim3(FT * FT), 0, st, pos, vis, cams, f.width,
-                       f.height, k, (const float4 *)rec, o);
+    if (k.r == 5) {             // the paper's radius: unrolled taps
+        hipLaunchKernelGGL(k_filter<5>, dim3(tiles), dim3(FT * FT), 0, st, pos, vis, cams,
+                           f.width, f.height, k, (const float4 *)rec, o);
+    } else {
+        hipLaunchKernelGGL(k_filter<0>, dim3(tiles), dim3(FT * FT), 0, st, pos, vis, cams,
+                           f.width, f.height, k, (const float4 *)rec, o);
+    }
 }
 
 // ------------------------------------------------------------------ soft backward

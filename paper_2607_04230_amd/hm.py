@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhm.so")
 
 HM_OK = 0
 LOD_OFF, LOD_ON = 0, 1
-RASTER_TILED, RASTER_DIRECT = 0, 1
+RASTER_TILED, RASTER_DIRECT, RASTER_TILED_ROWS = 0, 1, 2
 RESOLVE_FILTER, RESOLVE_SOFT, RESOLVE_CENTER = 0, 1, 2
 CALL_LOD, CALL_RASTER, CALL_RESOLVE = 0, 1, 2
 
@@ -282,8 +282,9 @@ def timing_collect() -> dict:
     out = {}
     for line in buf.value.decode().splitlines():
         name, ms, n = line.rsplit(" ", 2)
-        out[name.split("<")[0]] = (out.get(name.split("<")[0], (0.0, 0))[0] + float(ms),
-                                   out.get(name.split("<")[0], (0.0, 0))[1] + int(n))
+        base = name.lstrip("(").split("<")[0]          # template arguments folded
+        t, c = out.get(base, (0.0, 0))
+        out[base] = (t + float(ms), c + int(n))
     return out
 
 

@@ -62,6 +62,18 @@ def test_validation_errors_are_reported():
                                ctypes.byref(out)) == 2
     assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 0xFFFFFFFF, None,
                                ctypes.byref(out)) == 2
+    # the per-pixel tile expansion takes at most 256 threads; the row walker more
+    p = hm.raster_defaults(fr)
+    p.block = 512
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 10, ctypes.byref(p),
+                               ctypes.byref(out)) == 2
+    assert b"256" in L.hm_last_error()
+    p.algo = hm.RASTER_TILED_ROWS
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 10, ctypes.byref(p),
+                               ctypes.byref(out)) == 0
+    p.algo = 5
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 10, ctypes.byref(p),
+                               ctypes.byref(out)) == 1
     # NULL strands / arrays -> invalid, before any launch
     st = hm.Strands(None, None, None, None, 1, 10)
     rp = hm.raster_defaults(fr)

@@ -69,9 +69,12 @@ def test_tiny_end_to_end(O, torch):
     (hm.RASTER_DIRECT, 32, 256, 4, 256),
     (hm.RASTER_TILED, 8, 64, 2, 64),
     (hm.RASTER_TILED, 16, 1, 8, 128),
-    (hm.RASTER_TILED, 32, 4096, 64, 512),
+    (hm.RASTER_TILED, 32, 4096, 64, 256),
     (hm.RASTER_TILED, 16, 300, 3, 128),
     (hm.RASTER_TILED, 32, 100, 1, 256),
+    (hm.RASTER_TILED_ROWS, 8, 64, 2, 64),
+    (hm.RASTER_TILED_ROWS, 32, 4096, 64, 512),
+    (hm.RASTER_TILED_ROWS, 16, 300, 3, 128),
 ])
 def test_tiny_vis_invariant_to_launch_shape(O, torch, algo, tile, chunk, K, block):
     sc = scenes.config_tiny()

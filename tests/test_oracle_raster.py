@@ -226,3 +226,41 @@ def test_scene_depth_prefill_occludes(O):
     assert (ids[0, 8, :8] == opaque).all()              # wall wins on the left
     assert (ids[0, 8, 9:13] == 0).all()                 # strand visible on the right
     assert (int(vis[0, 0, 0]) >> 40) == O.qdepth(1.0, 0.5, 2.0)
+
+
+def test_cover_counts_equal_per_segment_rasters(O):
+    # the raster's work count is the number of (segment, pixel) pairs each
+    # predicate accepts: rasterizing every segment alone and counting its
+    # non-empty pixels must give the same totals
+    for seed in range(3):
+        sc = scenes.micro_scene(seed)
+        t, soff, (_, ncp) = O.lod_select(sc)
+        pos, _, fl = O.generate(sc, t, ncp)
+        for r_min in (0.0, 0.5):
+            seg, uc, ua = O.cover_counts(pos, fl, soff, sc.cams, sc.width, sc.height, r_min)
+            n, c0, c1 = 0, 0, 0
+            for v in range(ncp - 1):
+                if fl[v] & 2:                    # tip: no segment starts here
+                    continue
+                one = np.ascontiguousarray(pos[v:v + 2])
+                vis = O.raster(one, np.array([1, 2], np.uint8), np.array([0, 2], np.uint32),
+                               sc.cams, sc.width, sc.height, r_min)
+                n += 1
+                c0 += int((vis[0, 0] != EMPTY).sum())
+                c1 += int((vis[0, 1] != EMPTY).sum())
+            assert (seg, uc, ua) == (n, c0, c1)
+            assert 0 < uc <= ua
+
+
+def test_stored_work_counts_match_the_oracle(O):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "work_counts.json")) as f:
+        stored = json.load(f)["head"]
+    sc = scenes.config_head()
+    t, soff, (ns, ncp) = O.lod_select(sc)
+    pos, _, fl = O.generate(sc, t, ncp)
+    seg, uc, ua = O.cover_counts(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min)
+    assert (ns, ncp, seg, uc, ua) == (stored["strands"], stored["control_points"],
+                                      stored["segments"], stored["centre_pairs"],
+                                      stored["conservative_pairs"])
