@@ -182,7 +182,10 @@ static hm_status make_shade(const hm_shade_params *p, ShadeK &k)
     // mismatch when nearer by >= ceil(t 2^24)
     k.dq_rej = (uint32_t)floor((double)p->depth_reject * 16777216.0);
     k.dq_mis = (uint32_t)ceil((double)p->depth_mismatch * 16777216.0);
+    REQUIRE(isfinite(p->strip_half) && p->strip_half >= 0.0f && p->strip_half <= 16.0f,
+            HM_ERR_RANGE, "strip_half outside [0, 16]");
     const float h = p->strip_half;
+    k.strip_half = h;
     k.strip2 = h * h;
     k.iso_len = p->iso_len;
     k.soft_k = (float)(1.0 / ((double)p->soft_sigma * sqrt(2.0)));

@@ -19,7 +19,8 @@ struct ShadeK {
     int r;                     // filter radius
     float inv_spar2, inv_sperp2, inv_siso2, inv_sc2;
     uint32_t dq_rej, dq_mis;   // depth thresholds in 24-bit code units
-    float strip2;              // squared strip half width (binary32)
+    float strip_half;          // strip half width (px)
+    float strip2;              // its square (binary32)
     float iso_len;
     float soft_k;              // 1 / (sigma * sqrt(2))
     float bgr, bgg, bgb;

@@ -246,7 +246,19 @@ __device__ __forceinline__ bool seg_tiles(const float4 *proj, const uint8_t *fla
     if (u >= unit_count(n, rk)) return false;
     uint32_t v;
     unit_map(scene_off, rk, n, u, st.s, v);
-    if (!load_seg(proj, flags, u, v, n, rk.r_min, st.sg)) return false;
+    if (v + 1 >= n || (flags[v] & HM_TIP)) return false;
+    const float4 a = proj[u], b = proj[u + 1];
+    if (a.w == 0.0f || b.w == 0.0f) return false;
+    // the fields of make_seg that the tile tests read, computed the same way
+    Seg &sg = st.sg;
+    sg = Seg{};
+    sg.x0 = a.x;
+    sg.y0 = a.y;
+    sg.dx = b.x - a.x;
+    sg.dy = b.y - a.y;
+    sg.ra = fmaxx(0.5f * fmaxx(a.z, b.z), rk.r_min);
+    sg.sxmn = fminx(a.x, b.x); sg.sxmx = fmaxx(a.x, b.x);
+    sg.symn = fminx(a.y, b.y); sg.symx = fmaxx(a.y, b.y);
     int i0, i1, j0, j1;
     if (!seg_box(st.sg, rk.W, rk.H, i0, i1, j0, j1)) return false;
     st.tx0 = (uint32_t)i0 / rk.T;
@@ -256,19 +268,28 @@ __device__ __forceinline__ bool seg_tiles(const float4 *proj, const uint8_t *fla
     return true;
 }
 
-// k-th tile of the segment's tile box; returns false when the segment cannot
-// reach it.
-__device__ __forceinline__ bool seg_tile_k(const SegTiles &st, const RasterK &rk, uint32_t k,
-                                           uint32_t &tile)
+// Tile (tx0 + kx, ty0 + ky) of the segment's tile box; returns false when the
+// segment cannot reach it.  A box of a single tile needs no test (an extra
+// pair would be harmless: the raster tests every pixel exactly).
+__device__ __forceinline__ bool seg_tile_at(const SegTiles &st, const RasterK &rk, uint32_t kx,
+                                            uint32_t ky, uint32_t &tile)
 {
-    const uint32_t tx = st.tx0 + k % st.bw, ty = st.ty0 + k / st.bw;
-    const float px0 = (float)(tx * rk.T), py0 = (float)(ty * rk.T);
+    const uint32_t tx = st.tx0 + kx, ty = st.ty0 + ky;
     tile = (st.s * rk.nty + ty) * rk.ntx + tx;
+    if (st.nt == 1u) return true;
+    const float px0 = (float)(tx * rk.T), py0 = (float)(ty * rk.T);
     return seg_hits_box(st.sg, px0, px0 + (float)rk.T, py0, py0 + (float)rk.T);
 }
 
 constexpr uint32_t BIN_SLOTS = 1024;      // LDS hash slots per workgroup
-constexpr uint32_t BIN_SUB = 8;           // segments per thread between table flushes
+#ifndef HM_BIN_SUB
+#define HM_BIN_SUB 8
+#endif
+#ifndef HM_BIN_BLOCK
+#define HM_BIN_BLOCK 256
+#endif
+constexpr uint32_t BIN_SUB = HM_BIN_SUB;      // segments per thread between table flushes
+constexpr uint32_t BIN_BLOCK = HM_BIN_BLOCK;  // threads per binning workgroup
 constexpr uint32_t BIN_FREE = 0xFFFFFFFFu;
 
 // Slot of `tile` in the workgroup's LDS table (linear probing), -1 if full.
@@ -291,7 +312,7 @@ __device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
 //           long list;
 //   pass 1: one returning global add per (workgroup, tile) reserves a range
 //           of the tile's list; pairs then take LDS-atomic ranks inside it.
-__global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const uint8_t *flags,
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, const float4 *proj, const uint8_t *flags,
                                              const uint32_t *scene_off, RasterK rk, uint32_t cap,
                                              uint32_t *tile_cnt, const uint32_t *tile_off,
                                              uint32_t *tile_cur, uint32_t *entries,
@@ -300,7 +321,7 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
-    const uint32_t span = blockDim.x * BIN_SUB;     // segments per table flush
+    const uint32_t span = BIN_BLOCK * BIN_SUB;     // segments per table flush
     // v below is a segment unit (see unit_map); lists store units
     for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
         for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
@@ -317,9 +338,10 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
                 ok = false;
             }
             if (!ok) continue;
-            for (uint32_t k = 0; k < st.nt; ++k) {
+            for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
+            for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
                 uint32_t tile;
-                if (!seg_tile_k(st, rk, k, tile)) continue;
+                if (!seg_tile_at(st, rk, kx, ky, tile)) continue;
                 const int sl = bin_slot(keys, tile);
                 if (sl >= 0) atomicAdd(&cnt[sl], 1u);
                 else if (pass == 0) atomicAdd(&tile_cnt[tile], 1u);
@@ -343,9 +365,10 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
                 const uint32_t v = base + sub * blockDim.x + threadIdx.x;
                 SegTiles st;
                 if (!seg_tiles(proj, flags, scene_off, rk, v, n, st) || st.nt > rk.K) continue;
-                for (uint32_t k = 0; k < st.nt; ++k) {
+                for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
+                for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
                     uint32_t tile;
-                    if (!seg_tile_k(st, rk, k, tile)) continue;
+                    if (!seg_tile_at(st, rk, kx, ky, tile)) continue;
                     // the slot exists already unless the table was full when
                     // the pair was inserted (it was then written directly)
                     const uint32_t h = (tile * 2654435761u) >> 22;
@@ -362,6 +385,14 @@ __global__ __launch_bounds__(256) void k_bin(int pass, const float4 *proj, const
         }
         __syncthreads();
     }
+}
+
+// Orders the LDS accesses of one wave around a hand-off between its lanes.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // items per tile = ceil(count / chunk); also resets the cursors.
@@ -418,10 +449,15 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint3
 // Per-segment records of a batch, struct of arrays with stride nb (fields a
 // caller does not use are not read: the loads are plain LDS reads): the 16
 // geometric fields of Seg (the slack e is recomputed from them), then the
-// stream id, the segment's first row slot, and its row / column clip inside
-// the tile packed as (j0 - py0) | (i0 - px0) << 8 | (i1 - px0) << 16.
+// stream id, then the segment's first row slot (15 bits: at most 1024 * 32
+// slots) with its row / column clip inside the tile (5 bits each, T <= 32):
+// slot | (j0 - py0) << 15 | (i0 - px0) << 20 | (i1 - px0) << 25.
 constexpr uint32_t REC_FLOATS = 16;
-constexpr uint32_t REC_WORDS = REC_FLOATS + 3;
+constexpr uint32_t REC_WORDS = REC_FLOATS + 2;
+__device__ __forceinline__ uint32_t rc_slot(uint32_t rc) { return rc & 0x7FFFu; }
+__device__ __forceinline__ int rc_j0(uint32_t rc) { return (int)((rc >> 15) & 31u); }
+__device__ __forceinline__ int rc_i0(uint32_t rc) { return (int)((rc >> 20) & 31u); }
+__device__ __forceinline__ int rc_i1(uint32_t rc) { return (int)(rc >> 25); }
 
 __device__ __forceinline__ void rec_store(float *rf, uint32_t nb, uint32_t k, const Seg &s)
 {
@@ -469,26 +505,19 @@ __device__ __forceinline__ bool tile_rows(const Seg &sg, int px0, int px1, int &
     return j0 <= j1;
 }
 
-// Orders the LDS accesses of one wave around a hand-off between its lanes.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Pixel slots of one wave's pixel -> row map (bytes); rows whose candidate
 // pixels exceed it are spread in several windows.
 constexpr uint32_t PIX_WINDOW = 256;
 
 // dynamic LDS bytes of k_raster_tiles for tile edge T and `block` threads:
 // two layers of keys and the segment records; for the per-pixel spread also
-// the row-start bitmap (block * T bits), each wave's pixel -> row window and
-// its 64 row descriptors (2 words each)
+// the row-start bitmap (block * T bits) and each wave's window of pixel
+// descriptors (one word each).  T = 32 with 256 threads takes 39936 B, so
+// four workgroups fit a CU's 160 KiB.
 static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat)
 {
     uint32_t b = 2u * T * T * 8u + block * 4u * REC_WORDS;
-    if (flat) b += block * T / 8u + (block / 64u) * (PIX_WINDOW + 64u * 8u);
+    if (flat) b += block * T / 8u + (block / 64u) * PIX_WINDOW * 4u;
     return b;
 }
 
@@ -525,17 +554,15 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
     float *rf = reinterpret_cast<float *>(lds + 2 * TT);
     uint32_t *rw = reinterpret_cast<uint32_t *>(rf);
     uint32_t *r_sid = rw + REC_FLOATS * nb;          // stream id
-    uint32_t *r_row = r_sid + nb;                    // first row slot
-    uint32_t *r_clip = r_row + nb;                   // packed row / column clip
+    uint32_t *r_rc = r_sid + nb;                     // first row slot + clip
     // per-pixel spread only
     const uint32_t wv = threadIdx.x >> 6;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t nw = nb >> 6;
     const uint32_t bmp_words = nb * rk.T / 32u;
-    uint32_t *bmp = r_clip + nb;
-    uint8_t *prow = reinterpret_cast<uint8_t *>(bmp + bmp_words) + wv * PIX_WINDOW;
-    uint32_t *rdesc = reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(bmp + bmp_words) +
-                                                   nw * PIX_WINDOW) + wv * 128u;
+    uint32_t *bmp = r_rc + nb;
+    // pixel descriptors: segment | (j - py0) << 8 | (i - px0) << 13
+    uint32_t *pdesc = bmp + bmp_words + wv * PIX_WINDOW;
 
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_items = item_off[rk.n_tiles];
@@ -615,9 +642,8 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                 const uint32_t c = pre >> 16, r0 = pre & 0xFFFFu;
                 rec_store(rf, nb, c, sg);
                 r_sid[c] = vu;
-                r_row[c] = r0;
-                r_clip[c] = (uint32_t)(j0 - py0) | ((uint32_t)(i0 - px0) << 8) |
-                            ((uint32_t)(i1 - px0) << 16);
+                r_rc[c] = r0 | ((uint32_t)(j0 - py0) << 15) | ((uint32_t)(i0 - px0) << 20) |
+                          ((uint32_t)(i1 - px0) << 25);
                 if (FLAT) atomicOr(&bmp[r0 >> 5], 1u << (r0 & 31u));
             }
             __syncthreads();
@@ -632,7 +658,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     uint32_t l2 = 0, h2 = nseg;      // first rows increase strictly
                     while (l2 < h2) {
                         const uint32_t mid = (l2 + h2) >> 1;
-                        if (r_row[mid] < g0 * 64u) l2 = mid + 1; else h2 = mid;
+                        if (rc_slot(r_rc[mid]) < g0 * 64u) l2 = mid + 1; else h2 = mid;
                     }
                     before = l2;
                 }
@@ -646,34 +672,32 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     uint32_t c = 0, d0 = 0;
                     if (rr < tot) {
                         const Seg sr = rec_load(rf, nb, o);
-                        const uint32_t clip = r_clip[o];
-                        const int j = py0 + (int)(clip & 0xFFu) + (int)(rr - r_row[o]);
+                        const uint32_t rc = r_rc[o];
+                        const int j = py0 + rc_j0(rc) + (int)(rr - rc_slot(rc));
                         int a0, a1;
                         row_span(sr, j, a0, a1);
-                        a0 = max(a0, px0 + (int)((clip >> 8) & 0xFFu));
-                        a1 = min(a1, px0 + (int)(clip >> 16));
+                        a0 = max(a0, px0 + rc_i0(rc));
+                        a1 = min(a1, px0 + rc_i1(rc));
                         if (a1 >= a0) c = (uint32_t)(a1 - a0 + 1);
-                        d0 = o | ((uint32_t)(j - py0) << 8) | ((uint32_t)(a0 - px0) << 16);
+                        d0 = o | ((uint32_t)(j - py0) << 8) | ((uint32_t)(a0 - px0) << 13);
                     }
                     const uint32_t inc = wave_inclusive_scan(c);
                     const uint32_t pc = inc - c;
                     const uint32_t P = __shfl(inc, 63, 64);
-                    rdesc[lane] = d0;
-                    rdesc[64 + lane] = pc;
                     for (uint32_t w0 = 0; w0 < P; w0 += PIX_WINDOW) {
                         const uint32_t m0 = pc > w0 ? pc : w0;
                         const uint32_t m1 = min(pc + c, w0 + PIX_WINDOW);
-                        for (uint32_t m = m0; m < m1; ++m) prow[m - w0] = (uint8_t)lane;
+                        // descriptor of pixel a0 + (m - pc) of this lane's row
+                        for (uint32_t m = m0; m < m1; ++m) pdesc[m - w0] = d0 + ((m - pc) << 13);
                         wave_sync();
                         const uint32_t wl = min(P - w0, PIX_WINDOW);
                         for (uint32_t p0 = 0; p0 < wl; p0 += 64) {
                             const uint32_t pl = p0 + lane;
                             if (pl < wl) {
-                                const uint32_t rl = prow[pl];
-                                const uint32_t d = rdesc[rl], pr = rdesc[64 + rl];
+                                const uint32_t d = pdesc[pl];
                                 const uint32_t ow = d & 0xFFu;
-                                const int j = py0 + (int)((d >> 8) & 0xFFu);
-                                const int i = px0 + (int)(d >> 16) + (int)(w0 + pl - pr);
+                                const int j = py0 + (int)((d >> 8) & 31u);
+                                const int i = px0 + (int)(d >> 13);
                                 const Seg sp = rec_load(rf, nb, ow);
                                 uint32_t q;
                                 const uint32_t msk = cover(sp, i, j, rk.r_min, zn, inv_range, q);
@@ -699,28 +723,28 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     uint32_t h2 = nseg;
                     while (h2 - ow > 1) {
                         const uint32_t mid = (ow + h2) >> 1;
-                        if (r_row[mid] <= r_beg) ow = mid; else h2 = mid;
+                        if (rc_slot(r_rc[mid]) <= r_beg) ow = mid; else h2 = mid;
                     }
                 }
-                uint32_t cur = 0xFFFFFFFFu, vo = 0, clip = 0;
+                uint32_t cur = 0xFFFFFFFFu, vo = 0, rc = 0;
                 Seg sr;
                 int jb = 0;
                 uint32_t pb = 0;
                 for (uint32_t rr = r_beg; rr < r_end; ++rr) {
-                    while (ow + 1 < nseg && r_row[ow + 1] <= rr) ++ow;
+                    while (ow + 1 < nseg && rc_slot(r_rc[ow + 1]) <= rr) ++ow;
                     if (ow != cur) {
                         cur = ow;
                         sr = rec_load(rf, nb, ow);
                         vo = r_sid[ow];
-                        clip = r_clip[ow];
-                        jb = py0 + (int)(clip & 0xFFu);
-                        pb = r_row[ow];
+                        rc = r_rc[ow];
+                        jb = py0 + rc_j0(rc);
+                        pb = rc_slot(rc);
                     }
                     const int j = jb + (int)(rr - pb);
                     int a0, a1;
                     row_span(sr, j, a0, a1);
-                    a0 = max(a0, px0 + (int)((clip >> 8) & 0xFFu));
-                    a1 = min(a1, px0 + (int)(clip >> 16));
+                    a0 = max(a0, px0 + rc_i0(rc));
+                    a1 = min(a1, px0 + rc_i1(rc));
                     for (int i = a0; i <= a1; ++i) {
                         uint32_t q;
                         const uint32_t msk = cover(sr, i, j, rk.r_min, zn, inv_range, q);
@@ -900,8 +924,8 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         return;
     }
     const uint32_t nt = rk.n_tiles;
-    const uint32_t gb = stride_grid((units + BIN_SUB - 1) / BIN_SUB, 256);
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 0, (const float4 *)w.proj,
+    const uint32_t gb = stride_grid((units + BIN_SUB - 1) / BIN_SUB, BIN_BLOCK);
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);
     const bool small = nt <= PLAN_SMALL;
@@ -913,7 +937,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         hipLaunchKernelGGL(k_tile_items, dim3((nt + 255) / 256), dim3(256), 0, st,
                            (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
     }
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(256), 0, st, 1, (const float4 *)w.proj,
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
                        w.counters);

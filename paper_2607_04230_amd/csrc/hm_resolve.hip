@@ -147,54 +147,41 @@ constexpr int FT = 16;          // output tile edge
 constexpr int RMAX = 8;         // largest supported radius
 constexpr int HALO_MAX = FT + 2 * RMAX;
 
-// Filter state of one output pixel: strip counts for alpha and the
-// exponent-shifted weighted colour sum.
+// Weighted colour sum of one output pixel, exponent-shifted.
 struct FilterAcc {
     float Sx, Sy, Sz, Wsum, emax;
-    int Hc, Ha;
     bool acc;               // some neighbour was accepted (the reconstruction exists)
 };
 
-// Per-pixel constants of the taps.  Exponents are in log2 units: a tap's
-// weight is 2^(e - emax) with
+// Per-pixel constants of the weight taps.  Exponents are in log2 units: a
+// tap's weight is 2^(e - emax) with
 //   e = -(pw^2 A + cw^2 B) - |C_P - C_Q|^2 Csc,
-// pw, cw the offset's components along / across the weight tangent (for the
-// isotropic fallback the tangent is (1, 0) and A = B).  When the centre sample
+// pw, cw the offset's components along / across the weight tangent (the
+// isotropic fallback has A = B).  The spatial part is the quadratic form
+//   qa fx^2 + qb fx fy + qc fy^2,
+// evaluated per row as fx (qa fx + qb fy) + qc fy^2.  When the centre sample
 // is a hit whose colour the filter compares against, the centre tap has
 // e = 0 >= every other e, so emax = 0 from the start; otherwise emax follows
 // the running maximum (a far-off strand would underflow every weight).
 struct FilterPix {
-    float Tx, Ty;           // binary32 strip tangent (0, 0 in the isotropic case)
-    float Tw0, Tw1;         // weight tangent
-    float A, B, Csc;
+    float qa, qb, qc;
+    float Csc;
     float Cx, Cy, Cz;       // centre colour
-    uint32_t qP, dq_rej;
-    float strip2;
+    uint32_t q_lo, q_span;  // accepted depth codes: (q - q_lo) mod 2^32 <= q_span
     bool track_max;
 };
 
-__device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, float fx, float fy,
-                                           float4 Q)
+__device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, float fx, float r1,
+                                           float r0, float4 Q)
 {
     const uint32_t bits = __float_as_uint(Q.w);
-    const bool qh = (bits >> 24) & 1u, qany = (bits >> 25) & 1u;
-    // strip membership in binary32, evaluated exactly as written (a zero
-    // tangent gives fx^2 + fy^2 bit for bit)
-    const float par = fx * f.Tx + fy * f.Ty;
-    const float ex = fx - par * f.Tx, ey = fy - par * f.Ty;
-    const float perp2 = ex * ex + ey * ey;
-    const bool in_strip = perp2 <= f.strip2;
-    a.Ha += (in_strip & qany) ? 1 : 0;
-    a.Hc += (in_strip & qh) ? 1 : 0;
-    const uint32_t qq = bits & 0xFFFFFFu;
-    const uint32_t dq = qq > f.qP ? qq - f.qP : f.qP - qq;
-    const bool take = qh & (dq <= f.dq_rej);
+    // centre-sample hit within the depth window [qP - rej, qP + rej]
+    const bool take = ((bits >> 24) & 1u) & (((bits & 0xFFFFFFu) - f.q_lo) <= f.q_span);
     // continuous weight (tolerance-compared): fused multiply-adds are fine here
-    const float pw = fmaf(fx, f.Tw0, fy * f.Tw1);
-    const float cw = fmaf(fx, f.Tw1, -(fy * f.Tw0));
+    const float esp = fmaf(fx, fmaf(f.qa, fx, r1), r0);
     const float d0 = f.Cx - Q.x, d1 = f.Cy - Q.y, d2 = f.Cz - Q.z;
     const float dc = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-    const float e = -fmaf(pw * pw, f.A, fmaf(cw * cw, f.B, dc * f.Csc));
+    const float e = -fmaf(dc, f.Csc, esp);
     if (f.track_max && take && e > a.emax) {
         const float sc = __builtin_amdgcn_exp2f(a.emax - e);
         a.Sx *= sc; a.Sy *= sc; a.Sz *= sc; a.Wsum *= sc;
@@ -206,6 +193,44 @@ __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, flo
     a.Sz = fmaf(w, Q.z, a.Sz);
     a.Wsum += w;
     a.acc |= take;
+}
+
+// Strip counts for alpha (Sec. 3.3): over the window taps whose distance to
+// the strand's screen line through the pixel is within the strip half width
+// h, count those with any hit (Ha) and with a centre hit (Hc).  Membership is
+// decided in binary32 exactly as perp2 = |o - (o.T) T|^2 <= h^2 (a zero
+// tangent, the isotropic case, gives |o|^2).  Only taps near the line are
+// tested: along the line's major axis every offset a in [-r, r] has its
+// minor-axis candidates in an interval of width 2h / |major component| around
+// the line, widened by 0.05 against rounding (an error of perp2 of a few ulp
+// of r^2 moves the boundary by far less).
+__device__ __forceinline__ void strip_counts(const float4 *tile, int E, int cx, int cy, int r,
+                                             float Tx, float Ty, float h, float h2, int &Hc,
+                                             int &Ha)
+{
+    Hc = 0;
+    Ha = 0;
+    const bool steep = fabsf(Ty) >= fabsf(Tx);      // iso (0, 0) counts as steep
+    const float M = steep ? Ty : Tx, m = steep ? Tx : Ty;
+    const float aM = fabsf(M);
+    const float slope = aM > 0.0f ? m / M : 0.0f;
+    const float half = (aM > 0.0f ? h / aM : h) + 0.05f;
+    for (int a = -r; a <= r; ++a) {
+        const float c = (float)a * slope;
+        const int b0 = max(-r, (int)ceilf(c - half)), b1 = min(r, (int)floorf(c + half));
+        for (int b = b0; b <= b1; ++b) {
+            const int ox = steep ? b : a, oy = steep ? a : b;
+            const float fx = (float)ox, fy = (float)oy;
+            const float par = fx * Tx + fy * Ty;
+            const float ex = fx - par * Tx, ey = fy - par * Ty;
+            const float perp2 = ex * ex + ey * ey;
+            if (perp2 <= h2) {
+                const uint32_t bits = __float_as_uint(tile[(cy + oy) * E + (cx + ox)].w);
+                Ha += (bits >> 25) & 1u;
+                Hc += (bits >> 24) & 1u;
+            }
+        }
+    }
 }
 
 // R > 0: the radius is a compile-time constant (each row of taps unrolls into
@@ -257,51 +282,57 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     const bool iso = !(tlen >= k.iso_len);
     const float4 CP = tile[(lj + r) * E + (li + r)];
     const bool colour_sim = hc && !mism;
-    constexpr float LOG2E = 1.44269504088896340736f;
-    FilterPix f;
-    f.Tx = 0.0f; f.Ty = 0.0f;
-    f.Tw0 = 1.0f; f.Tw1 = 0.0f;
-    f.A = k.inv_siso2 * LOG2E;
-    f.B = f.A;
+    constexpr double LOG2E = 1.4426950408889634074;
+    // binary32 tangent: strip membership decision (same bits as any IEEE
+    // evaluation); binary64 tangent: the continuous filter weights
+    float Tx = 0.0f, Ty = 0.0f;
+    double A = k.inv_siso2 * LOG2E, B = A, Tw0 = 1.0, Tw1 = 0.0;
     if (!iso) {
-        // binary32 tangent: strip membership decision (same bits as any IEEE
-        // evaluation); binary64 tangent: the continuous filter weights
         const float il = 1.0f / tlen;
-        f.Tx = tdx * il;
-        f.Ty = tdy * il;
+        Tx = tdx * il;
+        Ty = tdy * il;
         const DProj da = project_d(c, pos[vs]), db = project_d(c, pos[vs + 1]);
         const double ddx = db.x - da.x, ddy = db.y - da.y;
         const double dl = sqrt(ddx * ddx + ddy * ddy);
-        f.Tw0 = (float)(ddx / dl);
-        f.Tw1 = (float)(ddy / dl);
-        f.A = k.inv_spar2 * LOG2E;
-        f.B = k.inv_sperp2 * LOG2E;
+        Tw0 = ddx / dl;
+        Tw1 = ddy / dl;
+        A = k.inv_spar2 * LOG2E;
+        B = k.inv_sperp2 * LOG2E;
     }
-    f.Csc = colour_sim ? k.inv_sc2 * LOG2E : 0.0f;
+    FilterPix f;
+    f.qa = (float)(A * Tw0 * Tw0 + B * Tw1 * Tw1);
+    f.qb = (float)(2.0 * Tw0 * Tw1 * (A - B));
+    f.qc = (float)(A * Tw1 * Tw1 + B * Tw0 * Tw0);
+    f.Csc = colour_sim ? (float)(k.inv_sc2 * LOG2E) : 0.0f;
     f.Cx = CP.x; f.Cy = CP.y; f.Cz = CP.z;
-    f.qP = (uint32_t)(src >> HM_ID_BITS);
-    f.dq_rej = k.dq_rej;
-    f.strip2 = k.strip2;
+    const uint32_t qP = (uint32_t)(src >> HM_ID_BITS);
+    f.q_lo = qP - k.dq_rej;
+    f.q_span = 2u * k.dq_rej;
     f.track_max = !colour_sim;
     FilterAcc a;
     a.Sx = a.Sy = a.Sz = a.Wsum = 0.0f;
     a.emax = colour_sim ? 0.0f : -INFINITY;
-    a.Hc = a.Ha = 0;
     a.acc = false;
     const float4 *ctr = tile + (lj + r) * E + (li + r);
     if (R > 0) {
 #pragma unroll 1
         for (int oy = -R; oy <= R; ++oy) {
-            const float4 *row = ctr + oy * EMAX;
+            const float4 *row = ctr + oy * EMAX - R;    // non-negative LDS offsets
+            const float fy = (float)oy;
+            const float r1 = f.qb * fy, r0 = f.qc * (fy * fy);
 #pragma unroll
-            for (int ox = -R; ox <= R; ++ox) filter_tap(f, a, (float)ox, (float)oy, row[ox]);
+            for (int ox = -R; ox <= R; ++ox) filter_tap(f, a, (float)ox, r1, r0, row[ox + R]);
         }
     } else {
-        for (int oy = -r; oy <= r; ++oy)
-            for (int ox = -r; ox <= r; ++ox)
-                filter_tap(f, a, (float)ox, (float)oy, ctr[oy * E + ox]);
+        for (int oy = -r; oy <= r; ++oy) {
+            const float fy = (float)oy;
+            const float r1 = f.qb * fy, r0 = f.qc * (fy * fy);
+            for (int ox = -r; ox <= r; ++ox) filter_tap(f, a, (float)ox, r1, r0, ctr[oy * E + ox]);
+        }
     }
-    const float aP = a.Ha > 0 ? (float)a.Hc / (float)a.Ha : 1.0f;
+    int Hc, Ha;
+    strip_counts(tile, E, li + r, lj + r, r, Tx, Ty, k.strip_half, k.strip2, Hc, Ha);
+    const float aP = Ha > 0 ? (float)Hc / (float)Ha : 1.0f;
     float rr = 0.f, gg = 0.f, bb = 0.f, alpha = 0.f;
     if (hc && !mism) {
         rr = a.Sx / a.Wsum; gg = a.Sy / a.Wsum; bb = a.Sz / a.Wsum;
