@@ -137,41 +137,48 @@ __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
     return s;
 }
 
-// Coverage of pixel (i, j): bit0 centre sample, bit1 conservative; *q gets the
-// depth code at the clamped closest point when either bit is set.
-__device__ __forceinline__ uint32_t cover(const Seg &s, int i, int j, float r_min, float zn,
-                                          float inv_range, uint32_t &q)
+// Coverage of pixel (i, j): `centre` (centre sample) and `cons`
+// (conservative); q gets the depth code at the clamped closest point.  Returns
+// centre || cons.
+__device__ __forceinline__ bool cover(const Seg &s, int i, int j, float r_min, float zn,
+                                      float inv_range, bool &centre, bool &cons, uint32_t &q)
 {
-    // Evaluated without branches (selects only): the two tests, the closest
-    // point and the depth code are computed for every candidate pixel.  For a
-    // degenerate segment ilen2 = 0, so t = 0 and r is the endpoint radius.
+    // Evaluated without branches except for the rare degenerate segment: the
+    // two tests, the closest point and the depth code are computed for every
+    // candidate pixel.  For a degenerate segment ilen2 = 0, so t = 0 and r is
+    // the endpoint radius.  fminf / fmaxf (v_min / v_max) stand for the
+    // ternary minimum and maximum where only the sign of a zero could differ,
+    // which no comparison below can see (and a NaN radius from t = 0 * inf
+    // yields r_min either way).
     const float fi = (float)i, fj = (float)j;
     const float ux = (fi + 0.5f) - s.x0;
     const float uy = (fj + 0.5f) - s.y0;
     const float tn = ux * s.dx + uy * s.dy;
     const float t = tn * s.ilen2;
     const float wt = s.w0 + t * s.dw;
-    const float r = fmaxx(0.5f * wt, r_min);
+    const float r = fmaxf(0.5f * wt, r_min);
     const float r2 = r * r;
-    const float cr = ux * s.dy - uy * s.dx;
-    const bool seg_in = (tn >= 0.0f) & (tn < s.len2) & (cr * cr <= r2 * s.len2);
-    const bool disc_in = (ux * ux + uy * uy) <= r2;
-    const bool centre = s.len2 > 0.0f ? seg_in : disc_in;
+    if (__builtin_expect(s.len2 > 0.0f, 1)) {
+        const float cr = ux * s.dy - uy * s.dx;
+        centre = (tn >= 0.0f) & (tn < s.len2) & (cr * cr <= r2 * s.len2);
+    } else {
+        centre = (ux * ux + uy * uy) <= r2;
+    }
     const float bx0 = fi - s.ra, bx1 = (fi + 1.0f) + s.ra;
     const float by0 = fj - s.ra, by1 = (fj + 1.0f) + s.ra;
     const float fa = (bx0 - s.x0) * s.dy, fb = (bx1 - s.x0) * s.dy;
     const float ga = (by0 - s.y0) * s.dx, gb = (by1 - s.y0) * s.dx;
-    const float lo = fminx(fa, fb) - fmaxx(ga, gb);
-    const float hi = fmaxx(fa, fb) - fminx(ga, gb);
-    const bool cons = (s.sxmn <= bx1) & (s.sxmx >= bx0) & (s.symn <= by1) & (s.symx >= by0) &
-                      (lo <= 0.0f) & (hi >= 0.0f);
+    const float lo = fminf(fa, fb) - fmaxf(ga, gb);
+    const float hi = fmaxf(fa, fb) - fminf(ga, gb);
+    cons = (s.sxmn <= bx1) & (s.sxmx >= bx0) & (s.symn <= by1) & (s.symx >= by0) &
+           (lo <= 0.0f) & (hi >= 0.0f);
     float ts = t;
     ts = fmaxx(ts, 0.0f);
     ts = fminx(ts, 1.0f);
     const float iz = s.iz0 + ts * s.diz;
     const float z = 1.0f / iz;
     q = depth_code(z, zn, inv_range);
-    return (centre ? 1u : 0u) | (cons ? 2u : 0u);
+    return centre | cons;
 }
 
 // Scene of control point c: last s with scene_off[s] <= c (scene_off non-decreasing).

@@ -201,12 +201,13 @@ __global__ __launch_bounds__(256) void k_raster_direct(const float4 *proj, const
             a1 = a1 < i1 ? a1 : i1;
             for (int i = a0; i <= a1; ++i) {
                 uint32_t q;
-                const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
+                bool cc, ca;
+                const bool msk = cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
                 if (!msk) continue;
                 const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
                 const size_t p = (size_t)j * rk.W + i;
-                if (msk & 1u) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
-                if (msk & 2u) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
+                if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
+                if (ca) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
             }
         }
     }
@@ -700,14 +701,15 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                 const int i = px0 + (int)(d >> 13);
                                 const Seg sp = rec_load(rf, nb, ow);
                                 uint32_t q;
-                                const uint32_t msk = cover(sp, i, j, rk.r_min, zn, inv_range, q);
+                                bool cc, ca;
+                                const bool msk = cover(sp, i, j, rk.r_min, zn, inv_range, cc, ca, q);
                                 if (msk) {
                                     const unsigned long long key =
                                         ((unsigned long long)q << HM_ID_BITS) | r_sid[ow];
                                     const uint32_t x =
                                         (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
-                                    if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
-                                    if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
+                                    if (cc) atomicMin((unsigned long long *)&lc[x], key);
+                                    if (ca) atomicMin((unsigned long long *)&la[x], key);
                                 }
                             }
                         }
@@ -747,12 +749,13 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     a1 = min(a1, px0 + rc_i1(rc));
                     for (int i = a0; i <= a1; ++i) {
                         uint32_t q;
-                        const uint32_t msk = cover(sr, i, j, rk.r_min, zn, inv_range, q);
+                        bool cc, ca;
+                        const bool msk = cover(sr, i, j, rk.r_min, zn, inv_range, cc, ca, q);
                         if (!msk) continue;
                         const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | vo;
                         const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
-                        if (msk & 1u) atomicMin((unsigned long long *)&lc[x], key);
-                        if (msk & 2u) atomicMin((unsigned long long *)&la[x], key);
+                        if (cc) atomicMin((unsigned long long *)&lc[x], key);
+                        if (ca) atomicMin((unsigned long long *)&la[x], key);
                     }
                 }
             }
@@ -806,12 +809,13 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
             a1 = min(a1, i1);
             for (int i = a0; i <= a1; ++i) {
                 uint32_t q;
-                const uint32_t msk = cover(sg, i, j, rk.r_min, zn, inv_range, q);
+                bool cc, ca;
+                const bool msk = cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
                 if (!msk) continue;
                 const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
                 const size_t p = (size_t)j * rk.W + i;
-                if (msk & 1u) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
-                if (msk & 2u) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
+                if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
+                if (ca) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
             }
         }
     }
