@@ -213,7 +213,7 @@ typedef struct {
     float iso_scale;       /* isotropic fallback sigma_iso = iso_scale r */
     float depth_reject;    /* neighbour depth rejection threshold (normalised depth) */
     float depth_mismatch;  /* centre vs conservative depth mismatch (normalised depth) */
-    float strip_half;      /* alpha strip half width in px (Sec. 3.3.3) */
+    float strip_half;      /* alpha strip half width in px, [0, 16] (Sec. 3.3.3) */
     float iso_len;         /* screen tangent shorter than this (px) -> isotropic */
     float soft_sigma;      /* soft coverage: std of the Gaussian pixel filter (px) */
     float bg[3];           /* background the result is composited over */

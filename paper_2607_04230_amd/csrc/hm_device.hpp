@@ -208,6 +208,28 @@ __device__ __forceinline__ T wave_inclusive_scan(T x)
     return x;
 }
 
+// 32-bit inclusive scan over the 64 lanes of a full wave with DPP moves:
+// row_shr 1, 2, 4, 8 give the prefix inside each row of 16 lanes;
+// row_bcast 15 adds the end of rows 0 / 2 to rows 1 / 3, and row_bcast 31 the
+// end of row 1 to rows 2 and 3.  Every lane of the wave must be active.
+template <>
+__device__ __forceinline__ uint32_t wave_inclusive_scan<uint32_t>(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, false);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, false);
+    return x;
+}
+
+// Value of lane 63 (wave-uniform).
+__device__ __forceinline__ uint32_t wave_last(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
 // Exclusive scan over the block; lds must hold blockDim.x / 64 values.  Returns
 // the exclusive prefix and writes the block total to `total`.
 template <typename T>

@@ -684,7 +684,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     }
                     const uint32_t inc = wave_inclusive_scan(c);
                     const uint32_t pc = inc - c;
-                    const uint32_t P = __shfl(inc, 63, 64);
+                    const uint32_t P = wave_last(inc);
                     for (uint32_t w0 = 0; w0 < P; w0 += PIX_WINDOW) {
                         const uint32_t m0 = pc > w0 ? pc : w0;
                         const uint32_t m1 = min(pc + c, w0 + PIX_WINDOW);
