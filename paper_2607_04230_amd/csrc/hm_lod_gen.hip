@@ -275,15 +275,16 @@ struct GenK {
     float br, bg, bb;
 };
 
-// Cooperative assembly, one wave per bundle (the paper assigns a subgroup per
-// strand and shares control points through shuffles; on gfx950 a 64-lane wave
-// shares a bundle's strands through LDS): the strands' (u, v, phase), base
-// layer points and layer tangents are computed once into LDS, then every lane
-// evaluates control points (Hermite + curl) from LDS and stores them
-// coalesced.  Strands are processed in chunks that fit the LDS budget.
+// Cooperative assembly, one workgroup of four waves per bundle (the paper
+// assigns a subgroup per strand and shares control points through shuffles;
+// here the workgroup shares a bundle's strands through LDS): the strands'
+// (u, v, phase), base layer points and layer tangents are computed once into
+// LDS, then every lane evaluates control points (Hermite + curl) from LDS and
+// stores them coalesced.  Strands are processed in chunks that fit the LDS
+// budget.
 constexpr uint32_t GEN_LDS_FLOATS = 6144;   // 24 KB
 
-__global__ __launch_bounds__(64) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
+__global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
                                                         const uint32_t *strand_base,
                                                         const float *strand_rgb, GenK g,
                                                         float4 *pos_w, float4 *rgb,
@@ -412,7 +413,7 @@ void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_
 {
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    hipLaunchKernelGGL(k_generate_bundle, dim3(m.n_bundles), dim3(64), 0, st, m, table,
+    hipLaunchKernelGGL(k_generate_bundle, dim3(m.n_bundles), dim3(256), 0, st, m, table,
                        strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
                        reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
                        s.cap);
