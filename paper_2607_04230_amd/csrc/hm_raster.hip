@@ -3,7 +3,8 @@
 // The paper draws every styled segment with a DDA line and a 64-bit
 // image atomicMin per pixel and layer.  Here:
 //   1. k_prefill writes both layers (empty or the opaque scene depth);
-//   2. k_project computes each control point's screen record once;
+//   2. each control point's screen record is computed once, by the first
+//      binning pass (or by k_project on the direct path);
 //   3. TILED path: k_bin counts, then scatters, segment ids into per-screen-
 //      tile lists (T x T pixels), with wave-level ballot aggregation of the
 //      list atomics; an exclusive scan turns counts into offsets and each tile
@@ -239,16 +240,31 @@ struct SegTiles {
     uint32_t s, tx0, ty0, bw, nt;
 };
 
-__device__ __forceinline__ bool seg_tiles(const float4 *proj, const uint8_t *flags,
-                                          const uint32_t *scene_off, const RasterK &rk, uint32_t u,
-                                          uint32_t n, SegTiles &st)
+// PROJECT: also compute this unit's screen record from the stream (and the
+// next control point's, for the segment) and store it in proj[u]; otherwise
+// read both records from proj.  Both give the same bits.
+template <bool PROJECT>
+__device__ __forceinline__ bool seg_tiles(const float4 *proj_in, float4 *proj_out,
+                                          const float4 *pos_w, const hm_camera *cams,
+                                          const uint8_t *flags, const uint32_t *scene_off,
+                                          const RasterK &rk, uint32_t u, uint32_t n, SegTiles &st)
 {
     st.nt = 0;
     if (u >= unit_count(n, rk)) return false;
     uint32_t v;
     unit_map(scene_off, rk, n, u, st.s, v);
-    if (v + 1 >= n || (flags[v] & HM_TIP)) return false;
-    const float4 a = proj[u], b = proj[u + 1];
+    float4 a, b;
+    if (PROJECT) {
+        const Cam cam = load_cam(cams + st.s);
+        a = project(cam, pos_w[v]);
+        proj_out[u] = a;
+        if (v + 1 >= n || (flags[v] & HM_TIP)) return false;
+        b = project(cam, pos_w[v + 1]);
+    } else {
+        if (v + 1 >= n || (flags[v] & HM_TIP)) return false;
+        a = proj_in[u];
+        b = proj_in[u + 1];
+    }
     if (a.w == 0.0f || b.w == 0.0f) return false;
     // the fields of make_seg that the tile tests read, computed the same way
     Seg &sg = st.sg;
@@ -313,11 +329,13 @@ __device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
 //           long list;
 //   pass 1: one returning global add per (workgroup, tile) reserves a range
 //           of the tile's list; pairs then take LDS-atomic ranks inside it.
-__global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, const float4 *proj, const uint8_t *flags,
-                                             const uint32_t *scene_off, RasterK rk, uint32_t cap,
-                                             uint32_t *tile_cnt, const uint32_t *tile_off,
-                                             uint32_t *tile_cur, uint32_t *entries,
-                                             uint32_t *long_list, uint32_t *counters)
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const float4 *pos_w,
+                                                   const hm_camera *cams, const uint8_t *flags,
+                                                   const uint32_t *scene_off, RasterK rk,
+                                                   uint32_t cap, uint32_t *tile_cnt,
+                                                   const uint32_t *tile_off, uint32_t *tile_cur,
+                                                   uint32_t *entries, uint32_t *long_list,
+                                                   uint32_t *counters)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t n = stream_len(scene_off, rk, cap);
@@ -333,7 +351,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, const float4 *proj,
         for (uint32_t sub = 0; sub < BIN_SUB; ++sub) {
             const uint32_t v = base + sub * blockDim.x + threadIdx.x;
             SegTiles st;
-            bool ok = seg_tiles(proj, flags, scene_off, rk, v, n, st);
+            bool ok = pass == 0
+                          ? seg_tiles<true>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st)
+                          : seg_tiles<false>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st);
             if (ok && st.nt > rk.K) {
                 if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
                 ok = false;
@@ -365,7 +385,9 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, const float4 *proj,
             for (uint32_t sub = 0; sub < BIN_SUB; ++sub) {
                 const uint32_t v = base + sub * blockDim.x + threadIdx.x;
                 SegTiles st;
-                if (!seg_tiles(proj, flags, scene_off, rk, v, n, st) || st.nt > rk.K) continue;
+                if (!seg_tiles<false>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st) ||
+                    st.nt > rk.K)
+                    continue;
                 for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
                 for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
                     uint32_t tile;
@@ -919,17 +941,18 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                        tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
     const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
     const size_t units = (size_t)s.cap * units_per_cp(f, p);
-    hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
-                       s.scene_off, rk, cams, s.cap, w.proj);
     if (p.algo == HM_RASTER_DIRECT) {
+        hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
+                           s.scene_off, rk, cams, s.cap, w.proj);
         hipLaunchKernelGGL(k_raster_direct, dim3(stride_grid(units, 256)), dim3(256), 0, st,
                            (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
                            rk, s.cap, vis);
         return;
     }
+    // pass 0 of the binning also writes every unit's screen record
     const uint32_t nt = rk.n_tiles;
     const uint32_t gb = stride_grid((units + BIN_SUB - 1) / BIN_SUB, BIN_BLOCK);
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, (const float4 *)w.proj,
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);
     const bool small = nt <= PLAN_SMALL;
@@ -941,7 +964,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         hipLaunchKernelGGL(k_tile_items, dim3((nt + 255) / 256), dim3(256), 0, st,
                            (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
     }
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, (const float4 *)w.proj,
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
                        w.counters);
