@@ -40,17 +40,26 @@ static std::vector<TimedRec> g_recs;
 KTimer::KTimer(const char *name, hipStream_t st) : name_(name), st_(st)
 {
     if (!g_timing) return;
-    if (hipEventCreate(&a_) != hipSuccess || hipEventCreate(&b_) != hipSuccess) {
-        a_ = b_ = nullptr;
+    if (hipEventCreate(&a_) != hipSuccess) {
+        a_ = nullptr;
         return;
     }
-    hipEventRecord(a_, st_);
+    if (hipEventCreate(&b_) != hipSuccess || hipEventRecord(a_, st_) != hipSuccess) {
+        // timing is best effort: a launch that cannot be timed is not recorded
+        (void)hipEventDestroy(a_);
+        if (b_) (void)hipEventDestroy(b_);
+        a_ = b_ = nullptr;
+    }
 }
 
 KTimer::~KTimer()
 {
     if (!a_) return;
-    hipEventRecord(b_, st_);
+    if (hipEventRecord(b_, st_) != hipSuccess) {
+        (void)hipEventDestroy(a_);
+        (void)hipEventDestroy(b_);
+        return;
+    }
     std::lock_guard<std::mutex> g(g_tmu);
     g_recs.push_back({name_, a_, b_});
 }
@@ -221,8 +230,8 @@ hm_status hm_timing_collect(char *buf, size_t len)
             e.first += ms;
             e.second += 1;
         }
-        hipEventDestroy(r.a);
-        hipEventDestroy(r.b);
+        (void)hipEventDestroy(r.a);   // nothing to do if a destroy fails
+        (void)hipEventDestroy(r.b);
     }
     size_t o = 0;
     buf[0] = 0;
@@ -397,18 +406,18 @@ hm_status hm_graph_create(const hm_frame_desc *d, void *stream, hm_graph *out)
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(st, &graph);
     if (rs != HM_OK) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         return fail(rs, "%s", msg);
     }
     if (e != hipSuccess || !graph)
         return fail(HM_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);       // the executable graph no longer needs it
     if (e != hipSuccess) return fail(HM_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     hm_graph g = new (std::nothrow) hm_graph_s{exec};
     if (!g) {
-        hipGraphExecDestroy(exec);
+        (void)hipGraphExecDestroy(exec);
         return fail(HM_ERR_INVALID, "out of host memory");
     }
     *out = g;
@@ -426,8 +435,9 @@ hm_status hm_graph_launch(hm_graph g, void *stream)
 hm_status hm_graph_destroy(hm_graph g)
 {
     if (!g) return ok();
-    hipGraphExecDestroy(g->exec);
+    const hipError_t e = hipGraphExecDestroy(g->exec);
     delete g;
+    if (e != hipSuccess) return fail(HM_ERR_HIP, "hipGraphExecDestroy: %s", hipGetErrorString(e));
     return ok();
 }
 
