@@ -21,16 +21,16 @@ Candidate = Tuple[int, int, int, int, int]   # algo, tile, chunk, block, max_til
 DEFAULT_CANDIDATES: Tuple[Candidate, ...] = tuple(
     [(hm.RASTER_TILED, t, c, b, k)
      for t in (16, 32) for c in (256, 512, 1024, 2048, 1 << 20) for b in (128, 256)
-     for k in (4, 8)]
+     for k in (4, 8, 16)]
     + [(hm.RASTER_TILED_ROWS, t, 512, 512, 4) for t in (16, 32)]
     + [(hm.RASTER_TILED, 8, 1 << 20, 256, 16), (hm.RASTER_DIRECT, 32, 256, 256, 4)])
 
 QUICK_CANDIDATES: Tuple[Candidate, ...] = (
-    (hm.RASTER_TILED, 32, 512, 256, 4), (hm.RASTER_TILED, 32, 512, 256, 8),
-    (hm.RASTER_TILED, 32, 1024, 256, 8), (hm.RASTER_TILED, 32, 256, 256, 4),
-    (hm.RASTER_TILED, 32, 2048, 256, 8), (hm.RASTER_TILED, 16, 512, 256, 8),
-    (hm.RASTER_TILED, 32, 1 << 20, 256, 4), (hm.RASTER_TILED, 32, 512, 128, 4),
-    (hm.RASTER_TILED_ROWS, 32, 512, 512, 4))
+    (hm.RASTER_TILED, 32, 512, 256, 8), (hm.RASTER_TILED, 32, 512, 256, 4),
+    (hm.RASTER_TILED, 32, 1024, 256, 8), (hm.RASTER_TILED, 32, 2048, 256, 8),
+    (hm.RASTER_TILED, 32, 512, 256, 16), (hm.RASTER_TILED, 32, 1024, 256, 16),
+    (hm.RASTER_TILED, 32, 2048, 256, 16), (hm.RASTER_TILED, 16, 2048, 256, 8),
+    (hm.RASTER_TILED_ROWS, 32, 512, 256, 8))
 
 
 def cache_path() -> str:
