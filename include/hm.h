@@ -84,7 +84,9 @@ typedef struct {
 
 /* Generated strand stream: control points of all strands, strand after
  * strand, bundle after bundle (table order).  Segment v joins CP v and CP
- * v + 1 when CP v is not a tip. */
+ * v + 1 when CP v is not a tip.  When scene_off[n_scenes] exceeds cap, the
+ * stream is truncated to its first cap CPs and CP cap - 1 is flagged as a
+ * tip, so that no call reads past cap. */
 typedef struct {
     float *pos_w;               /* [cap][4]: x, y, z (world), width (world units) */
     float *rgb;                 /* [cap][4]: albedo r, g, b, ambient occlusion (1) */

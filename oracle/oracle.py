@@ -176,7 +176,10 @@ def lod_depth_offset(table: np.ndarray, bundle_nstrands: np.ndarray) -> np.ndarr
     return out
 
 
-def generate(sc, table: np.ndarray, n_cp: int):
+def generate(sc, table: np.ndarray, n_cp: int, cap: int = None):
+    """Strand stream of the LOD table (Sec. 3.1.1).  With `cap` below n_cp the
+    stream is cut to its first cap control points and the last one is flagged
+    as a tip (the stream-capacity rule of the library's interface)."""
     pos_w = np.zeros((max(n_cp, 1), 4), np.float32)
     rgb = np.zeros((max(n_cp, 1), 4), np.float32)
     flags = np.zeros(max(n_cp, 1), np.uint8)
@@ -192,6 +195,11 @@ def generate(sc, table: np.ndarray, n_cp: int):
                             sc.curl_turns, _p(brgb), _p(pos_w), _p(rgb), _p(flags))
     if rc != 0:
         raise ValueError("oracle generate: unsupported layer count")
+    if cap is not None and cap < n_cp:
+        pos_w, rgb, flags = pos_w[:cap].copy(), rgb[:cap].copy(), flags[:cap].copy()
+        if cap > 0:
+            flags[cap - 1] |= 2
+        return pos_w, rgb, flags
     return pos_w[:n_cp], rgb[:n_cp], flags[:n_cp]
 
 

@@ -400,7 +400,8 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             rgb[c] = col;
             uint8_t fl = 0;
             if (j == 0) fl |= (uint8_t)HM_ROOT;
-            if (j == C - 1u) fl |= (uint8_t)HM_TIP;
+            // the last CP of a stream truncated to the capacity ends its strand
+            if (j == C - 1u || c == limit - 1u) fl |= (uint8_t)HM_TIP;
             flags[c] = fl;
         }
         __syncthreads();

@@ -136,3 +136,45 @@ def test_soft_forward_diff_config(O, torch):
     ds = _gpu(sc, torch)
     assert np.array_equal(ds.host_vis(), ref["vis"])
     assert _rgba_err(ds.out.cpu().numpy(), ref["out"], ref["vis"], "soft") <= TOL
+
+
+def test_empty_frame_camera_facing_away(O, torch):
+    # every segment is behind the camera: both layers stay empty and every
+    # pixel is background
+    sc = scenes.config_tiny()
+    sc.cams = scenes.look_at_camera((0.0, 1.3, 2.6), (0.0, 1.3, 6.0), sc.width,
+                                    sc.height)[None].astype(np.float32)
+    ref = O.render(sc)
+    ds = _gpu(sc, torch)
+    _compare_stream(ds, ref)
+    vis = ds.host_vis()
+    assert np.array_equal(vis, ref["vis"])
+    assert (vis == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    out = ds.out.cpu().numpy()
+    assert _rgba_err(out, ref["out"], ref["vis"], "empty") <= TOL
+    assert (out[..., 3] == 0.0).all()
+
+
+@pytest.mark.parametrize("cap", [2, 1001, 5000])
+def test_stream_truncated_to_capacity(O, torch, cap):
+    # a stream capacity below the LOD total keeps the first cap control
+    # points, the last one flagged as a tip; raster and resolve read nothing
+    # past cap
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_tiny()
+    table, soff, (ns, ncp) = O.lod_select(sc)
+    assert cap < ncp
+    pos, rgb, fl = O.generate(sc, table, ncp, cap=cap)
+    soff_c = np.minimum(soff, cap).astype(np.uint32)
+    vis = O.raster(pos, fl, soff_c, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+    out = O.resolve(pos, rgb, fl, vis, sc.cams, sc.width, sc.height, ResolveParams(), sc.mode,
+                    sc.bg)
+    ds = DeviceScene(sc, cap=cap)
+    ds.render()
+    torch.cuda.synchronize()
+    gp, gr, gf = ds.host_stream()
+    assert gp.shape[0] == cap
+    assert np.array_equal(gf, fl)
+    assert np.array_equal(gp.view(np.uint32), pos.view(np.uint32))
+    assert np.array_equal(ds.host_vis(), vis)
+    assert _rgba_err(ds.out.cpu().numpy(), out, vis, "truncated") <= TOL

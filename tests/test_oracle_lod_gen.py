@@ -251,3 +251,15 @@ def test_generation_colour_routing_and_lod_prefix(O):
         for k in range(7):
             assert (pos2[t2[b, 3] + k * 17: t2[b, 3] + (k + 1) * 17] ==
                     pos[t[b, 3] + k * 17: t[b, 3] + (k + 1) * 17]).all()
+
+
+def test_generate_truncated_stream_rule(O):
+    sc = scenes.config_tiny()
+    table, soff, (ns, ncp) = O.lod_select(sc)
+    pos, rgb, fl = O.generate(sc, table, ncp)
+    for cap in (1, 2, 17, ncp - 1):
+        p2, r2, f2 = O.generate(sc, table, ncp, cap=cap)
+        assert p2.shape[0] == cap and np.array_equal(p2, pos[:cap]) and np.array_equal(r2, rgb[:cap])
+        assert np.array_equal(f2[:-1], fl[:cap - 1]) and f2[-1] == (fl[cap - 1] | 2)
+    p3, _, f3 = O.generate(sc, table, ncp, cap=ncp + 5)
+    assert np.array_equal(f3, fl) and p3.shape[0] == ncp
