@@ -259,6 +259,41 @@ def extra_diff(steps):
             "params": int(n)}
 
 
+def extra_shadow(steps):
+    """Deep-opacity-map shadows on the 1080p head: light-view raster, layer
+    counts and per-pixel lookup (with the LOD depth correction), and the
+    shadowed frame against the unshadowed one."""
+    import torch
+    from paper_2607_04230_amd import hm, scenes
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_head()
+    shp = scenes.ShadowParams(width=1024, height=1024)
+    ds = DeviceScene(sc)
+    plain = _time_ms(ds.render, steps, 2)
+    ds.render_shadowed(shp)
+    torch.cuda.synchronize()
+    shadows = _time_ms(lambda: ds.shadows(shp), steps, 2)
+    full = _time_ms(lambda: ds.render_shadowed(shp), steps, 2)
+    hm.timing_enable(True)
+    hm.timing_collect()
+    for _ in range(steps):
+        ds.shadows(shp)
+    torch.cuda.synchronize()
+    t = hm.timing_collect()
+    hm.timing_enable(False)
+    per = {k: v[0] / max(v[1], 1) for k, v in t.items()}
+    T = ds.shadow
+    hit = ds.vis[0, 0] != -1
+    r = {"light_map": [shp.width, shp.height], "n_layers": shp.n_layers,
+         "frame_ms": plain, "shadowed_frame_ms": full, "shadow_passes_ms": shadows,
+         "kernel_ms": {k: per[k] for k in sorted(per)},
+         "shadowed_fraction": float(((T < 0.99) & hit).sum().item() / max(hit.sum().item(), 1)),
+         "fragments_in_map": int(ds.dom_counts.sum().item())}
+    del ds
+    torch.cuda.empty_cache()
+    return r
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -391,7 +426,8 @@ def main():
     if not args.no_extras:
         del ds
         torch.cuda.empty_cache()
-        for name, fn in (("lod", extra_lod), ("batched", extra_batched), ("diff", extra_diff)):
+        for name, fn in (("lod", extra_lod), ("batched", extra_batched), ("diff", extra_diff),
+                         ("shadow", extra_shadow)):
             print(f"[bench] extra workload: {name}", file=sys.stderr, flush=True)
             line[name] = fn(max(args.steps // 2, 5))
     if not args.no_cpu:

@@ -220,6 +220,10 @@ typedef struct {
     float soft_sigma;      /* soft coverage: std of the Gaussian pixel filter (px) */
     float bg[3];           /* background the result is composited over */
     int32_t mode;          /* HM_RESOLVE_FILTER / HM_RESOLVE_SOFT / HM_RESOLVE_CENTER */
+    const float *shadow;   /* optional (device, [S][height][width]): the light's
+                              transmittance at each pixel's shaded point (from
+                              hm_dom_shadow); scales the diffuse and specular
+                              terms of the centre shading.  NULL: unshadowed */
 } hm_shade_params;
 
 /* Deferred resolve, out_rgba[S][height][width][4] float (straight colour
@@ -247,8 +251,50 @@ hm_status hm_resolve_shade_bwd(const hm_strands *s, const uint64_t *vis, const h
                                const float *d_out, float *grad_pos_w, float *grad_rgb,
                                void *stream);
 
+/* ------------------------------------------------------------------ shadows */
+/* Deep-opacity-map shadows (Sec. 3.4, which cites Yuksel & Keyser 2008 for
+ * the map) queried with the LOD depth correction of Sec. 3.2.3.  Single
+ * scene.  The light is a pinhole camera; its view of the stream is first
+ * rasterized with hm_raster_vis (frame {1, width, height}, no scene depth)
+ * into light_vis, whose conservative layer gives the nearest fragment q0 of
+ * every light pixel. */
+typedef struct {
+    uint32_t width, height;  /* light map resolution */
+    uint32_t n_layers;       /* layers behind the nearest fragment, 1 .. 8 */
+    uint32_t layer_codes;    /* layer thickness in 24-bit depth-code units, >= 1 */
+    float r_min;             /* fragment coverage half width in the light view (px) */
+    float alpha;             /* opacity of one fragment (> 0) */
+} hm_dom_params;
+
+/* counts[n_layers][height][width] (uint32, device, overwritten): every
+ * (segment, light pixel) pair accepted by the conservative test, at depth
+ * code q, adds 1 to layer min((q - q0) / layer_codes, n_layers - 1) of its
+ * pixel (exact and order-independent).  ws: hm_workspace_size(HM_CALL_DOM,
+ * {1, width, height}, 0, cap, NULL) bytes. */
+hm_status hm_dom_accumulate(const hm_strands *s, const hm_camera *light, const hm_dom_params *p,
+                            const uint64_t *light_vis, uint32_t *counts, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* shadow[height][width] (float, device) of the camera frame `frame` (one
+ * scene) with visibility vis: for a pixel with a centre hit, the shaded point
+ * (as the resolve computes it, binary64) is projected by the light camera to
+ * a light pixel and a depth code q; the LOD correction moves it towards the
+ * light inside the groom, q' = q0 + (uint32)((float)(q - q0) * beta) with
+ * beta = N_LOD / N_b of its bundle (table and bundle_nstrands as given to
+ * and returned by hm_lod_select), which shifts the log of its depth below q0
+ * by Delta = -log beta; the opacity in front of q' is the counts of the
+ * layers before it plus the linearly interpolated part of its own layer (the
+ * last layer is taken whole once passed), and shadow = exp(-alpha *
+ * opacity).  Other pixels, and points outside the light frustum or map, get
+ * 1.  Pass the result as hm_shade_params.shadow. */
+hm_status hm_dom_shadow(const hm_strands *s, const uint64_t *vis, const hm_camera *cam,
+                        const hm_frame *frame, const hm_camera *light, const hm_dom_params *p,
+                        const uint64_t *light_vis, const uint32_t *counts,
+                        const uint32_t *table, const uint32_t *bundle_nstrands,
+                        uint32_t n_bundles, float *shadow, void *stream);
+
 /* ------------------------------------------------------------------ workspace */
-enum { HM_CALL_LOD = 0, HM_CALL_RASTER = 1, HM_CALL_RESOLVE = 2 };
+enum { HM_CALL_LOD = 0, HM_CALL_RASTER = 1, HM_CALL_RESOLVE = 2, HM_CALL_DOM = 3 };
 
 /* Workspace bytes for `call`.  n_bundles (LOD) or cap (raster) size it;
  * raster params may be NULL (defaults).  Returns HM_ERR_RANGE on overflow. */

@@ -640,7 +640,7 @@ static v3d orc_cp_tangent(const float *pos_w, const uint8_t *flags, uint64_t v)
  * about the half vector, one directional light (Sec. 3.4, simplified). */
 static void orc_shade_px(const float *pos_w, const float *rgb, const uint8_t *flags,
                          const orc_cam *c, const orc_shade_params *sp, uint64_t v,
-                         double px, double py, double out[3])
+                         double px, double py, double shadow, double out[3])
 {
     double a[3], b[3];
     orc_proj64(c, pos_w + 4 * v, a);
@@ -672,8 +672,10 @@ static void orc_shade_px(const float *pos_w, const float *rgb, const uint8_t *fl
     double spec = sh;
     for (int k = 0; k < sp->spec_squarings; ++k) spec = spec * spec;
     double albv[3] = {alb.x, alb.y, alb.z};
+    /* the light's transmittance scales the direct terms, not the ambient one */
     for (int ch = 0; ch < 3; ++ch)
-        out[ch] = albv[ch] * sp->light_rgb[ch] * (sp->ka + sp->kd * diff) + sp->ks * sp->light_rgb[ch] * spec;
+        out[ch] = albv[ch] * sp->light_rgb[ch] * (sp->ka + shadow * sp->kd * diff) +
+                  shadow * sp->ks * sp->light_rgb[ch] * spec;
 }
 
 static int orc_is_hit(uint64_t k)
@@ -685,10 +687,26 @@ static int orc_is_hit(uint64_t k)
  * filter + alpha estimation + composite over bg (Sec. 3.3, Code 2 with the
  * readings stated in the design notes).  out_rgba [S][H][W][4] in binary64.
  * center_rgb (optional, [S][H][W][3]) receives the raw centre shading. */
+int orc_resolve_shadowed(const float *pos_w, const float *rgb, const uint8_t *flags,
+                         const uint64_t *vis, const float *cams, uint32_t n_scenes, int width,
+                         int height, const orc_shade_params *sp, const int *win,
+                         const double *shadow, double *out_rgba, double *center_rgb);
+
 int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                 const uint64_t *vis, const float *cams, uint32_t n_scenes, int width,
                 int height, const orc_shade_params *sp, const int *win, double *out_rgba,
                 double *center_rgb)
+{
+    return orc_resolve_shadowed(pos_w, rgb, flags, vis, cams, n_scenes, width, height, sp, win,
+                                NULL, out_rgba, center_rgb);
+}
+
+/* As orc_resolve; shadow (optional, [S][H][W]) is the light's transmittance
+ * at each pixel's shaded point. */
+int orc_resolve_shadowed(const float *pos_w, const float *rgb, const uint8_t *flags,
+                         const uint64_t *vis, const float *cams, uint32_t n_scenes, int width,
+                         int height, const orc_shade_params *sp, const int *win,
+                         const double *shadow, double *out_rgba, double *center_rgb)
 {
     size_t npix = (size_t)width * height;
     if (sp->mode == 1) return -2;   /* soft coverage lives in the binary64 torch oracle */
@@ -713,7 +731,8 @@ int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
                 double *o = cc + 3 * p;
                 o[0] = o[1] = o[2] = 0.0;
                 if (orc_is_hit(g[p]))
-                    orc_shade_px(pos_w, rgb, flags, c, sp, g[p] & ORC_ID_MASK, i + 0.5, j + 0.5, o);
+                    orc_shade_px(pos_w, rgb, flags, c, sp, g[p] & ORC_ID_MASK, i + 0.5, j + 0.5,
+                                 shadow ? shadow[(size_t)s * npix + p] : 1.0, o);
                 if (center_rgb) {
                     double *q = center_rgb + ((size_t)s * npix + p) * 3;
                     q[0] = o[0]; q[1] = o[1]; q[2] = o[2];
@@ -819,5 +838,134 @@ int orc_resolve(const float *pos_w, const float *rgb, const uint8_t *flags,
             }
     }
     free(cc);
+    return 0;
+}
+
+/* ------------------------------------------------------------ deep opacity map
+ * Shadows of Sec. 3.4 (deep opacity maps, Yuksel & Keyser 2008) queried with
+ * the LOD depth correction of Sec. 3.2.3.  The map is built from the light's
+ * view: q0(p) is the depth code of the nearest fragment of light pixel p (the
+ * conservative layer of the light view's visibility buffer, rasterized
+ * without a scene depth), and every (segment, light pixel) pair accepted by
+ * the conservative test, at depth code q, is counted in layer
+ * min((q - q0) / L, K - 1) of that pixel.  Counting (instead of blending
+ * opacities) keeps the map exact and independent of order. */
+int orc_dom_accumulate(const float *pos_w, const uint8_t *flags, uint64_t n_cp,
+                       const float *lcam, int width, int height, float r_min,
+                       const uint64_t *light_vis, uint32_t layer_codes, uint32_t n_layers,
+                       uint32_t *counts)
+{
+    size_t npix = (size_t)width * (size_t)height;
+    memset(counts, 0, sizeof(uint32_t) * npix * n_layers);
+    const orc_cam *c = (const orc_cam *)lcam;
+    float inv_range = 1.0f / (c->zfar - c->znear);
+    const uint64_t *va = light_vis + npix;
+    for (uint64_t v = 0; v + 1 < n_cp; ++v) {
+        if (flags[v] & ORC_TIP) continue;
+        float a[4], b[4];
+        if (!orc_proj(c, pos_w + 4 * v, a) || !orc_proj(c, pos_w + 4 * (v + 1), b)) continue;
+        float ra = 0.5f * (a[2] > b[2] ? a[2] : b[2]);
+        ra = ra > r_min ? ra : r_min;
+        float xmn = (a[0] < b[0] ? a[0] : b[0]) - ra - 2.0f;
+        float xmx = (a[0] > b[0] ? a[0] : b[0]) + ra + 2.0f;
+        float ymn = (a[1] < b[1] ? a[1] : b[1]) - ra - 2.0f;
+        float ymx = (a[1] > b[1] ? a[1] : b[1]) + ra + 2.0f;
+        if (xmx < 0.0f || ymx < 0.0f || xmn > (float)width || ymn > (float)height) continue;
+        int i0 = xmn > 0.0f ? (int)xmn : 0, j0 = ymn > 0.0f ? (int)ymn : 0;
+        int i1 = xmx < (float)(width - 1) ? (int)xmx : width - 1;
+        int j1 = ymx < (float)(height - 1) ? (int)ymx : height - 1;
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) {
+                uint32_t q;
+                int m = orc_cover(a, b, i, j, r_min, c->znear, inv_range, &q);
+                if (!(m & 2)) continue;
+                size_t p = (size_t)j * width + i;
+                uint32_t q0 = (uint32_t)(va[p] >> ORC_ID_BITS);
+                uint32_t k = q > q0 ? (q - q0) / layer_codes : 0u;
+                if (k > n_layers - 1) k = n_layers - 1;
+                counts[(size_t)k * npix + p] += 1u;
+            }
+    }
+    return 0;
+}
+
+/* Transmittance towards the light at the shaded point of every camera pixel
+ * with a centre hit (T = 1 elsewhere).  The point X is the one the resolve
+ * shades (binary64), projected by the light camera in binary64: light pixel
+ * floor(x), floor(y) and depth code q of its linear depth.  The LOD
+ * correction moves it towards the light inside the groom: with
+ * beta = N_LOD / N_b of its bundle (binary32), the log of its depth below the
+ * first fragment is shifted by -Delta = log beta, i.e. q' = q0 +
+ * (uint32)((float)(q - q0) * beta).  The opacity in front of q' is the
+ * counts of the layers before q' plus the linearly interpolated part of its
+ * own layer (the last layer reaches to infinity and is taken whole once
+ * passed), times the per-fragment opacity alpha; T = exp(-opacity). */
+int orc_dom_shadow(const float *pos_w, const uint8_t *flags, const uint64_t *vis,
+                   const float *cam, int width, int height, const float *lcam, int lwidth,
+                   int lheight, const uint64_t *light_vis, const uint32_t *counts,
+                   uint32_t layer_codes, uint32_t n_layers, const uint32_t *table,
+                   const uint32_t *bundle_nstrands, uint32_t n_bundles, double alpha,
+                   double *shadow)
+{
+    size_t lnpix = (size_t)lwidth * lheight;
+    const orc_cam *c = (const orc_cam *)cam, *lc = (const orc_cam *)lcam;
+    for (int j = 0; j < height; ++j)
+        for (int i = 0; i < width; ++i) {
+            size_t p = (size_t)j * width + i;
+            shadow[p] = 1.0;
+            if (!orc_is_hit(vis[p])) continue;
+            uint64_t v = vis[p] & ORC_ID_MASK;
+            /* the shaded point, as orc_shade_px computes it */
+            double a[3], b[3];
+            orc_proj64(c, pos_w + 4 * v, a);
+            orc_proj64(c, pos_w + 4 * (v + 1), b);
+            double dx = b[0] - a[0], dy = b[1] - a[1];
+            double len2 = dx * dx + dy * dy, ts = 0.0;
+            if (len2 > 0.0) {
+                ts = ((i + 0.5 - a[0]) * dx + (j + 0.5 - a[1]) * dy) / len2;
+                ts = ts < 0.0 ? 0.0 : (ts > 1.0 ? 1.0 : ts);
+            }
+            double iz = a[2] + ts * (b[2] - a[2]);
+            double t3 = ts * b[2] / iz;
+            v3d P0 = d3_loadf(pos_w + 4 * v), P1 = d3_loadf(pos_w + 4 * (v + 1));
+            v3d X = d3_add(P0, d3_scale(d3_sub(P1, P0), t3));
+            /* into the light view */
+            double ex = X.x - lc->eye[0], ey = X.y - lc->eye[1], ez = X.z - lc->eye[2];
+            double LX = lc->R[0] * ex + lc->R[1] * ey + lc->R[2] * ez;
+            double LY = lc->R[3] * ex + lc->R[4] * ey + lc->R[5] * ez;
+            double LZ = lc->R[6] * ex + lc->R[7] * ey + lc->R[8] * ez;
+            if (!(LZ > lc->znear && LZ < lc->zfar)) continue;
+            double lx = lc->cx + lc->fx * LX / LZ, ly = lc->cy - lc->fy * LY / LZ;
+            if (!(lx >= 0.0 && ly >= 0.0 && lx < (double)lwidth && ly < (double)lheight)) continue;
+            size_t lp = (size_t)floor(ly) * lwidth + (size_t)floor(lx);
+            uint64_t k0 = light_vis[lnpix + lp];
+            if (k0 == ORC_EMPTY) continue;
+            uint32_t q0 = (uint32_t)(k0 >> ORC_ID_BITS);
+            double dq = (LZ - lc->znear) / ((double)lc->zfar - lc->znear) * 16777216.0;
+            uint32_t q = dq > 0.0 ? (dq >= 16777215.0 ? 16777215u : (uint32_t)dq) : 0u;
+            if (q <= q0) continue;
+            /* bundle of segment v: last b whose first CP is <= v */
+            uint32_t lo = 0, hi = n_bundles;
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) / 2;
+                if (table[4 * (size_t)mid + 3] <= v) lo = mid; else hi = mid;
+            }
+            float beta = (float)table[4 * (size_t)lo] / (float)bundle_nstrands[lo];
+            uint32_t d = (uint32_t)((float)(q - q0) * beta);
+            uint32_t kq = d / layer_codes;
+            double f;
+            if (kq >= n_layers - 1) {
+                kq = n_layers - 1;
+                f = (double)(d - kq * layer_codes) / layer_codes;
+                f = f < 1.0 ? f : 1.0;
+            } else {
+                f = (double)(d - kq * layer_codes) / layer_codes;
+            }
+            double o = 0.0;
+            for (uint32_t k = 0; k < kq; ++k) o += counts[(size_t)k * lnpix + lp];
+            o += f * counts[(size_t)kq * lnpix + lp];
+            shadow[p] = exp(-alpha * o);
+        }
+    (void)flags;
     return 0;
 }

@@ -78,6 +78,13 @@ def lib():
         L.orc_cover_counts.argtypes = [P, P, P, P, u32, i32, i32, f32, P]
         L.orc_resolve.restype = i32
         L.orc_resolve.argtypes = [P, P, P, P, P, u32, i32, i32, P, P, P, P]
+        L.orc_resolve_shadowed.restype = i32
+        L.orc_resolve_shadowed.argtypes = [P, P, P, P, P, u32, i32, i32, P, P, P, P, P]
+        L.orc_dom_accumulate.restype = i32
+        L.orc_dom_accumulate.argtypes = [P, P, u64, P, i32, i32, f32, P, u32, u32, P]
+        L.orc_dom_shadow.restype = i32
+        L.orc_dom_shadow.argtypes = [P, P, P, P, i32, i32, P, i32, i32, P, P, u32, u32, P, P,
+                                     u32, ctypes.c_double, P]
         _lib = L
     return _lib
 
@@ -269,8 +276,36 @@ def _shade_struct(rp, mode, bg):
     return s
 
 
+def dom_accumulate(pos_w, flags, light_cam, width, height, r_min, light_vis, layer_codes,
+                   n_layers=4):
+    """Deep-opacity-map fragment counts [n_layers][H][W] (uint32) from the
+    light view (Sec. 3.4 shadows; layers as in Yuksel & Keyser 2008)."""
+    pos_w = _c(pos_w, np.float32)
+    counts = np.zeros((n_layers, height, width), np.uint32)
+    lib().orc_dom_accumulate(_p(pos_w), _p(_c(flags, np.uint8)), pos_w.shape[0],
+                             _p(_c(light_cam, np.float32)), width, height, r_min,
+                             _p(_c(light_vis, np.uint64)), layer_codes, n_layers, _p(counts))
+    return counts
+
+
+def dom_shadow(pos_w, flags, vis, cam, width, height, light_cam, lwidth, lheight, light_vis,
+               counts, layer_codes, table, bundle_nstrands, alpha):
+    """Light transmittance [H][W] (binary64) at the shaded point of every
+    centre-hit pixel, with the LOD depth correction of Sec. 3.2.3."""
+    T = np.zeros((height, width), np.float64)
+    counts = _c(counts, np.uint32)
+    tab = _c(table, np.uint32)
+    lib().orc_dom_shadow(_p(_c(pos_w, np.float32)), _p(_c(flags, np.uint8)),
+                         _p(_c(vis, np.uint64)), _p(_c(cam, np.float32)), width, height,
+                         _p(_c(light_cam, np.float32)), lwidth, lheight,
+                         _p(_c(light_vis, np.uint64)), _p(counts), layer_codes,
+                         counts.shape[0], _p(tab), _p(_c(bundle_nstrands, np.uint32)),
+                         tab.shape[0], float(np.float32(alpha)), _p(T))
+    return T
+
+
 def resolve(pos_w, rgb, flags, vis, cams, width, height, rp, mode=0, bg=(0.0, 0.0, 0.0),
-            want_center=False, window=None):
+            want_center=False, window=None, shadow=None):
     """Filtered (mode 0) or centre-only (mode 2) RGBA [S][H][W][4] in float64.
     window (i0, j0, i1, j1), inclusive: compute only those output pixels."""
     S = int(np.asarray(cams).reshape(-1, 18).shape[0])
@@ -278,10 +313,11 @@ def resolve(pos_w, rgb, flags, vis, cams, width, height, rp, mode=0, bg=(0.0, 0.
     cc = np.zeros((S, height, width, 3), np.float64) if want_center else None
     sp = _shade_struct(rp, mode, bg)
     win = None if window is None else np.asarray(window, np.int32)
-    rc = lib().orc_resolve(_p(_c(pos_w, np.float32)), _p(_c(rgb, np.float32)),
-                           _p(_c(flags, np.uint8)), _p(_c(vis, np.uint64)),
-                           _p(_c(cams, np.float32)), S, width, height, ctypes.byref(sp),
-                           _p(win), _p(out), _p(cc))
+    sh = None if shadow is None else _c(shadow, np.float64)
+    rc = lib().orc_resolve_shadowed(_p(_c(pos_w, np.float32)), _p(_c(rgb, np.float32)),
+                                    _p(_c(flags, np.uint8)), _p(_c(vis, np.uint64)),
+                                    _p(_c(cams, np.float32)), S, width, height,
+                                    ctypes.byref(sp), _p(win), _p(sh), _p(out), _p(cc))
     if rc != 0:
         raise ValueError(f"oracle resolve failed ({rc})")
     return (out, cc) if want_center else out

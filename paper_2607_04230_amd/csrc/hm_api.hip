@@ -200,6 +200,26 @@ static hm_status make_shade(const hm_shade_params *p, ShadeK &k)
     k.soft_k = (float)(1.0 / ((double)p->soft_sigma * sqrt(2.0)));
     k.bgr = p->bg[0]; k.bgg = p->bg[1]; k.bgb = p->bg[2];
     k.mode = p->mode;
+    REQUIRE(!p->shadow || p->mode != HM_RESOLVE_SOFT, HM_ERR_INVALID,
+            "shadow applies to the FILTER and CENTER resolves only");
+    k.shadow = p->shadow;
+    return HM_OK;
+}
+
+static hm_status check_dom(const hm_dom_params *p)
+{
+    REQUIRE(p, HM_ERR_INVALID, "dom params NULL");
+    hm_frame lf{1, p->width, p->height};
+    hm_status st = check_frame(&lf);
+    if (st) return st;
+    REQUIRE(p->n_layers >= 1 && p->n_layers <= 8, HM_ERR_RANGE, "n_layers %u outside [1, 8]",
+            p->n_layers);
+    REQUIRE(p->layer_codes >= 1 && p->layer_codes <= 16777216u, HM_ERR_RANGE,
+            "layer_codes outside [1, 2^24]");
+    REQUIRE(isfinite(p->r_min) && p->r_min >= 0.0f, HM_ERR_RANGE, "r_min must be finite, >= 0");
+    REQUIRE(isfinite(p->alpha) && p->alpha > 0.0f, HM_ERR_RANGE, "alpha must be finite, > 0");
+    REQUIRE((double)p->width * p->height * p->n_layers < 4.0e9, HM_ERR_RANGE,
+            "light map too large");
     return HM_OK;
 }
 
@@ -273,6 +293,9 @@ hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bund
         *bytes = raster_workspace(*frame, cap, *p);
     } else if (call == HM_CALL_RESOLVE) {
         *bytes = resolve_workspace(*frame);
+    } else if (call == HM_CALL_DOM) {
+        REQUIRE(cap >= 1 && cap < 0xFFFFFFFFu, HM_ERR_RANGE, "cap outside [1, 2^32 - 2]");
+        *bytes = dom_workspace(cap);
     } else {
         return fail(HM_ERR_INVALID, "unknown call %d", call);
     }
@@ -450,4 +473,36 @@ extern "C" hm_status hm_lod_depth_offset(const uint32_t *table, const uint32_t *
     REQUIRE(n_bundles >= 1, HM_ERR_INVALID, "n_bundles must be >= 1");
     hm::launch_lod_delta(table, bundle_nstrands, n_bundles, delta_out, (hipStream_t)stream);
     return check_launch("hm_lod_depth_offset");
+}
+
+extern "C" hm_status hm_dom_accumulate(const hm_strands *s, const hm_camera *light,
+                                       const hm_dom_params *p, const uint64_t *light_vis,
+                                       uint32_t *counts, void *ws, size_t ws_bytes, void *stream)
+{
+    hm_status st;
+    if ((st = check_strands(s)) || (st = check_dom(p))) return st;
+    REQUIRE(s->n_scenes == 1, HM_ERR_INVALID, "deep opacity maps take a single scene");
+    REQUIRE(light && light_vis && counts, HM_ERR_INVALID, "NULL argument");
+    if ((st = check_ws(ws, ws_bytes, hm::dom_workspace(s->cap)))) return st;
+    hm::launch_dom_accum(*s, light, *p, light_vis, counts, ws, (hipStream_t)stream);
+    return check_launch("hm_dom_accumulate");
+}
+
+extern "C" hm_status hm_dom_shadow(const hm_strands *s, const uint64_t *vis, const hm_camera *cam,
+                                   const hm_frame *frame, const hm_camera *light,
+                                   const hm_dom_params *p, const uint64_t *light_vis,
+                                   const uint32_t *counts, const uint32_t *table,
+                                   const uint32_t *bundle_nstrands, uint32_t n_bundles,
+                                   float *shadow, void *stream)
+{
+    hm_status st;
+    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = check_dom(p))) return st;
+    REQUIRE(frame->n_scenes == 1 && s->n_scenes == 1, HM_ERR_INVALID,
+            "deep opacity maps take a single scene");
+    REQUIRE(vis && cam && light && light_vis && counts && table && bundle_nstrands && shadow,
+            HM_ERR_INVALID, "NULL argument");
+    REQUIRE(n_bundles >= 1, HM_ERR_INVALID, "n_bundles must be >= 1");
+    hm::launch_dom_shadow(*s, vis, cam, *frame, light, *p, light_vis, counts, table,
+                          bundle_nstrands, n_bundles, shadow, (hipStream_t)stream);
+    return check_launch("hm_dom_shadow");
 }

@@ -25,6 +25,7 @@ struct ShadeK {
     float soft_k;              // 1 / (sigma * sqrt(2))
     float bgr, bgg, bgb;
     int mode;
+    const float *shadow;       // light transmittance per pixel, or nullptr
 };
 
 size_t align_up(size_t x, size_t a = 256);
@@ -55,6 +56,15 @@ void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *c
 void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camera *cams,
                         const hm_frame &f, const ShadeK &k, const float *d_out, float *gpos,
                         float *grgb, hipStream_t st);
+
+// deep-opacity-map shadows
+size_t dom_workspace(uint32_t cap);
+void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_params &p,
+                      const uint64_t *light_vis, uint32_t *counts, void *ws, hipStream_t st);
+void launch_dom_shadow(const hm_strands &s, const uint64_t *vis, const hm_camera *cam,
+                       const hm_frame &f, const hm_camera *light, const hm_dom_params &p,
+                       const uint64_t *light_vis, const uint32_t *counts, const uint32_t *table,
+                       const uint32_t *nstr, uint32_t n_bundles, float *shadow, hipStream_t st);
 
 // number of workgroups for grid-stride kernels
 uint32_t stride_grid(size_t n, uint32_t block);

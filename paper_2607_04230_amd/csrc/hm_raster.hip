@@ -843,6 +843,49 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
     }
 }
 
+// ------------------------------------------------------------------ deep opacity map
+// Fragment counts per light-map layer: one thread per segment of the light
+// view's screen records, candidate pixels by row spans, the conservative test
+// of the raster, then a 32-bit global add into layer
+// min((q - q0) / layer_codes, n_layers - 1), q0 the nearest fragment of the
+// pixel (the light view's conservative layer).
+__global__ __launch_bounds__(256) void k_dom_accum(const float4 *proj, const uint8_t *flags,
+                                                   const uint32_t *scene_off, RasterK rk,
+                                                   uint32_t cap, const hm_camera *light,
+                                                   const uint64_t *light_vis,
+                                                   uint32_t layer_codes, uint32_t n_layers,
+                                                   uint32_t *counts)
+{
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    const size_t hw = (size_t)rk.W * rk.H;
+    const uint64_t *va = light_vis + hw;
+    float zn, inv_range;
+    scene_depth_consts(light, 0, zn, inv_range);
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        Seg sg;
+        if (!load_seg(proj, flags, v, v, n, rk.r_min, sg)) continue;
+        int i0, i1, j0, j1;
+        if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
+        for (int j = j0; j <= j1; ++j) {
+            int a0, a1;
+            row_span(sg, j, a0, a1);
+            a0 = max(a0, i0);
+            a1 = min(a1, i1);
+            for (int i = a0; i <= a1; ++i) {
+                uint32_t q;
+                bool cc, ca;
+                cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                if (!ca) continue;
+                const size_t p = (size_t)j * rk.W + i;
+                const uint32_t q0 = (uint32_t)(va[p] >> HM_ID_BITS);
+                uint32_t k = q > q0 ? (q - q0) / layer_codes : 0u;
+                k = k < n_layers - 1u ? k : n_layers - 1u;
+                atomicAdd(counts + (size_t)k * hw + p, 1u);
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host side
 static RasterK make_rk(const hm_frame &f, const hm_raster_params &p)
 {
@@ -989,6 +1032,35 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     hipLaunchKernelGGL(k_raster_long, dim3(256), dim3(256), 0, st, (const float4 *)w.proj,
                        (const uint8_t *)s.flags, s.scene_off, cams, rk, s.cap,
                        (const uint32_t *)w.long_list, (const uint32_t *)w.counters, vis);
+}
+
+}  // namespace hm
+
+namespace hm {
+
+size_t dom_workspace(uint32_t cap) { return align_up(sizeof(float4) * (size_t)cap); }
+
+void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_params &p,
+                      const uint64_t *light_vis, uint32_t *counts, void *ws, hipStream_t st)
+{
+    hm_frame f;
+    f.n_scenes = 1;
+    f.width = p.width;
+    f.height = p.height;
+    hm_raster_params rp;
+    raster_defaults(f, rp);
+    rp.r_min = p.r_min;
+    const RasterK rk = make_rk(f, rp);
+    float4 *proj = (float4 *)ws;
+    const size_t hw = (size_t)p.width * p.height;
+    hipLaunchKernelGGL(k_fill_u32, dim3(stride_grid(hw * p.n_layers, 256)), dim3(256), 0, st,
+                       counts, (uint32_t)(hw * p.n_layers), 0u);
+    hipLaunchKernelGGL(k_project, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const float4 *>(s.pos_w), s.scene_off, rk, light, s.cap,
+                       proj);
+    hipLaunchKernelGGL(k_dom_accum, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st,
+                       (const float4 *)proj, (const uint8_t *)s.flags, s.scene_off, rk, s.cap,
+                       light, light_vis, p.layer_codes, p.n_layers, counts);
 }
 
 }  // namespace hm

@@ -92,8 +92,10 @@ __device__ __forceinline__ SegShade seg_shade_point(const float4 *pos, const flo
     return r;
 }
 
-// Kajiya-Kay style diffuse sin(T, L) plus a specular lobe (1 - (T.H)^2)^(2^n).
-__device__ __forceinline__ V3 shade(const SegShade &g, const Cam &c, const ShadeK &k)
+// Kajiya-Kay style diffuse sin(T, L) plus a specular lobe (1 - (T.H)^2)^(2^n);
+// sh (the light's transmittance) scales both direct terms, not the ambient one.
+__device__ __forceinline__ V3 shade(const SegShade &g, const Cam &c, const ShadeK &k,
+                                    float sh = 1.0f)
 {
     const V3 L = v3(k.Lx, k.Ly, k.Lz);
     const V3 V = nrm(v3(c.ex, c.ey, c.ez) - g.X);
@@ -103,9 +105,10 @@ __device__ __forceinline__ V3 shade(const SegShade &g, const Cam &c, const Shade
     const float diff = sd > 0.0f ? sqrtf(sd) : 0.0f;
     float sp = fmaxx(1.0f - th * th, 0.0f);
     for (int i = 0; i < k.nsq; ++i) sp = sp * sp;
-    const float dd = k.ka + k.kd * diff;
-    return v3(g.alb.x * k.Er * dd + k.ks * k.Er * sp, g.alb.y * k.Eg * dd + k.ks * k.Eg * sp,
-              g.alb.z * k.Eb * dd + k.ks * k.Eb * sp);
+    const float dd = k.ka + (sh * k.kd) * diff;
+    const float ks = sh * k.ks;
+    return v3(g.alb.x * k.Er * dd + ks * k.Er * sp, g.alb.y * k.Eg * dd + ks * k.Eg * sp,
+              g.alb.z * k.Eb * dd + ks * k.Eb * sp);
 }
 
 // ------------------------------------------------------------------ centre shading
@@ -130,7 +133,7 @@ __global__ __launch_bounds__(256) void k_shade(const float4 *pos, const float4 *
             const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
             const SegShade g = seg_shade_point(pos, rgb, flags, a, b, v, (double)i + 0.5,
                                                (double)j + 0.5);
-            col = shade(g, c, k);
+            col = shade(g, c, k, k.shadow ? k.shadow[p] : 1.0f);
         }
         const uint32_t bits = (hc ? (uint32_t)(kc >> HM_ID_BITS) : 0u) | (hc ? 1u << 24 : 0u) |
                               ((hc || ha) ? 1u << 25 : 0u);
@@ -643,6 +646,120 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const float4 *pos, const float
         atomic_add3(grgb + 4 * (size_t)v, gc0);
         atomic_add3(grgb + 4 * ((size_t)v + 1), gc1);
     }
+}
+
+// ------------------------------------------------------------------ deep-opacity lookup
+// Transmittance towards the light at the shaded point of every pixel with a
+// centre hit, everything in binary64 in the order the host-side definition
+// uses: screen projection as (f X) / Z, the closest screen parameter, the
+// perspective-correct segment parameter, the point X, its light-view
+// coordinates, light pixel and 24-bit depth code.  The LOD-corrected code
+// q' = q0 + (uint32)((float)(q - q0) * beta) is a binary32 product; the
+// opacity in front of q' sums whole layers and the interpolated part of the
+// layer holding q' (the last layer taken whole once passed).
+struct DomK {
+    uint32_t W, H, LW, LH;
+    uint32_t layer_codes, n_layers, n_bundles;
+    double alpha;
+};
+
+__device__ __forceinline__ void dom_proj(const DCam &c, D3 P, double &x, double &y, double &iz)
+{
+    const double dx = P.x - c.e[0], dy = P.y - c.e[1], dz = P.z - c.e[2];
+    const double X = c.R[0] * dx + c.R[1] * dy + c.R[2] * dz;
+    const double Y = c.R[3] * dx + c.R[4] * dy + c.R[5] * dz;
+    const double Z = c.R[6] * dx + c.R[7] * dy + c.R[8] * dz;
+    x = c.cx + c.fx * X / Z;
+    y = c.cy - c.fy * Y / Z;
+    iz = 1.0 / Z;
+}
+
+__global__ __launch_bounds__(256) void k_dom_shadow(const float4 *pos, const uint64_t *vis,
+                                                    const hm_camera *cam, const hm_camera *light,
+                                                    const uint64_t *light_vis,
+                                                    const uint32_t *counts, const uint32_t *table,
+                                                    const uint32_t *nstr, DomK d, float *shadow)
+{
+    const size_t hw = (size_t)d.W * d.H, lhw = (size_t)d.LW * d.LH;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < hw;
+         p += (size_t)gridDim.x * blockDim.x) {
+        float T = 1.0f;
+        const uint64_t kc = vis[p];
+        if (is_hit(kc)) {
+            const uint32_t v = (uint32_t)(kc & HM_ID_MASK);
+            const DCam c = load_dcam(cam);
+            const uint32_t j = (uint32_t)(p / d.W), i = (uint32_t)(p - (size_t)j * d.W);
+            const D3 P0 = dl(pos[v]), P1 = dl(pos[v + 1]);
+            double ax, ay, aiz, bx, by, biz;
+            dom_proj(c, P0, ax, ay, aiz);
+            dom_proj(c, P1, bx, by, biz);
+            const double dx = bx - ax, dy = by - ay;
+            const double len2 = dx * dx + dy * dy;
+            double ts = 0.0;
+            if (len2 > 0.0) {
+                ts = (((double)i + 0.5 - ax) * dx + ((double)j + 0.5 - ay) * dy) / len2;
+                ts = ts < 0.0 ? 0.0 : (ts > 1.0 ? 1.0 : ts);
+            }
+            const double iz = aiz + ts * (biz - aiz);
+            const double t3 = ts * biz / iz;
+            const D3 X = P0 + (P1 - P0) * t3;
+            const DCam lc = load_dcam(light);
+            const double zn = light->znear, zf = light->zfar;
+            const double ex = X.x - lc.e[0], ey = X.y - lc.e[1], ez = X.z - lc.e[2];
+            const double LX = lc.R[0] * ex + lc.R[1] * ey + lc.R[2] * ez;
+            const double LY = lc.R[3] * ex + lc.R[4] * ey + lc.R[5] * ez;
+            const double LZ = lc.R[6] * ex + lc.R[7] * ey + lc.R[8] * ez;
+            const double lx = lc.cx + lc.fx * LX / LZ, ly = lc.cy - lc.fy * LY / LZ;
+            if (LZ > zn && LZ < zf && lx >= 0.0 && ly >= 0.0 && lx < (double)d.LW &&
+                ly < (double)d.LH) {
+                const size_t lp = (size_t)floor(ly) * d.LW + (size_t)floor(lx);
+                const uint64_t k0 = light_vis[lhw + lp];
+                const double dq = (LZ - zn) / (zf - zn) * 16777216.0;
+                const uint32_t q =
+                    dq > 0.0 ? (dq >= 16777215.0 ? 16777215u : (uint32_t)dq) : 0u;
+                const uint32_t q0 = (uint32_t)(k0 >> HM_ID_BITS);
+                if (k0 != HM_EMPTY && q > q0) {
+                    // bundle of segment v: last b with first CP table[4b+3] <= v
+                    uint32_t lo = 0, hi = d.n_bundles;
+                    while (hi - lo > 1) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (table[4 * (size_t)mid + 3] <= v) lo = mid; else hi = mid;
+                    }
+                    const float beta = (float)table[4 * (size_t)lo] / (float)nstr[lo];
+                    const uint32_t dd = (uint32_t)((float)(q - q0) * beta);
+                    uint32_t kq = dd / d.layer_codes;
+                    double f;
+                    if (kq >= d.n_layers - 1) {
+                        kq = d.n_layers - 1;
+                        f = (double)(dd - kq * d.layer_codes) / d.layer_codes;
+                        f = f < 1.0 ? f : 1.0;
+                    } else {
+                        f = (double)(dd - kq * d.layer_codes) / d.layer_codes;
+                    }
+                    double o = 0.0;
+                    for (uint32_t k = 0; k < kq; ++k) o += counts[(size_t)k * lhw + lp];
+                    o += f * counts[(size_t)kq * lhw + lp];
+                    T = (float)exp(-d.alpha * o);
+                }
+            }
+        }
+        shadow[p] = T;
+    }
+}
+
+void launch_dom_shadow(const hm_strands &s, const uint64_t *vis, const hm_camera *cam,
+                       const hm_frame &f, const hm_camera *light, const hm_dom_params &p,
+                       const uint64_t *light_vis, const uint32_t *counts, const uint32_t *table,
+                       const uint32_t *nstr, uint32_t n_bundles, float *shadow, hipStream_t st)
+{
+    DomK d;
+    d.W = f.width; d.H = f.height; d.LW = p.width; d.LH = p.height;
+    d.layer_codes = p.layer_codes; d.n_layers = p.n_layers; d.n_bundles = n_bundles;
+    d.alpha = p.alpha;
+    const size_t npix = (size_t)f.width * f.height;
+    hipLaunchKernelGGL(k_dom_shadow, dim3(stride_grid(npix, 256)), dim3(256), 0, st,
+                       reinterpret_cast<const float4 *>(s.pos_w), vis, cam, light, light_vis,
+                       counts, table, nstr, d, shadow);
 }
 
 void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camera *cams,

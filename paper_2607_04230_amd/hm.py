@@ -20,7 +20,7 @@ HM_OK = 0
 LOD_OFF, LOD_ON = 0, 1
 RASTER_TILED, RASTER_DIRECT, RASTER_TILED_ROWS = 0, 1, 2
 RESOLVE_FILTER, RESOLVE_SOFT, RESOLVE_CENTER = 0, 1, 2
-CALL_LOD, CALL_RASTER, CALL_RESOLVE = 0, 1, 2
+CALL_LOD, CALL_RASTER, CALL_RESOLVE, CALL_DOM = 0, 1, 2, 3
 
 _u32, _i32, _f32, _vp, _sz = ctypes.c_uint32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
 
@@ -65,13 +65,19 @@ class ShadeParams(ctypes.Structure):
                 ("ks", _f32), ("spec_squarings", _i32), ("filter_radius", _i32), ("s_par", _f32),
                 ("s_perp", _f32), ("sigma_c", _f32), ("iso_scale", _f32), ("depth_reject", _f32),
                 ("depth_mismatch", _f32), ("strip_half", _f32), ("iso_len", _f32),
-                ("soft_sigma", _f32), ("bg", _f32 * 3), ("mode", _i32)]
+                ("soft_sigma", _f32), ("bg", _f32 * 3), ("mode", _i32), ("shadow", _vp)]
+
+
+class DomParams(ctypes.Structure):
+    _fields_ = [("width", _u32), ("height", _u32), ("n_layers", _u32), ("layer_codes", _u32),
+                ("r_min", _f32), ("alpha", _f32)]
 
 
 EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_shade",
            "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
            "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
-           "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset"]
+           "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset",
+           "hm_dom_accumulate", "hm_dom_shadow"]
 
 
 def lod_depth_offset(table, bundle_nstrands, delta_out):
@@ -81,6 +87,26 @@ def lod_depth_offset(table, bundle_nstrands, delta_out):
     L.hm_lod_depth_offset.restype = _i32
     _check(L.hm_lod_depth_offset(_ptr(table), _ptr(bundle_nstrands), table.shape[0],
                                  _ptr(delta_out), _stream()), "hm_lod_depth_offset")
+
+
+def dom_accumulate(st, light, dp, light_vis, counts, ws):
+    """Deep-opacity-map fragment counts [n_layers][H][W] (uint32 / int32 tensor out)."""
+    L = load()
+    L.hm_dom_accumulate.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    _check(L.hm_dom_accumulate(ctypes.byref(st), _ptr(light), ctypes.byref(dp), _ptr(light_vis),
+                               _ptr(counts), _ptr(ws), ws.numel() * ws.element_size(),
+                               _stream()),
+           "hm_dom_accumulate")
+
+
+def dom_shadow(st, vis, cam, fr, light, dp, light_vis, counts, table, bundle_nstrands, shadow):
+    """Light transmittance per camera pixel [H][W] (float32 tensor out)."""
+    L = load()
+    L.hm_dom_shadow.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _u32, _vp, _vp]
+    _check(L.hm_dom_shadow(ctypes.byref(st), _ptr(vis), _ptr(cam), ctypes.byref(fr), _ptr(light),
+                           ctypes.byref(dp), _ptr(light_vis), _ptr(counts), _ptr(table),
+                           _ptr(bundle_nstrands), table.shape[0], _ptr(shadow), _stream()),
+           "hm_dom_shadow")
 
 
 class FrameDesc(ctypes.Structure):

@@ -12,7 +12,7 @@ from typing import Optional
 import numpy as np
 
 from . import hm
-from .scenes import ResolveParams, Scene
+from .scenes import ResolveParams, Scene, ShadowParams, light_camera
 
 
 def _u32(a: np.ndarray):
@@ -97,6 +97,50 @@ class DeviceScene:
         self.lod()
         self.generate()
         self.raster()
+        self.resolve()
+        return self.out
+
+    def shadows(self, shp: ShadowParams):
+        """Deep-opacity-map shadows of a single-scene frame (Sec. 3.4 with the
+        LOD depth correction of Sec. 3.2.3): the stream is rasterized from the
+        light camera, the fragment counts per layer accumulated, and the
+        transmittance of every pixel's shaded point computed from the current
+        visibility buffer; later resolves are shadowed by it.  Call after
+        raster()."""
+        import torch
+        if self.S != 1:
+            raise ValueError("deep opacity maps take a single scene")
+        dev = "cuda"
+        if getattr(self, "_dom", None) is None or self._dom[0] != shp:
+            lfr = hm.frame(1, shp.width, shp.height)
+            lrp = hm.raster_defaults(lfr)
+            lrp.r_min = shp.r_min
+            self._dom = (shp, _f32(light_camera(self.sc, shp, self.resolve_params)), lfr, lrp,
+                         torch.empty((1, 2, shp.height, shp.width), dtype=torch.int64, device=dev),
+                         torch.zeros(hm.workspace_size(hm.CALL_RASTER, lfr, cap=self.cap,
+                                                       rparams=lrp),
+                                     dtype=torch.uint8, device=dev),
+                         hm.DomParams(shp.width, shp.height, shp.n_layers, shp.layer_codes(),
+                                      shp.r_min, shp.alpha),
+                         torch.empty((shp.n_layers, shp.height, shp.width), dtype=torch.int32,
+                                     device=dev),
+                         torch.zeros(hm.workspace_size(hm.CALL_DOM, lfr, cap=self.cap),
+                                     dtype=torch.uint8, device=dev),
+                         torch.ones((self.H, self.W), dtype=torch.float32, device=dev))
+        _, light, lfr, lrp, lvis, lws, dp, counts, dws, shadow = self._dom
+        hm.raster_vis(self.st, light, lfr, lrp, None, lvis, lws)
+        hm.dom_accumulate(self.st, light, dp, lvis, counts, dws)
+        hm.dom_shadow(self.st, self.vis, self.cams, self.fr, light, dp, lvis, counts, self.table,
+                      self.mesh_t["bundle_nstrands"], shadow)
+        self.light_cam, self.light_vis, self.dom_counts, self.shadow = light, lvis, counts, shadow
+        self.sp.shadow = hm._ptr(shadow)
+        return shadow
+
+    def render_shadowed(self, shp: ShadowParams):
+        self.lod()
+        self.generate()
+        self.raster()
+        self.shadows(shp)
         self.resolve()
         return self.out
 

@@ -56,6 +56,42 @@ class ResolveParams:
 
 
 @dataclasses.dataclass
+class ShadowParams:
+    """Deep-opacity-map shadows (Sec. 3.4; the paper cites Yuksel & Keyser
+    2008 for the map and gives no constants, so these are choices): a pinhole
+    light camera looking at the groom from the light direction, 4 layers of
+    fixed thickness behind the nearest fragment, and a constant opacity per
+    fragment."""
+    width: int = 512
+    height: int = 512
+    distance: float = 4.0            # light camera eye = groom centre + distance * L
+    vfov_deg: float = 45.0
+    znear: float = 0.1
+    zfar: float = 10.0
+    n_layers: int = 4
+    layer_world: float = 0.05        # layer thickness (world units along the light view)
+    alpha: float = 0.05              # opacity of one fragment
+    r_min: float = 0.5               # fragment coverage half width in the light view (px)
+
+    def layer_codes(self) -> int:
+        """Layer thickness in 24-bit depth-code units."""
+        return max(1, int(self.layer_world / (self.zfar - self.znear) * 16777216.0))
+
+
+def light_camera(sc: "Scene", sp: ShadowParams, rp: "ResolveParams" = None) -> np.ndarray:
+    """Light camera record [1][18] for scene `sc`: a pinhole at the groom's
+    bounding-box centre + distance * L looking back at that centre."""
+    rp = rp or ResolveParams()
+    L = np.asarray(rp.light_dir, np.float64)
+    L /= np.linalg.norm(L)
+    pts = np.asarray(sc.layer_pos, np.float64).reshape(-1, 3)
+    centre = 0.5 * (pts.min(0) + pts.max(0))
+    up = (0.0, 0.0, 1.0) if abs(L[1]) > 0.99 else (0.0, 1.0, 0.0)
+    return look_at_camera(centre + sp.distance * L, centre, sp.width, sp.height,
+                          vfov_deg=sp.vfov_deg, znear=sp.znear, zfar=sp.zfar, up=up)[None]
+
+
+@dataclasses.dataclass
 class Scene:
     """Everything one render call needs, as host numpy arrays."""
     name: str
@@ -259,7 +295,8 @@ def config_head(seed=1002, width=1920, height=1080, strands_per_quad=64, n_cp=17
                  width, height, sz, seed=seed, strand_width=strand_width, mode=mode)
 
 
-def config_lod(seed=1003, width=2560, height=1440, n_heads=32, lod_lambda=3.0) -> Scene:
+def config_lod(seed=1003, width=2560, height=1440, n_heads=32, lod_lambda=3.0, d_near=2.0,
+               d_far=60.0) -> Scene:
     """32 full-head characters at geometric distances 2..60 in one 1440p view, LOD on."""
     rng = np.random.default_rng(seed)
     pts, quads = scalp("head2000")
@@ -269,7 +306,7 @@ def config_lod(seed=1003, width=2560, height=1440, n_heads=32, lod_lambda=3.0) -
     hfov = 2.0 * math.atan(width / height * math.tan(vfov / 2))
     layers, qs, centers = [], [], []
     for k in range(n_heads):
-        d = 2.0 * 30.0 ** (k / (n_heads - 1))
+        d = d_near * (d_far / d_near) ** (k / max(n_heads - 1, 1))
         frac = (0.618 * k) % 1.0
         a = (frac - 0.5) * 0.8 * hfov
         c = np.array([d * math.sin(a), -0.4, -d * math.cos(a)])

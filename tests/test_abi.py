@@ -108,3 +108,72 @@ def test_validation_errors_are_reported():
     assert L.hm_lod_select(ctypes.byref(m), dummy, ctypes.byref(fr), ctypes.byref(lp), dummy,
                            dummy, dummy, dummy, 1 << 20, None) == 2
     assert b"n_layers" in L.hm_last_error()
+    # shadows: single scene, layer count and opacity ranges, workspace
+    dp = hm.DomParams(64, 64, 4, 1000, 0.5, 0.05)
+    ws = hm.workspace_size(hm.CALL_DOM, fr, cap=1000)
+    assert ws >= 16 * 1000
+    assert L.hm_dom_accumulate(ctypes.byref(st), dummy, ctypes.byref(dp), dummy, dummy, dummy,
+                               8, None) == 3
+    for field, val in (("n_layers", 0), ("n_layers", 9), ("layer_codes", 0), ("alpha", 0.0)):
+        bad_dp = hm.DomParams(64, 64, 4, 1000, 0.5, 0.05)
+        setattr(bad_dp, field, val)
+        assert L.hm_dom_accumulate(ctypes.byref(st), dummy, ctypes.byref(bad_dp), dummy, dummy,
+                                   dummy, 1 << 30, None) == 2, field
+    assert L.hm_dom_shadow(ctypes.byref(st), dummy, dummy, ctypes.byref(fr2), dummy,
+                           ctypes.byref(dp), dummy, dummy, dummy, dummy, 4, dummy, None) == 1
+    assert b"single scene" in L.hm_last_error()
+    # a shadowed soft resolve is refused (its backward has no shadow term)
+    sp = hm.shade_params(ResolveParams(), hm.RESOLVE_SOFT)
+    sp.shadow = 0x1000
+    assert L.hm_resolve_shade(ctypes.byref(st), dummy, dummy, ctypes.byref(fr), ctypes.byref(sp),
+                              dummy, dummy, 1 << 30, None) == 1
+
+
+_LAYOUT = {
+    "hm_camera": ("Camera", ["R", "eye", "fx", "zfar"]),
+    "hm_frame": ("Frame", ["n_scenes", "height"]),
+    "hm_hair_mesh": ("HairMesh", None),
+    "hm_strands": ("Strands", None),
+    "hm_lod_params": ("LodParams", None),
+    "hm_gen_params": ("GenParams", None),
+    "hm_raster_params": ("RasterParams", None),
+    "hm_shade_params": ("ShadeParams", None),
+    "hm_dom_params": ("DomParams", None),
+    "hm_frame_desc": ("FrameDesc", None),
+}
+
+
+_C_NAME = {"lam": "lambda"}     # a Python keyword on the C side
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and every field offset of the header's structs, compiled by the
+    host C compiler, equal those of the Python binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hm.h"', 'int main(void) {']
+    for cname, (pyname, _) in _LAYOUT.items():
+        if not hasattr(hm, pyname):
+            continue
+        py = getattr(hm, pyname)
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            c = _C_NAME.get(f[0], f[0])
+            lines.append(f'printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {c}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    seen = 0
+    for line in out.splitlines():
+        cname, field, val = line.split()
+        py = getattr(hm, _LAYOUT[cname][0])
+        got = ctypes.sizeof(py) if field == "size" else getattr(py, field).offset
+        assert got == int(val), (cname, field, got, val)
+        seen += 1
+    assert seen > 60
