@@ -254,10 +254,11 @@ hm_status hm_resolve_shade_bwd(const hm_strands *s, const uint64_t *vis, const h
 /* ------------------------------------------------------------------ shadows */
 /* Deep-opacity-map shadows (Sec. 3.4, which cites Yuksel & Keyser 2008 for
  * the map) queried with the LOD depth correction of Sec. 3.2.3.  Single
- * scene.  The light is a pinhole camera; its view of the stream is first
- * rasterized with hm_raster_vis (frame {1, width, height}, no scene depth)
- * into light_vis, whose conservative layer gives the nearest fragment q0 of
- * every light pixel. */
+ * scene.  The light is a pinhole camera; hm_dom_accumulate rasterizes the
+ * stream from it (as hm_raster_vis does for frame {1, width, height}, no
+ * scene depth, r_min below) into light_vis, whose conservative layer gives
+ * the nearest fragment q0 of every light pixel, and then counts the
+ * fragments behind q0 per layer. */
 typedef struct {
     uint32_t width, height;  /* light map resolution */
     uint32_t n_layers;       /* layers behind the nearest fragment, 1 .. 8 */
@@ -266,14 +267,17 @@ typedef struct {
     float alpha;             /* opacity of one fragment (> 0) */
 } hm_dom_params;
 
-/* counts[n_layers][height][width] (uint32, device, overwritten): every
- * (segment, light pixel) pair accepted by the conservative test, at depth
- * code q, adds 1 to layer min((q - q0) / layer_codes, n_layers - 1) of its
- * pixel (exact and order-independent).  ws: hm_workspace_size(HM_CALL_DOM,
- * {1, width, height}, 0, cap, NULL) bytes. */
+/* light_vis[2][height][width] (uint64, device, overwritten): the light
+ * view's visibility buffer.  counts[n_layers][height][width] (uint32,
+ * device, overwritten): every (segment, light pixel) pair accepted by the
+ * conservative test, at depth code q, adds 1 to layer
+ * min((q - q0) / layer_codes, n_layers - 1) of its pixel (exact and
+ * order-independent).  ws: hm_workspace_size(HM_CALL_DOM, {1, width,
+ * height}, 0, cap, NULL) bytes; the light view's bins are built there and
+ * walked twice (visibility, then counts). */
 hm_status hm_dom_accumulate(const hm_strands *s, const hm_camera *light, const hm_dom_params *p,
-                            const uint64_t *light_vis, uint32_t *counts, void *ws,
-                            size_t ws_bytes, void *stream);
+                            uint64_t *light_vis, uint32_t *counts, void *ws, size_t ws_bytes,
+                            void *stream);
 
 /* shadow[height][width] (float, device) of the camera frame `frame` (one
  * scene) with visibility vis: for a pixel with a centre hit, the shaded point

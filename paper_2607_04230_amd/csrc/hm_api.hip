@@ -295,7 +295,8 @@ hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bund
         *bytes = resolve_workspace(*frame);
     } else if (call == HM_CALL_DOM) {
         REQUIRE(cap >= 1 && cap < 0xFFFFFFFFu, HM_ERR_RANGE, "cap outside [1, 2^32 - 2]");
-        *bytes = dom_workspace(cap);
+        REQUIRE(frame->n_scenes == 1, HM_ERR_INVALID, "the light map frame has one scene");
+        *bytes = dom_workspace(*frame, cap);
     } else {
         return fail(HM_ERR_INVALID, "unknown call %d", call);
     }
@@ -476,14 +477,15 @@ extern "C" hm_status hm_lod_depth_offset(const uint32_t *table, const uint32_t *
 }
 
 extern "C" hm_status hm_dom_accumulate(const hm_strands *s, const hm_camera *light,
-                                       const hm_dom_params *p, const uint64_t *light_vis,
+                                       const hm_dom_params *p, uint64_t *light_vis,
                                        uint32_t *counts, void *ws, size_t ws_bytes, void *stream)
 {
     hm_status st;
     if ((st = check_strands(s)) || (st = check_dom(p))) return st;
     REQUIRE(s->n_scenes == 1, HM_ERR_INVALID, "deep opacity maps take a single scene");
     REQUIRE(light && light_vis && counts, HM_ERR_INVALID, "NULL argument");
-    if ((st = check_ws(ws, ws_bytes, hm::dom_workspace(s->cap)))) return st;
+    const hm_frame lf{1, p->width, p->height};
+    if ((st = check_ws(ws, ws_bytes, hm::dom_workspace(lf, s->cap)))) return st;
     hm::launch_dom_accum(*s, light, *p, light_vis, counts, ws, (hipStream_t)stream);
     return check_launch("hm_dom_accumulate");
 }

@@ -58,9 +58,9 @@ void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camer
                         float *grgb, hipStream_t st);
 
 // deep-opacity-map shadows
-size_t dom_workspace(uint32_t cap);
+size_t dom_workspace(const hm_frame &light_frame, uint32_t cap);
 void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_params &p,
-                      const uint64_t *light_vis, uint32_t *counts, void *ws, hipStream_t st);
+                      uint64_t *light_vis, uint32_t *counts, void *ws, hipStream_t st);
 void launch_dom_shadow(const hm_strands &s, const uint64_t *vis, const hm_camera *cam,
                        const hm_frame &f, const hm_camera *light, const hm_dom_params &p,
                        const uint64_t *light_vis, const uint32_t *counts, const uint32_t *table,

@@ -544,6 +544,21 @@ static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat)
     return b;
 }
 
+// Tile words of a pass: two layers of 64-bit keys, or (deep-opacity counting)
+// the first-fragment depth code plus one count per layer, 32 bits each.
+__host__ __device__ inline uint32_t tile_words(uint32_t TT, bool dom, uint32_t n_layers)
+{
+    return dom ? (1u + n_layers) * TT : 4u * TT;
+}
+
+// Deep-opacity counting pass of the tile raster: q0 of every pixel comes from
+// the light view's conservative layer (vis), accepted conservative pairs are
+// counted in layer min((q - q0) / layer_codes, n_layers - 1).
+struct DomK {
+    uint32_t *counts;       // [n_layers][H][W]
+    uint32_t layer_codes, n_layers;
+};
+
 // Persistent tile raster.  Work items (a tile and a chunk of its segment
 // list) are pulled from counters[1].  The tile's two layers live in LDS.
 //
@@ -562,11 +577,21 @@ static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat)
 //
 // NBC: the workgroup size when known at compile time (the record fields then
 // sit at fixed LDS offsets), 0 for any blockDim.
-template <bool FLAT, uint32_t NBC>
+__device__ __forceinline__ void dom_count(uint32_t *cnt, const uint32_t *q0t, uint32_t x,
+                                          uint32_t TT, uint32_t q, const DomK &dk)
+{
+    const uint32_t q0 = q0t[x];
+    uint32_t k = q > q0 ? (q - q0) / dk.layer_codes : 0u;
+    k = k < dk.n_layers - 1u ? k : dk.n_layers - 1u;
+    atomicAdd(&cnt[k * TT + x], 1u);
+}
+
+template <bool FLAT, uint32_t NBC, bool DOM>
 __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
                                uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
-                               const uint32_t *entries, uint32_t *counters, uint64_t *vis)
+                               const uint32_t *entries, uint32_t *counters, uint64_t *vis,
+                               DomK dk)
 {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t sh_item;
@@ -574,7 +599,8 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
     const uint32_t TT = rk.T * rk.T;
     const uint32_t nb = NBC ? NBC : blockDim.x;
     uint64_t *lc = lds, *la = lds + TT;
-    float *rf = reinterpret_cast<float *>(lds + 2 * TT);
+    uint32_t *q0t = reinterpret_cast<uint32_t *>(lds), *cnt = q0t + TT;    // DOM only
+    float *rf = reinterpret_cast<float *>(lds) + tile_words(TT, DOM, dk.n_layers);
     uint32_t *rw = reinterpret_cast<uint32_t *>(rf);
     uint32_t *r_sid = rw + REC_FLOATS * nb;          // stream id
     uint32_t *r_rc = r_sid + nb;                     // first row slot + clip
@@ -593,9 +619,13 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
     const uint32_t tiles_per_scene = rk.ntx * rk.nty;
     for (;;) {
         if (threadIdx.x == 0) sh_item = atomicAdd(&counters[1], 1u);
-        for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
-            lc[x] = HM_EMPTY;
-            la[x] = HM_EMPTY;
+        if (DOM) {
+            for (uint32_t x = threadIdx.x; x < dk.n_layers * TT; x += blockDim.x) cnt[x] = 0u;
+        } else {
+            for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
+                lc[x] = HM_EMPTY;
+                la[x] = HM_EMPTY;
+            }
         }
         __syncthreads();
         const uint32_t item = sh_item;
@@ -623,7 +653,18 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
         // a tile that is one work item owns its pixels: start from the
         // prefilled values and write back without atomics
         const bool whole = tend - tile_off[t] <= rk.chunk;
-        if (whole) {
+        if (DOM) {
+            for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
+                const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+                uint32_t q0 = 0xFFFFFFFFu;
+                if (lx < tw && ly < th) {
+                    const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
+                    q0 = (uint32_t)(va[p] >> HM_ID_BITS);
+                }
+                q0t[x] = q0;
+            }
+            __syncthreads();
+        } else if (whole) {
             for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
                 const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
                 if (lx >= tw || ly >= th) continue;
@@ -725,11 +766,13 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                 uint32_t q;
                                 bool cc, ca;
                                 const bool msk = cover(sp, i, j, rk.r_min, zn, inv_range, cc, ca, q);
-                                if (msk) {
+                                const uint32_t x =
+                                    (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
+                                if (DOM) {
+                                    if (ca) dom_count(cnt, q0t, x, TT, q, dk);
+                                } else if (msk) {
                                     const unsigned long long key =
                                         ((unsigned long long)q << HM_ID_BITS) | r_sid[ow];
-                                    const uint32_t x =
-                                        (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
                                     if (cc) atomicMin((unsigned long long *)&lc[x], key);
                                     if (ca) atomicMin((unsigned long long *)&la[x], key);
                                 }
@@ -773,9 +816,13 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                         uint32_t q;
                         bool cc, ca;
                         const bool msk = cover(sr, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                        const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
+                        if (DOM) {
+                            if (ca) dom_count(cnt, q0t, x, TT, q, dk);
+                            continue;
+                        }
                         if (!msk) continue;
                         const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | vo;
-                        const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
                         if (cc) atomicMin((unsigned long long *)&lc[x], key);
                         if (ca) atomicMin((unsigned long long *)&la[x], key);
                     }
@@ -787,6 +834,14 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
             if (lx >= tw || ly >= th) continue;
             const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
+            if (DOM) {
+                for (uint32_t k = 0; k < dk.n_layers; ++k) {
+                    const uint32_t c = cnt[k * TT + x];
+                    if (whole) dk.counts[(size_t)k * hw + p] = c;
+                    else if (c) atomicAdd(dk.counts + (size_t)k * hw + p, c);
+                }
+                continue;
+            }
             const uint64_t kc = lc[x], ka = la[x];
             if (whole) {
                 vc[p] = kc;
@@ -800,12 +855,15 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
     }
 }
 
-// One wave per long segment: lanes stride over its candidate rows.
+// One wave per long segment: lanes stride over its candidate rows (DOM: the
+// counting pass, one global add per accepted conservative pair).
+template <bool DOM>
 __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const uint8_t *flags,
                                                      const uint32_t *scene_off,
                                                      const hm_camera *cams, RasterK rk,
                                                      uint32_t cap, const uint32_t *long_list,
-                                                     const uint32_t *counters, uint64_t *vis)
+                                                     const uint32_t *counters, uint64_t *vis,
+                                                     DomK dk)
 {
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_long = counters[0];
@@ -833,9 +891,17 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
                 uint32_t q;
                 bool cc, ca;
                 const bool msk = cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                const size_t p = (size_t)j * rk.W + i;
+                if (DOM) {
+                    if (!ca) continue;
+                    const uint32_t q0 = (uint32_t)(va[p] >> HM_ID_BITS);
+                    uint32_t k = q > q0 ? (q - q0) / dk.layer_codes : 0u;
+                    k = k < dk.n_layers - 1u ? k : dk.n_layers - 1u;
+                    atomicAdd(dk.counts + (size_t)k * hw + p, 1u);
+                    continue;
+                }
                 if (!msk) continue;
                 const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
-                const size_t p = (size_t)j * rk.W + i;
                 if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
                 if (ca) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
             }
@@ -844,46 +910,13 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
 }
 
 // ------------------------------------------------------------------ deep opacity map
-// Fragment counts per light-map layer: one thread per segment of the light
-// view's screen records, candidate pixels by row spans, the conservative test
-// of the raster, then a 32-bit global add into layer
-// min((q - q0) / layer_codes, n_layers - 1), q0 the nearest fragment of the
-// pixel (the light view's conservative layer).
-__global__ __launch_bounds__(256) void k_dom_accum(const float4 *proj, const uint8_t *flags,
-                                                   const uint32_t *scene_off, RasterK rk,
-                                                   uint32_t cap, const hm_camera *light,
-                                                   const uint64_t *light_vis,
-                                                   uint32_t layer_codes, uint32_t n_layers,
-                                                   uint32_t *counts)
+// Zero the counts and rewind the work-item counter for the counting pass (the
+// long-segment count of the binning, counters[0], is kept).
+__global__ __launch_bounds__(256) void k_dom_clear(uint32_t *counts, uint32_t n, uint32_t *counters)
 {
-    const uint32_t n = stream_len(scene_off, rk, cap);
-    const size_t hw = (size_t)rk.W * rk.H;
-    const uint64_t *va = light_vis + hw;
-    float zn, inv_range;
-    scene_depth_consts(light, 0, zn, inv_range);
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
-        Seg sg;
-        if (!load_seg(proj, flags, v, v, n, rk.r_min, sg)) continue;
-        int i0, i1, j0, j1;
-        if (!seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) continue;
-        for (int j = j0; j <= j1; ++j) {
-            int a0, a1;
-            row_span(sg, j, a0, a1);
-            a0 = max(a0, i0);
-            a1 = min(a1, i1);
-            for (int i = a0; i <= a1; ++i) {
-                uint32_t q;
-                bool cc, ca;
-                cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
-                if (!ca) continue;
-                const size_t p = (size_t)j * rk.W + i;
-                const uint32_t q0 = (uint32_t)(va[p] >> HM_ID_BITS);
-                uint32_t k = q > q0 ? (q - q0) / layer_codes : 0u;
-                k = k < n_layers - 1u ? k : n_layers - 1u;
-                atomicAdd(counts + (size_t)k * hw + p, 1u);
-            }
-        }
-    }
+    const uint32_t i0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i0 == 0) counters[1] = 0u;
+    for (uint32_t i = i0; i < n; i += gridDim.x * blockDim.x) counts[i] = 0u;
 }
 
 // ------------------------------------------------------------------ host side
@@ -1015,10 +1048,10 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
 #define HM_TILES_LAUNCH(FL, NB)                                                                \
-    hipLaunchKernelGGL((k_raster_tiles<FL, NB>), dim3(grid), dim3(p.block), lds, st,             \
+    hipLaunchKernelGGL((k_raster_tiles<FL, NB, false>), dim3(grid), dim3(p.block), lds, st,      \
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,  \
                        s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,          \
-                       (const uint32_t *)w.entries, w.counters, vis)
+                       (const uint32_t *)w.entries, w.counters, vis, DomK{nullptr, 1u, 1u})
     if (p.algo == HM_RASTER_TILED) {
         if (p.block == 256) HM_TILES_LAUNCH(true, 256);
         else if (p.block == 128) HM_TILES_LAUNCH(true, 128);
@@ -1029,38 +1062,66 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         else HM_TILES_LAUNCH(false, 0);
     }
 #undef HM_TILES_LAUNCH
-    hipLaunchKernelGGL(k_raster_long, dim3(256), dim3(256), 0, st, (const float4 *)w.proj,
-                       (const uint8_t *)s.flags, s.scene_off, cams, rk, s.cap,
-                       (const uint32_t *)w.long_list, (const uint32_t *)w.counters, vis);
+    hipLaunchKernelGGL(k_raster_long<false>, dim3(256), dim3(256), 0, st,
+                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,
+                       s.cap, (const uint32_t *)w.long_list, (const uint32_t *)w.counters, vis,
+                       DomK{nullptr, 1u, 1u});
 }
 
 }  // namespace hm
 
 namespace hm {
 
-size_t dom_workspace(uint32_t cap) { return align_up(sizeof(float4) * (size_t)cap); }
+static hm_raster_params dom_raster_params(const hm_frame &lf, const hm_dom_params &p)
+{
+    hm_raster_params rp;
+    raster_defaults(lf, rp);
+    rp.r_min = p.r_min;
+    return rp;
+}
 
-void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_params &p,
-                      const uint64_t *light_vis, uint32_t *counts, void *ws, hipStream_t st)
+static hm_frame dom_frame(const hm_dom_params &p)
 {
     hm_frame f;
     f.n_scenes = 1;
     f.width = p.width;
     f.height = p.height;
+    return f;
+}
+
+size_t dom_workspace(const hm_frame &lf, uint32_t cap)
+{
     hm_raster_params rp;
-    raster_defaults(f, rp);
-    rp.r_min = p.r_min;
+    raster_defaults(lf, rp);
+    return raster_workspace(lf, cap, rp);
+}
+
+// The light view is rasterized by the raster path (its bins stay in the
+// workspace), then the same work items are walked again by the counting pass
+// of the tile kernel, with the completed conservative layer as q0.
+void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_params &p,
+                      uint64_t *light_vis, uint32_t *counts, void *ws, hipStream_t st)
+{
+    const hm_frame f = dom_frame(p);
+    const hm_raster_params rp = dom_raster_params(f, p);
+    launch_raster(s, light, f, rp, nullptr, light_vis, ws, st);
     const RasterK rk = make_rk(f, rp);
-    float4 *proj = (float4 *)ws;
-    const size_t hw = (size_t)p.width * p.height;
-    hipLaunchKernelGGL(k_fill_u32, dim3(stride_grid(hw * p.n_layers, 256)), dim3(256), 0, st,
-                       counts, (uint32_t)(hw * p.n_layers), 0u);
-    hipLaunchKernelGGL(k_project, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st,
-                       reinterpret_cast<const float4 *>(s.pos_w), s.scene_off, rk, light, s.cap,
-                       proj);
-    hipLaunchKernelGGL(k_dom_accum, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st,
-                       (const float4 *)proj, (const uint8_t *)s.flags, s.scene_off, rk, s.cap,
-                       light, light_vis, p.layer_codes, p.n_layers, counts);
+    RasterWs w = carve(ws, f, s.cap, rp);
+    const size_t n = (size_t)p.width * p.height * p.n_layers;
+    hipLaunchKernelGGL(k_dom_clear, dim3(stride_grid(n, 256)), dim3(256), 0, st, counts,
+                       (uint32_t)n, w.counters);
+    const DomK dk{counts, p.layer_codes, p.n_layers};
+    const uint32_t TT = rp.tile * rp.tile;
+    const uint32_t lds = tile_lds_bytes(rp.tile, rp.block, true) - 4u * TT * 4u +
+                         tile_words(TT, true, p.n_layers) * 4u;
+    hipLaunchKernelGGL((k_raster_tiles<true, 256, true>), dim3(256u * 8u), dim3(256), lds, st,
+                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light, rk,
+                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
+                       (const uint32_t *)w.entries, w.counters, light_vis, dk);
+    hipLaunchKernelGGL(k_raster_long<true>, dim3(256), dim3(256), 0, st, (const float4 *)w.proj,
+                       (const uint8_t *)s.flags, s.scene_off, light, rk, s.cap,
+                       (const uint32_t *)w.long_list, (const uint32_t *)w.counters, light_vis,
+                       dk);
 }
 
 }  // namespace hm

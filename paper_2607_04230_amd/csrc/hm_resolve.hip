@@ -657,7 +657,7 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const float4 *pos, const float
 // q' = q0 + (uint32)((float)(q - q0) * beta) is a binary32 product; the
 // opacity in front of q' sums whole layers and the interpolated part of the
 // layer holding q' (the last layer taken whole once passed).
-struct DomK {
+struct DomQ {
     uint32_t W, H, LW, LH;
     uint32_t layer_codes, n_layers, n_bundles;
     double alpha;
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(256) void k_dom_shadow(const float4 *pos, const uin
                                                     const hm_camera *cam, const hm_camera *light,
                                                     const uint64_t *light_vis,
                                                     const uint32_t *counts, const uint32_t *table,
-                                                    const uint32_t *nstr, DomK d, float *shadow)
+                                                    const uint32_t *nstr, DomQ d, float *shadow)
 {
     const size_t hw = (size_t)d.W * d.H, lhw = (size_t)d.LW * d.LH;
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < hw;
@@ -752,7 +752,7 @@ void launch_dom_shadow(const hm_strands &s, const uint64_t *vis, const hm_camera
                        const uint64_t *light_vis, const uint32_t *counts, const uint32_t *table,
                        const uint32_t *nstr, uint32_t n_bundles, float *shadow, hipStream_t st)
 {
-    DomK d;
+    DomQ d;
     d.W = f.width; d.H = f.height; d.LW = p.width; d.LH = p.height;
     d.layer_codes = p.layer_codes; d.n_layers = p.n_layers; d.n_bundles = n_bundles;
     d.alpha = p.alpha;

@@ -113,13 +113,8 @@ class DeviceScene:
         dev = "cuda"
         if getattr(self, "_dom", None) is None or self._dom[0] != shp:
             lfr = hm.frame(1, shp.width, shp.height)
-            lrp = hm.raster_defaults(lfr)
-            lrp.r_min = shp.r_min
-            self._dom = (shp, _f32(light_camera(self.sc, shp, self.resolve_params)), lfr, lrp,
+            self._dom = (shp, _f32(light_camera(self.sc, shp, self.resolve_params)),
                          torch.empty((1, 2, shp.height, shp.width), dtype=torch.int64, device=dev),
-                         torch.zeros(hm.workspace_size(hm.CALL_RASTER, lfr, cap=self.cap,
-                                                       rparams=lrp),
-                                     dtype=torch.uint8, device=dev),
                          hm.DomParams(shp.width, shp.height, shp.n_layers, shp.layer_codes(),
                                       shp.r_min, shp.alpha),
                          torch.empty((shp.n_layers, shp.height, shp.width), dtype=torch.int32,
@@ -127,8 +122,7 @@ class DeviceScene:
                          torch.zeros(hm.workspace_size(hm.CALL_DOM, lfr, cap=self.cap),
                                      dtype=torch.uint8, device=dev),
                          torch.ones((self.H, self.W), dtype=torch.float32, device=dev))
-        _, light, lfr, lrp, lvis, lws, dp, counts, dws, shadow = self._dom
-        hm.raster_vis(self.st, light, lfr, lrp, None, lvis, lws)
+        _, light, lvis, dp, counts, dws, shadow = self._dom
         hm.dom_accumulate(self.st, light, dp, lvis, counts, dws)
         hm.dom_shadow(self.st, self.vis, self.cams, self.fr, light, dp, lvis, counts, self.table,
                       self.mesh_t["bundle_nstrands"], shadow)
