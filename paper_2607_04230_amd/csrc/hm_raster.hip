@@ -998,7 +998,7 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.algo = HM_RASTER_TILED;
     p.tile = 32;
     p.chunk = 512;
-    p.max_tiles_per_seg = 8;
+    p.max_tiles_per_seg = 16;
     p.block = 256;
     p.grid = 0;
     p.shared_views = 0;
