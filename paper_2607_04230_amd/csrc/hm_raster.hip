@@ -19,6 +19,8 @@
 // as the reference launch shape.  Every path evaluates the same binary32
 // predicates per pixel, and min is order-independent, so the buffer is
 // bit-identical across paths and tuning parameters.
+#include <algorithm>
+
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
 #include "hm_scan.hpp"
@@ -305,8 +307,12 @@ constexpr uint32_t BIN_SLOTS = 1024;      // LDS hash slots per workgroup
 #ifndef HM_BIN_BLOCK
 #define HM_BIN_BLOCK 256
 #endif
-constexpr uint32_t BIN_SUB = HM_BIN_SUB;      // segments per thread between table flushes
+#ifndef HM_BIN_WGS
+#define HM_BIN_WGS 1024
+#endif
+constexpr uint32_t BIN_SUB = HM_BIN_SUB;      // most segments per thread between table flushes
 constexpr uint32_t BIN_BLOCK = HM_BIN_BLOCK;  // threads per binning workgroup
+constexpr uint32_t BIN_WGS = HM_BIN_WGS;      // workgroups the segments are spread over (at least)
 constexpr uint32_t BIN_FREE = 0xFFFFFFFFu;
 
 // Slot of `tile` in the workgroup's LDS table (linear probing), -1 if full.
@@ -321,7 +327,7 @@ __device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
     return -1;
 }
 
-// Per-tile segment lists.  Each workgroup takes BIN_SUB * blockDim consecutive
+// Per-tile segment lists.  Each workgroup takes nsub * blockDim consecutive
 // segments (consecutive segments belong to the same few strands, so they fall
 // in a few tiles) and aggregates its (segment, tile) pairs per tile in an LDS table:
 //   pass 0: counts per tile, flushed with one non-returning global add per
@@ -335,12 +341,12 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                                                    uint32_t cap, uint32_t *tile_cnt,
                                                    const uint32_t *tile_off, uint32_t *tile_cur,
                                                    uint32_t *entries, uint32_t *long_list,
-                                                   uint32_t *counters)
+                                                   uint32_t *counters, uint32_t nsub)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
-    const uint32_t span = BIN_BLOCK * BIN_SUB;     // segments per table flush
+    const uint32_t span = BIN_BLOCK * nsub;        // segments per table flush
     // v below is a segment unit (see unit_map); lists store units
     for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
         for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
             cnt[x] = 0;
         }
         __syncthreads();
-        for (uint32_t sub = 0; sub < BIN_SUB; ++sub) {
+        for (uint32_t sub = 0; sub < nsub; ++sub) {
             const uint32_t v = base + sub * blockDim.x + threadIdx.x;
             SegTiles st;
             bool ok = pass == 0
@@ -382,7 +388,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
         }
         __syncthreads();
         if (pass == 1) {
-            for (uint32_t sub = 0; sub < BIN_SUB; ++sub) {
+            for (uint32_t sub = 0; sub < nsub; ++sub) {
                 const uint32_t v = base + sub * blockDim.x + threadIdx.x;
                 SegTiles st;
                 if (!seg_tiles<false>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st) ||
@@ -1027,10 +1033,20 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     }
     // pass 0 of the binning also writes every unit's screen record
     const uint32_t nt = rk.n_tiles;
-    const uint32_t gb = stride_grid((units + BIN_SUB - 1) / BIN_SUB, BIN_BLOCK);
+    // segments per thread between flushes: up to BIN_SUB, fewer when that
+    // would leave fewer than BIN_WGS workgroups.  Measured: a 9 k-segment
+    // frame bins in 9 us with one segment per thread against 34 us with 8
+    // (5 workgroups); more workgroups than ~1024 cost more in contended
+    // per-tile global adds than they gain (2 M segments: 58 us at 1024 or
+    // fewer, 62 us at 2048, 78 us at 4096)
+    const size_t per_sub = (size_t)BIN_BLOCK * BIN_WGS;
+    const uint32_t nsub =
+        (uint32_t)std::min<size_t>(std::max<size_t>(units / per_sub, 1), BIN_SUB);
+    const uint32_t gb = stride_grid((units + nsub - 1) / nsub, BIN_BLOCK);
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
-                       (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters);
+                       (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters,
+                       nsub);
     const bool small = nt <= PLAN_SMALL;
     if (small) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), 0, st, w.tile_cnt, nt, rk.chunk,
@@ -1043,7 +1059,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
-                       w.counters);
+                       w.counters, nsub);
     if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;

@@ -500,151 +500,222 @@ __device__ __forceinline__ void atomic_add3(float *base, D3 g)
     atomicAdd(base + 2, (float)g.z);
 }
 
+// Gradient contributions of one pixel of the soft resolve (binary64), or
+// false when the pixel has no visible segment or a zero output gradient.
+struct SoftGrad {
+    uint32_t v;
+    bool root, tip;
+    D3 gP0, gP1, gPm, gPp;        // positions of v, v + 1, v - 1, v + 2
+    double g_ww0, g_ww1;          // widths of v, v + 1
+    D3 gc0, gc1;                  // colours of v, v + 1
+};
+
+__device__ __forceinline__ bool soft_bwd_pixel(const float4 *pos, const float4 *rgb,
+                                               const uint8_t *flags, const uint64_t *vis,
+                                               const DCam &c, uint32_t s, uint32_t W,
+                                               size_t hw, uint32_t i, uint32_t j, const ShadeK &k,
+                                               const float4 *dout, SoftGrad &o)
+{
+    const double kk = k.soft_k, isp = 0.5641895835477563;   // 1/sqrt(pi)
+    const size_t loc = (size_t)j * W + i;
+    const size_t p = (size_t)s * hw + loc;
+    const uint64_t src = soft_source(vis[(size_t)s * 2 * hw + loc],
+                                     vis[(size_t)s * 2 * hw + hw + loc]);
+    if (src == HM_EMPTY) return false;
+    const float4 go = dout[p];
+    if (go.x == 0.0f && go.y == 0.0f && go.z == 0.0f && go.w == 0.0f) return false;
+    const uint32_t v = (uint32_t)(src & HM_ID_MASK);
+    const uint8_t f0 = flags[v], f1 = flags[v + 1];
+    const bool root = f0 & HM_ROOT, tip = f1 & HM_TIP;
+    const float4 Q0 = pos[v], Q1 = pos[v + 1];
+    const D3 P0 = dl(Q0), P1 = dl(Q1);
+    const D3 Pm = root ? P0 : dl(pos[v - 1]);
+    const D3 Pp = tip ? P1 : dl(pos[v + 2]);
+    const double px = (double)i + 0.5, py = (double)j + 0.5;
+
+    // ---- forward (binary64)
+    const DPt a = proj_pt(c, P0), b = proj_pt(c, P1);
+    const double w0 = (double)Q0.w * c.fy * a.iz, w1 = (double)Q1.w * c.fy * b.iz;
+    const double dx = b.x - a.x, dy = b.y - a.y, len2 = dx * dx + dy * dy;
+    const double ux = px - a.x, uy = py - a.y;
+    double traw = len2 > 0.0 ? (ux * dx + uy * dy) / len2 : 0.0;
+    const bool interior = len2 > 0.0 && traw > 0.0 && traw < 1.0;
+    const double ts = traw < 0.0 ? 0.0 : (traw > 1.0 ? 1.0 : traw);
+    const double ex = ux - ts * dx, ey = uy - ts * dy;
+    const double d = sqrt(ex * ex + ey * ey);
+    const double wt = w0 + ts * (w1 - w0);
+    const double za = (d + 0.5 * wt) * kk, zb = (d - 0.5 * wt) * kk;
+    const double alpha = 0.5 * (erf(za) - erf(zb));
+    const double ga2 = exp(-za * za), gb2 = exp(-zb * zb);
+    const double iz = a.iz + ts * (b.iz - a.iz);
+    const double t3 = ts * b.iz / iz;
+    const D3 X = P0 + (P1 - P0) * t3;
+    const D3 D0 = root ? (P1 - P0) : (P1 - Pm);
+    const D3 D1 = tip ? (P1 - P0) : (Pp - P0);
+    const double n0 = lend(D0), n1 = lend(D1);
+    const D3 T0 = n0 > 0 ? D0 * (1.0 / n0) : d3(0, 0, 0);
+    const D3 T1 = n1 > 0 ? D1 * (1.0 / n1) : d3(0, 0, 0);
+    const D3 Tm = T0 + (T1 - T0) * t3;
+    const double nm = lend(Tm);
+    const D3 T = nm > 0 ? Tm * (1.0 / nm) : d3(0, 0, 0);
+    const D3 c0 = dl(rgb[v]), c1 = dl(rgb[v + 1]);
+    const D3 alb = c0 + (c1 - c0) * t3;
+    const D3 EV = d3(c.e[0], c.e[1], c.e[2]) - X;
+    const double nv = lend(EV);
+    const D3 V = EV * (1.0 / nv);
+    const D3 L = d3(k.Lx, k.Ly, k.Lz);
+    const D3 LV = L + V;
+    const double nh = lend(LV);
+    const D3 Hh = LV * (1.0 / nh);
+    const double tl = dotd(T, L), th = dotd(T, Hh);
+    const double sd = 1.0 - tl * tl;
+    const double diff = sd > 0.0 ? sqrt(sd) : 0.0;
+    const double sh0 = 1.0 - th * th;
+    const double sh = sh0 > 0.0 ? sh0 : 0.0;
+    double q = sh, shp = 1.0;                    // shp = sh^(2^n - 1)
+    for (int it = 0; it < k.nsq; ++it) { shp *= q; q = q * q; }
+    const double spec = q;
+    const double E[3] = {k.Er, k.Eg, k.Eb}, bgc[3] = {k.bgr, k.bgg, k.bgb};
+    const double albv[3] = {alb.x, alb.y, alb.z};
+    const double gI[3] = {go.x, go.y, go.z};
+    double Sv[3];
+    const double dd = k.ka + k.kd * diff;
+    for (int ch = 0; ch < 3; ++ch) Sv[ch] = albv[ch] * E[ch] * dd + k.ks * E[ch] * spec;
+
+    // ---- backward
+    double g_alpha = go.w;
+    double galb[3], g_diff = 0.0, g_spec = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+        g_alpha += gI[ch] * (Sv[ch] - bgc[ch]);
+        const double gS = gI[ch] * alpha;
+        galb[ch] = gS * E[ch] * dd;
+        g_diff += gS * albv[ch] * E[ch] * k.kd;
+        g_spec += gS * k.ks * E[ch];
+    }
+    const double g_sh = sh0 > 0.0 ? g_spec * (double)(1 << k.nsq) * shp : 0.0;
+    const double g_th = -2.0 * th * g_sh;
+    const double g_tl = sd > 0.0 ? -tl / diff * g_diff : 0.0;
+    const D3 gT = L * g_tl + Hh * g_th;
+    const D3 gH = T * g_th;
+    const D3 gV = nrm_back(Hh, nh, gH);
+    const D3 gX = nrm_back(V, nv, gV) * -1.0;
+    const D3 gAlb = d3(galb[0], galb[1], galb[2]);
+    double g_t3 = dotd(gAlb, c1 - c0);
+    const D3 gc0 = gAlb * (1.0 - t3), gc1 = gAlb * t3;
+    const D3 gTm = nrm_back(T, nm, gT);
+    g_t3 += dotd(gTm, T1 - T0);
+    const D3 gT0 = gTm * (1.0 - t3), gT1 = gTm * t3;
+    const D3 gD0 = nrm_back(T0, n0, gT0), gD1 = nrm_back(T1, n1, gT1);
+    D3 gP0 = gX * (1.0 - t3), gP1 = gX * t3, gPm = d3(0, 0, 0), gPp = d3(0, 0, 0);
+    g_t3 += dotd(gX, P1 - P0);
+    if (root) { gP1 = gP1 + gD0; gP0 = gP0 - gD0; } else { gP1 = gP1 + gD0; gPm = gPm - gD0; }
+    if (tip) { gP1 = gP1 + gD1; gP0 = gP0 - gD1; } else { gPp = gPp + gD1; gP0 = gP0 - gD1; }
+    // t3 = ts iz1 / iz(ts)
+    const double iz2 = iz * iz;
+    double g_ts = g_t3 * a.iz * b.iz / iz2;
+    double g_iz0 = -g_t3 * ts * b.iz * (1.0 - ts) / iz2;
+    double g_iz1 = g_t3 * ts * a.iz * (1.0 - ts) / iz2;
+    // alpha(d, wt)
+    const double g_d = g_alpha * kk * isp * (ga2 - gb2);
+    const double g_wt = g_alpha * 0.5 * kk * isp * (ga2 + gb2);
+    double g_w0 = g_wt * (1.0 - ts), g_w1 = g_wt * ts;
+    g_ts += g_wt * (w1 - w0);
+    double g_x0 = 0, g_y0 = 0, g_x1 = 0, g_y1 = 0;
+    if (d > 0.0) {
+        const double gex = g_d * ex / d, gey = g_d * ey / d;
+        g_x0 += gex * (ts - 1.0); g_x1 += -gex * ts;
+        g_y0 += gey * (ts - 1.0); g_y1 += -gey * ts;
+        g_ts += -(gex * dx + gey * dy);
+    }
+    if (interior) {
+        const double il = 1.0 / len2;
+        g_x0 += g_ts * (-dx - ux + 2.0 * traw * dx) * il;
+        g_x1 += g_ts * (ux - 2.0 * traw * dx) * il;
+        g_y0 += g_ts * (-dy - uy + 2.0 * traw * dy) * il;
+        g_y1 += g_ts * (uy - 2.0 * traw * dy) * il;
+    }
+    // pixel widths w = width fy / z
+    g_iz0 += g_w0 * (double)Q0.w * c.fy;
+    g_iz1 += g_w1 * (double)Q1.w * c.fy;
+    const double g_ww0 = g_w0 * c.fy * a.iz, g_ww1 = g_w1 * c.fy * b.iz;
+    gP0 = gP0 + proj_back(c, a, g_x0, g_y0, g_iz0);
+    gP1 = gP1 + proj_back(c, b, g_x1, g_y1, g_iz1);
+
+    o.v = v;
+    o.root = root;
+    o.tip = tip;
+    o.gP0 = gP0; o.gP1 = gP1; o.gPm = gPm; o.gPp = gPp;
+    o.g_ww0 = g_ww0; o.g_ww1 = g_ww1;
+    o.gc0 = gc0; o.gc1 = gc1;
+    return true;
+}
+
+// Per-workgroup gradient table: control point -> {d pos xyz, d width, d rgb},
+// LDS adds, flushed with one global add per nonzero component and point.
+constexpr uint32_t BWD_SLOTS = 1024;      // >= 4 points x 256 pixels: never full
+constexpr uint32_t BWD_FREE = 0xFFFFFFFFu;
+
+__device__ __forceinline__ void bwd_add(uint32_t *keys, float *vals, uint32_t cp, D3 gp,
+                                        double gw, D3 gc)
+{
+    uint32_t sl = (cp * 2654435761u) >> 22;
+    for (;;) {
+        const uint32_t prev = atomicCAS(&keys[sl], BWD_FREE, cp);
+        if (prev == BWD_FREE || prev == cp) break;
+        sl = (sl + 1u) & (BWD_SLOTS - 1u);
+    }
+    float *o = vals + sl * 8u;
+    const float g[7] = {(float)gp.x, (float)gp.y, (float)gp.z, (float)gw,
+                        (float)gc.x, (float)gc.y, (float)gc.z};
+#pragma unroll
+    for (int q = 0; q < 7; ++q)
+        if (g[q] != 0.0f) atomicAdd(o + q, g[q]);
+}
+
+// One 16 x 16 pixel tile per workgroup iteration: every pixel's contributions
+// to the control points v - 1 .. v + 2 are summed in LDS (neighbouring pixels
+// mostly share segments), then added to the global gradients.
 __global__ __launch_bounds__(256) void k_soft_bwd(const float4 *pos, const float4 *rgb,
                                                   const uint8_t *flags, const uint64_t *vis,
                                                   const hm_camera *cams, uint32_t S, uint32_t W,
                                                   uint32_t H, ShadeK k, const float4 *dout,
                                                   float *gpos, float *grgb)
 {
+    __shared__ uint32_t keys[BWD_SLOTS];
+    __shared__ float vals[BWD_SLOTS * 8];
     const size_t hw = (size_t)W * H;
-    const size_t n = hw * S;
-    const double kk = k.soft_k, isp = 0.5641895835477563;   // 1/sqrt(pi)
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
-         p += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t s = (uint32_t)(p / hw);
-        const size_t loc = p - (size_t)s * hw;
-        const uint64_t src = soft_source(vis[(size_t)s * 2 * hw + loc],
-                                         vis[(size_t)s * 2 * hw + hw + loc]);
-        if (src == HM_EMPTY) continue;
-        const float4 go = dout[p];
-        if (go.x == 0.0f && go.y == 0.0f && go.z == 0.0f && go.w == 0.0f) continue;
-        const DCam c = load_dcam(cams + s);
-        const uint32_t v = (uint32_t)(src & HM_ID_MASK);
-        const uint8_t f0 = flags[v], f1 = flags[v + 1];
-        const bool root = f0 & HM_ROOT, tip = f1 & HM_TIP;
-        const float4 Q0 = pos[v], Q1 = pos[v + 1];
-        const D3 P0 = dl(Q0), P1 = dl(Q1);
-        const D3 Pm = root ? P0 : dl(pos[v - 1]);
-        const D3 Pp = tip ? P1 : dl(pos[v + 2]);
-        const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
-        const double px = (double)i + 0.5, py = (double)j + 0.5;
-
-        // ---- forward (binary64)
-        const DPt a = proj_pt(c, P0), b = proj_pt(c, P1);
-        const double w0 = (double)Q0.w * c.fy * a.iz, w1 = (double)Q1.w * c.fy * b.iz;
-        const double dx = b.x - a.x, dy = b.y - a.y, len2 = dx * dx + dy * dy;
-        const double ux = px - a.x, uy = py - a.y;
-        double traw = len2 > 0.0 ? (ux * dx + uy * dy) / len2 : 0.0;
-        const bool interior = len2 > 0.0 && traw > 0.0 && traw < 1.0;
-        const double ts = traw < 0.0 ? 0.0 : (traw > 1.0 ? 1.0 : traw);
-        const double ex = ux - ts * dx, ey = uy - ts * dy;
-        const double d = sqrt(ex * ex + ey * ey);
-        const double wt = w0 + ts * (w1 - w0);
-        const double za = (d + 0.5 * wt) * kk, zb = (d - 0.5 * wt) * kk;
-        const double alpha = 0.5 * (erf(za) - erf(zb));
-        const double ga2 = exp(-za * za), gb2 = exp(-zb * zb);
-        const double iz = a.iz + ts * (b.iz - a.iz);
-        const double t3 = ts * b.iz / iz;
-        const D3 X = P0 + (P1 - P0) * t3;
-        const D3 D0 = root ? (P1 - P0) : (P1 - Pm);
-        const D3 D1 = tip ? (P1 - P0) : (Pp - P0);
-        const double n0 = lend(D0), n1 = lend(D1);
-        const D3 T0 = n0 > 0 ? D0 * (1.0 / n0) : d3(0, 0, 0);
-        const D3 T1 = n1 > 0 ? D1 * (1.0 / n1) : d3(0, 0, 0);
-        const D3 Tm = T0 + (T1 - T0) * t3;
-        const double nm = lend(Tm);
-        const D3 T = nm > 0 ? Tm * (1.0 / nm) : d3(0, 0, 0);
-        const D3 c0 = dl(rgb[v]), c1 = dl(rgb[v + 1]);
-        const D3 alb = c0 + (c1 - c0) * t3;
-        const D3 EV = d3(c.e[0], c.e[1], c.e[2]) - X;
-        const double nv = lend(EV);
-        const D3 V = EV * (1.0 / nv);
-        const D3 L = d3(k.Lx, k.Ly, k.Lz);
-        const D3 LV = L + V;
-        const double nh = lend(LV);
-        const D3 Hh = LV * (1.0 / nh);
-        const double tl = dotd(T, L), th = dotd(T, Hh);
-        const double sd = 1.0 - tl * tl;
-        const double diff = sd > 0.0 ? sqrt(sd) : 0.0;
-        const double sh0 = 1.0 - th * th;
-        const double sh = sh0 > 0.0 ? sh0 : 0.0;
-        double q = sh, shp = 1.0;                    // shp = sh^(2^n - 1)
-        for (int it = 0; it < k.nsq; ++it) { shp *= q; q = q * q; }
-        const double spec = q;
-        const double E[3] = {k.Er, k.Eg, k.Eb}, bgc[3] = {k.bgr, k.bgg, k.bgb};
-        const double albv[3] = {alb.x, alb.y, alb.z};
-        const double gI[3] = {go.x, go.y, go.z};
-        double Sv[3];
-        const double dd = k.ka + k.kd * diff;
-        for (int ch = 0; ch < 3; ++ch) Sv[ch] = albv[ch] * E[ch] * dd + k.ks * E[ch] * spec;
-
-        // ---- backward
-        double g_alpha = go.w;
-        double galb[3], g_diff = 0.0, g_spec = 0.0;
-        for (int ch = 0; ch < 3; ++ch) {
-            g_alpha += gI[ch] * (Sv[ch] - bgc[ch]);
-            const double gS = gI[ch] * alpha;
-            galb[ch] = gS * E[ch] * dd;
-            g_diff += gS * albv[ch] * E[ch] * k.kd;
-            g_spec += gS * k.ks * E[ch];
+    const uint32_t ntx = (W + 15u) / 16u, nty = (H + 15u) / 16u;
+    const uint32_t per = ntx * nty, ntiles = per * S;
+    const uint32_t tid = threadIdx.x;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        for (uint32_t x = tid; x < BWD_SLOTS; x += blockDim.x) keys[x] = BWD_FREE;
+        for (uint32_t x = tid; x < BWD_SLOTS * 8u; x += blockDim.x) vals[x] = 0.0f;
+        __syncthreads();
+        const uint32_t s = t / per, r = t - s * per;
+        const uint32_t ty = r / ntx, tx = r - ty * ntx;
+        const uint32_t i = tx * 16u + (tid & 15u), j = ty * 16u + (tid >> 4);
+        SoftGrad g;
+        if (i < W && j < H &&
+            soft_bwd_pixel(pos, rgb, flags, vis, load_dcam(cams + s), s, W, hw, i, j, k, dout,
+                           g)) {
+            bwd_add(keys, vals, g.v, g.gP0, g.g_ww0, g.gc0);
+            bwd_add(keys, vals, g.v + 1u, g.gP1, g.g_ww1, g.gc1);
+            if (!g.root) bwd_add(keys, vals, g.v - 1u, g.gPm, 0.0, d3(0, 0, 0));
+            if (!g.tip) bwd_add(keys, vals, g.v + 2u, g.gPp, 0.0, d3(0, 0, 0));
         }
-        const double g_sh = sh0 > 0.0 ? g_spec * (double)(1 << k.nsq) * shp : 0.0;
-        const double g_th = -2.0 * th * g_sh;
-        const double g_tl = sd > 0.0 ? -tl / diff * g_diff : 0.0;
-        const D3 gT = L * g_tl + Hh * g_th;
-        const D3 gH = T * g_th;
-        const D3 gV = nrm_back(Hh, nh, gH);
-        const D3 gX = nrm_back(V, nv, gV) * -1.0;
-        const D3 gAlb = d3(galb[0], galb[1], galb[2]);
-        double g_t3 = dotd(gAlb, c1 - c0);
-        const D3 gc0 = gAlb * (1.0 - t3), gc1 = gAlb * t3;
-        const D3 gTm = nrm_back(T, nm, gT);
-        g_t3 += dotd(gTm, T1 - T0);
-        const D3 gT0 = gTm * (1.0 - t3), gT1 = gTm * t3;
-        const D3 gD0 = nrm_back(T0, n0, gT0), gD1 = nrm_back(T1, n1, gT1);
-        D3 gP0 = gX * (1.0 - t3), gP1 = gX * t3, gPm = d3(0, 0, 0), gPp = d3(0, 0, 0);
-        g_t3 += dotd(gX, P1 - P0);
-        if (root) { gP1 = gP1 + gD0; gP0 = gP0 - gD0; } else { gP1 = gP1 + gD0; gPm = gPm - gD0; }
-        if (tip) { gP1 = gP1 + gD1; gP0 = gP0 - gD1; } else { gPp = gPp + gD1; gP0 = gP0 - gD1; }
-        // t3 = ts iz1 / iz(ts)
-        const double iz2 = iz * iz;
-        double g_ts = g_t3 * a.iz * b.iz / iz2;
-        double g_iz0 = -g_t3 * ts * b.iz * (1.0 - ts) / iz2;
-        double g_iz1 = g_t3 * ts * a.iz * (1.0 - ts) / iz2;
-        // alpha(d, wt)
-        const double g_d = g_alpha * kk * isp * (ga2 - gb2);
-        const double g_wt = g_alpha * 0.5 * kk * isp * (ga2 + gb2);
-        double g_w0 = g_wt * (1.0 - ts), g_w1 = g_wt * ts;
-        g_ts += g_wt * (w1 - w0);
-        double g_x0 = 0, g_y0 = 0, g_x1 = 0, g_y1 = 0;
-        if (d > 0.0) {
-            const double gex = g_d * ex / d, gey = g_d * ey / d;
-            g_x0 += gex * (ts - 1.0); g_x1 += -gex * ts;
-            g_y0 += gey * (ts - 1.0); g_y1 += -gey * ts;
-            g_ts += -(gex * dx + gey * dy);
+        __syncthreads();
+        for (uint32_t x = tid; x < BWD_SLOTS; x += blockDim.x) {
+            const uint32_t cp = keys[x];
+            if (cp == BWD_FREE) continue;
+            const float *o = vals + x * 8u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (o[q] != 0.0f) atomicAdd(gpos + 4 * (size_t)cp + q, o[q]);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                if (o[4 + q] != 0.0f) atomicAdd(grgb + 4 * (size_t)cp + q, o[4 + q]);
         }
-        if (interior) {
-            const double il = 1.0 / len2;
-            g_x0 += g_ts * (-dx - ux + 2.0 * traw * dx) * il;
-            g_x1 += g_ts * (ux - 2.0 * traw * dx) * il;
-            g_y0 += g_ts * (-dy - uy + 2.0 * traw * dy) * il;
-            g_y1 += g_ts * (uy - 2.0 * traw * dy) * il;
-        }
-        // pixel widths w = width fy / z
-        g_iz0 += g_w0 * (double)Q0.w * c.fy;
-        g_iz1 += g_w1 * (double)Q1.w * c.fy;
-        const double g_ww0 = g_w0 * c.fy * a.iz, g_ww1 = g_w1 * c.fy * b.iz;
-        gP0 = gP0 + proj_back(c, a, g_x0, g_y0, g_iz0);
-        gP1 = gP1 + proj_back(c, b, g_x1, g_y1, g_iz1);
-
-        atomic_add3(gpos + 4 * (size_t)v, gP0);
-        atomic_add3(gpos + 4 * ((size_t)v + 1), gP1);
-        atomicAdd(gpos + 4 * (size_t)v + 3, (float)g_ww0);
-        atomicAdd(gpos + 4 * ((size_t)v + 1) + 3, (float)g_ww1);
-        if (!root) atomic_add3(gpos + 4 * ((size_t)v - 1), gPm);
-        if (!tip) atomic_add3(gpos + 4 * ((size_t)v + 2), gPp);
-        atomic_add3(grgb + 4 * (size_t)v, gc0);
-        atomic_add3(grgb + 4 * ((size_t)v + 1), gc1);
+        __syncthreads();
     }
 }
 
@@ -766,8 +837,8 @@ void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camer
                         const hm_frame &f, const ShadeK &k, const float *d_out, float *gpos,
                         float *grgb, hipStream_t st)
 {
-    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
-    hipLaunchKernelGGL(k_soft_bwd, dim3(stride_grid(npix, 256)), dim3(256), 0, st,
+    const size_t ntiles = (size_t)((f.width + 15) / 16) * ((f.height + 15) / 16) * f.n_scenes;
+    hipLaunchKernelGGL(k_soft_bwd, dim3(stride_grid(ntiles * 256, 256)), dim3(256), 0, st,
                        reinterpret_cast<const float4 *>(s.pos_w),
                        reinterpret_cast<const float4 *>(s.rgb), (const uint8_t *)s.flags, vis,
                        cams, f.n_scenes, f.width, f.height, k,
