@@ -259,6 +259,38 @@ def extra_diff(steps):
             "params": int(n)}
 
 
+def extra_fused(steps):
+    """Generation fused with a direct (global-atomic) raster in one pass per
+    bundle, against the separate generate + binned tile raster, on the 1080p
+    head: whole frames and the generation + raster part alone."""
+    import torch
+    from paper_2607_04230_amd import hm, scenes
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_head()
+    ds = DeviceScene(sc)
+    ds.lod()
+    torch.cuda.synchronize()
+
+    def separate():
+        ds.generate()
+        ds.raster()
+    r = {"frame_ms_separate": _time_ms(ds.render, steps, 2),
+         "frame_ms_fused": _time_ms(ds.render_fused, steps, 2),
+         "gen_raster_ms_separate": _time_ms(separate, steps, 2),
+         "gen_raster_ms_fused": _time_ms(ds.generate_raster, steps, 2)}
+    hm.timing_enable(True)
+    hm.timing_collect()
+    for _ in range(steps):
+        ds.generate_raster()
+    torch.cuda.synchronize()
+    t = hm.timing_collect()
+    hm.timing_enable(False)
+    r["kernel_ms_fused"] = {k: v[0] / max(v[1], 1) for k, v in sorted(t.items())}
+    del ds
+    torch.cuda.empty_cache()
+    return r
+
+
 def extra_shadow(steps):
     """Deep-opacity-map shadows on the 1080p head: light-view raster, layer
     counts and per-pixel lookup (with the LOD depth correction), and the
@@ -427,7 +459,7 @@ def main():
         del ds
         torch.cuda.empty_cache()
         for name, fn in (("lod", extra_lod), ("batched", extra_batched), ("diff", extra_diff),
-                         ("shadow", extra_shadow)):
+                         ("shadow", extra_shadow), ("fused", extra_fused)):
             print(f"[bench] extra workload: {name}", file=sys.stderr, flush=True)
             line[name] = fn(max(args.steps // 2, 5))
     if not args.no_cpu:

@@ -161,6 +161,23 @@ hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
                               const hm_gen_params *p, const hm_strands *out, void *stream);
 
 /* ------------------------------------------------------------------ rasterization */
+/* Strand generation fused with the raster (Sec. 3.1.1 with 3.1.2: the paper
+ * assembles strands and rasterizes their segments in the same workgroup,
+ * without a separate pass over a stored stream).  One workgroup per bundle
+ * generates its control points exactly as hm_generate_strands (and writes
+ * them to out, for the resolve), projects each one where it is made, and
+ * rasterizes every segment of a finished chunk of strands from LDS with
+ * global atomic minima on both layers.  vis receives exactly what
+ * hm_raster_vis writes for the same stream (frame->n_scenes scenes, scene
+ * of bundle b = mesh->bundle_scene[b]; r_min as hm_raster_params.r_min;
+ * scene_z optional as there); no binning, so no workspace.  One view per
+ * scene (no shared views). */
+hm_status hm_generate_raster(const hm_hair_mesh *mesh, const uint32_t *table,
+                             const uint32_t *strand_base, const float *strand_rgb,
+                             const hm_gen_params *p, const hm_strands *out,
+                             const hm_camera *cams, const hm_frame *frame, float r_min,
+                             const float *scene_z, uint64_t *vis, void *stream);
+
 /* HM_RASTER_TILED: screen tiles resolved in LDS, candidate pixels spread one
  *   per lane (workgroups of at most 256 threads);
  * HM_RASTER_DIRECT: one thread per segment, 64-bit atomics on the buffer;

@@ -333,6 +333,28 @@ hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
     return check_launch("hm_generate_strands");
 }
 
+hm_status hm_generate_raster(const hm_hair_mesh *mesh, const uint32_t *table,
+                             const uint32_t *strand_base, const float *strand_rgb,
+                             const hm_gen_params *p, const hm_strands *out,
+                             const hm_camera *cams, const hm_frame *frame, float r_min,
+                             const float *scene_z, uint64_t *vis, void *stream)
+{
+    hm_status st;
+    if ((st = check_mesh(mesh)) || (st = check_strands(out)) || (st = check_frame(frame)))
+        return st;
+    REQUIRE(table && p && cams && vis, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(!strand_rgb || strand_base, HM_ERR_INVALID, "strand_rgb needs strand_base");
+    REQUIRE(isfinite(p->width) && isfinite(p->curl_amp) && isfinite(p->curl_turns) &&
+                p->curl_turns >= 0,
+            HM_ERR_RANGE, "generation parameters must be finite (curl_turns >= 0)");
+    REQUIRE(out->n_scenes == frame->n_scenes, HM_ERR_INVALID,
+            "strands.n_scenes (%u) != frame.n_scenes (%u)", out->n_scenes, frame->n_scenes);
+    REQUIRE(isfinite(r_min) && r_min >= 0.0f, HM_ERR_RANGE, "r_min must be finite, >= 0");
+    launch_generate_raster(*mesh, table, strand_base, strand_rgb, *p, *out, cams, *frame, r_min,
+                           scene_z, vis, (hipStream_t)stream);
+    return check_launch("hm_generate_raster");
+}
+
 hm_status hm_raster_vis(const hm_strands *s, const hm_camera *cams, const hm_frame *frame,
                         const hm_raster_params *p, const float *scene_z, uint64_t *vis,
                         void *ws, size_t ws_bytes, void *stream)

@@ -57,6 +57,15 @@ void launch_resolve_bwd(const hm_strands &s, const uint64_t *vis, const hm_camer
                         const hm_frame &f, const ShadeK &k, const float *d_out, float *gpos,
                         float *grgb, hipStream_t st);
 
+// strand generation fused with the raster (direct, global atomics)
+void launch_prefill(uint64_t *vis, const float *scene_z, const hm_camera *cams,
+                    const hm_frame &f, hipStream_t st);
+void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
+                            const uint32_t *strand_base, const float *strand_rgb,
+                            const hm_gen_params &p, const hm_strands &s, const hm_camera *cams,
+                            const hm_frame &f, float r_min, const float *scene_z, uint64_t *vis,
+                            hipStream_t st);
+
 // deep-opacity-map shadows
 size_t dom_workspace(const hm_frame &light_frame, uint32_t cap);
 void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_params &p,

@@ -284,14 +284,31 @@ struct GenK {
 // budget.
 constexpr uint32_t GEN_LDS_FLOATS = 6144;   // 24 KB
 
+// Raster side of the fused generate + raster kernel.
+struct FuseK {
+    const hm_camera *cams;
+    uint64_t *vis;        // [S][2][H][W], prefilled
+    uint32_t W, H;
+    float r_min;
+};
+constexpr uint32_t FUSE_CPS = 1024;        // screen records of one strand chunk in LDS (16 KB)
+
+// One workgroup per bundle.  FUSED: every control point is also projected
+// where it is generated (screen record in LDS, as the raster's projection
+// computes it), and once a chunk of strands is complete each of its segments
+// is rasterized from LDS by one thread with global atomic minima on both
+// layers -- the paper's assembly-and-raster in one pass, with the same
+// coverage tests, depth codes and keys as the raster call.
+template <bool FUSED>
 __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
                                                         const uint32_t *strand_base,
                                                         const float *strand_rgb, GenK g,
                                                         float4 *pos_w, float4 *rgb,
                                                         uint8_t *flags, const uint32_t *scene_off,
-                                                        uint32_t S, uint32_t cap)
+                                                        uint32_t S, uint32_t cap, FuseK fk)
 {
     __shared__ float sm[GEN_LDS_FLOATS];
+    __shared__ float4 pr[FUSED ? FUSE_CPS : 1];
     const uint32_t b = blockIdx.x;
     const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
     const uint32_t n = tb.x, C = tb.y, cp0 = tb.w;
@@ -300,7 +317,14 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
     const uint32_t limit = total < cap ? total : cap;
     const uint32_t NL = m.n_layers;
     const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
-    const uint32_t chunk = GEN_LDS_FLOATS / stride;        // >= 15 strands for L <= 64
+    uint32_t chunk = GEN_LDS_FLOATS / stride;              // >= 15 strands for L <= 64
+    if (FUSED) chunk = min(chunk, FUSE_CPS / C);           // >= 8 strands for C <= 127
+    Cam cam;
+    uint32_t sc = 0;
+    if (FUSED) {
+        sc = m.bundle_scene[b];
+        cam = load_cam(fk.cams + sc);
+    }
     const uint4 q4 = reinterpret_cast<const uint4 *>(m.quads)[b];
     const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
     const uint32_t hb = bundle_hash(g.seed, m.bundle_key[b]);
@@ -390,6 +414,7 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             pw.z = X[2] + amp * (cth * e1.z + sth * e2.z);
             pw.w = g.width;
             pos_w[c] = pw;
+            if (FUSED) pr[r] = project(cam, pw);
             float4 col;
             if (strand_rgb) {
                 const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k0 + kk);
@@ -405,6 +430,39 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             flags[c] = fl;
         }
         __syncthreads();
+        if (FUSED) {
+            // segments of the chunk: CP j of strand kk joins j + 1 unless j
+            // is a tip (last CP of its strand, or of a truncated stream)
+            const size_t hw = (size_t)fk.W * fk.H;
+            uint64_t *vc = fk.vis + (size_t)sc * 2 * hw, *va = vc + hw;
+            const float zn = cam.zn, inv_range = 1.0f / (cam.zf - zn);
+            for (uint32_t r = threadIdx.x; r < nk * C; r += blockDim.x) {
+                const uint32_t kk = r / C, j = r - kk * C;
+                const uint32_t c = cp0 + (k0 + kk) * C + j;
+                if (j + 1u >= C || c + 1u >= limit) continue;
+                const float4 pa = pr[r], pb = pr[r + 1];
+                if (pa.w == 0.0f || pb.w == 0.0f) continue;
+                const Seg sg = make_seg(pa, pb, fk.r_min);
+                int i0, i1, j0, j1;
+                if (!seg_box(sg, fk.W, fk.H, i0, i1, j0, j1)) continue;
+                for (int y = j0; y <= j1; ++y) {
+                    int a0, a1;
+                    row_span(sg, y, a0, a1);
+                    a0 = a0 > i0 ? a0 : i0;
+                    a1 = a1 < i1 ? a1 : i1;
+                    for (int x = a0; x <= a1; ++x) {
+                        uint32_t q;
+                        bool cc, ca;
+                        if (!cover(sg, x, y, fk.r_min, zn, inv_range, cc, ca, q)) continue;
+                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | c;
+                        const size_t px = (size_t)y * fk.W + x;
+                        if (cc) atomicMin((unsigned long long *)(vc + px), key);
+                        if (ca) atomicMin((unsigned long long *)(va + px), key);
+                    }
+                }
+            }
+            // pr is rewritten only after the next chunk's three barriers
+        }
     }
 }
 
@@ -414,10 +472,25 @@ void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_
 {
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    hipLaunchKernelGGL(k_generate_bundle, dim3(m.n_bundles), dim3(256), 0, st, m, table,
+    hipLaunchKernelGGL(k_generate_bundle<false>, dim3(m.n_bundles), dim3(256), 0, st, m, table,
                        strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
                        reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
-                       s.cap);
+                       s.cap, FuseK{nullptr, nullptr, 0u, 0u, 0.0f});
+}
+
+void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
+                            const uint32_t *strand_base, const float *strand_rgb,
+                            const hm_gen_params &p, const hm_strands &s, const hm_camera *cams,
+                            const hm_frame &f, float r_min, const float *scene_z, uint64_t *vis,
+                            hipStream_t st)
+{
+    launch_prefill(vis, scene_z, cams, f, st);
+    GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
+           p.base_rgb[2]};
+    hipLaunchKernelGGL(k_generate_bundle<true>, dim3(m.n_bundles), dim3(256), 0, st, m, table,
+                       strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
+                       reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
+                       s.cap, FuseK{cams, vis, f.width, f.height, r_min});
 }
 
 }  // namespace hm

@@ -114,50 +114,6 @@ __global__ __launch_bounds__(256) void k_project(const float4 *pos_w, const uint
 }
 
 // ------------------------------------------------------------------ helpers
-// Candidate pixel box of a segment (superset of every pixel either predicate
-// can accept), clipped to the image.  Returns false if empty.
-__device__ __forceinline__ bool seg_box(const Seg &sg, uint32_t W, uint32_t H, int &i0, int &i1,
-                                        int &j0, int &j1)
-{
-    const float xmn = sg.sxmn - sg.ra - 2.0f, xmx = sg.sxmx + sg.ra + 2.0f;
-    const float ymn = sg.symn - sg.ra - 2.0f, ymx = sg.symx + sg.ra + 2.0f;
-    if (!(xmx >= 0.0f && ymx >= 0.0f && xmn <= (float)W && ymn <= (float)H)) return false;
-    i0 = xmn > 0.0f ? (int)xmn : 0;
-    j0 = ymn > 0.0f ? (int)ymn : 0;
-    i1 = xmx < (float)(W - 1) ? (int)xmx : (int)W - 1;
-    j1 = ymx < (float)(H - 1) ? (int)ymx : (int)H - 1;
-    return i0 <= i1 && j0 <= j1;
-}
-
-// Column range of candidate pixels in row j.  Pixel (i, j) can pass either
-// test only if the segment has a point with y in [j - ra, j + 1 + ra] and x in
-// [i - ra, i + 1 + ra] (the centre test's disc of radius r <= ra around the
-// pixel centre lies inside that square).  So: clip the segment to the row band
-// widened by ra, and take i in [x_lo - 1 - ra, x_hi + ra]; the slack sg.e
-// (0.05 px plus ~8 ulp of the coordinates' magnitude) absorbs binary32
-// rounding of the clip: an error of the clip parameter is bounded by the
-// rounding of its numerator over |dy|, far below the band's widening e / |dy|.
-__device__ __forceinline__ void row_span(const Seg &sg, int j, int &i0, int &i1)
-{
-    const float e = sg.e;
-    const float ylo = ((float)j - sg.ra) - e, yhi = (((float)j + 1.0f) + sg.ra) + e;
-    float xlo = sg.sxmn, xhi = sg.sxmx;
-    if (sg.idy != 0.0f) {
-        float ta = (ylo - sg.y0) * sg.idy, tb = (yhi - sg.y0) * sg.idy;
-        float t0 = fmaxx(fminx(ta, tb), 0.0f), t1 = fminx(fmaxx(ta, tb), 1.0f);
-        if (t0 > t1) { i0 = 1; i1 = 0; return; }
-        float xa = sg.x0 + t0 * sg.dx, xb = sg.x0 + t1 * sg.dx;
-        xlo = fminx(xa, xb);
-        xhi = fmaxx(xa, xb);
-    } else if (sg.symx < ylo || sg.symn > yhi) {
-        i0 = 1; i1 = 0;
-        return;
-    }
-    const float flo = ((xlo - 1.0f) - sg.ra) - e, fhi = (xhi + sg.ra) + e;
-    i0 = flo > -1.0e9f ? (int)ceilf(flo) : -1000000000;
-    i1 = fhi < 1.0e9f ? (int)floorf(fhi) : 1000000000;
-}
-
 // Segment of unit u (stream point v): v must not be a tip; both screen
 // records must be inside the depth range.
 __device__ __forceinline__ bool load_seg(const float4 *proj, const uint8_t *flags, uint32_t u,
@@ -1008,6 +964,15 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.block = 256;
     p.grid = 0;
     p.shared_views = 0;
+}
+
+void launch_prefill(uint64_t *vis, const float *scene_z, const hm_camera *cams,
+                    const hm_frame &f, hipStream_t st)
+{
+    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
+    hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
+                       cams, f.n_scenes, f.width, f.height, (uint32_t *)nullptr, 0u,
+                       (uint32_t *)nullptr, 0u);
 }
 
 void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,

@@ -77,7 +77,7 @@ EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_
            "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
            "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
            "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset",
-           "hm_dom_accumulate", "hm_dom_shadow"]
+           "hm_dom_accumulate", "hm_dom_shadow", "hm_generate_raster"]
 
 
 def lod_depth_offset(table, bundle_nstrands, delta_out):
@@ -87,6 +87,17 @@ def lod_depth_offset(table, bundle_nstrands, delta_out):
     L.hm_lod_depth_offset.restype = _i32
     _check(L.hm_lod_depth_offset(_ptr(table), _ptr(bundle_nstrands), table.shape[0],
                                  _ptr(delta_out), _stream()), "hm_lod_depth_offset")
+
+
+def generate_raster(mesh, table, strand_base, strand_rgb, gp, st, cams, fr, r_min, scene_z,
+                    vis):
+    """Strand generation fused with the direct raster (stream and visibility)."""
+    L = load()
+    L.hm_generate_raster.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f32, _vp, _vp, _vp]
+    _check(L.hm_generate_raster(ctypes.byref(mesh), _ptr(table), _ptr(strand_base),
+                                _ptr(strand_rgb), ctypes.byref(gp), ctypes.byref(st), _ptr(cams),
+                                ctypes.byref(fr), r_min, _ptr(scene_z), _ptr(vis), _stream()),
+           "hm_generate_raster")
 
 
 def dom_accumulate(st, light, dp, light_vis, counts, ws):

@@ -89,6 +89,18 @@ class DeviceScene:
         hm.raster_vis(self.st, self.cams, self.fr, self.rparams, self.scene_z, self.vis,
                       self.ws_raster)
 
+    def generate_raster(self):
+        """Generation and raster in one pass (fused, direct atomics)."""
+        hm.generate_raster(self.mesh, self.table, self.strand_base, self.strand_rgb, self.gp,
+                           self.st, self.cams, self.fr, self.rparams.r_min, self.scene_z,
+                           self.vis)
+
+    def render_fused(self):
+        self.lod()
+        self.generate_raster()
+        self.resolve()
+        return self.out
+
     def resolve(self, out=None):
         hm.resolve_shade(self.st, self.vis, self.cams, self.fr, self.sp,
                          self.out if out is None else out, self.ws_resolve)

@@ -108,6 +108,19 @@ def test_validation_errors_are_reported():
     assert L.hm_lod_select(ctypes.byref(m), dummy, ctypes.byref(fr), ctypes.byref(lp), dummy,
                            dummy, dummy, dummy, 1 << 20, None) == 2
     assert b"n_layers" in L.hm_last_error()
+    # fused generation + raster: scene counts must agree, r_min >= 0
+    gp = hm.GenParams()
+    assert L.hm_generate_raster(ctypes.byref(m), dummy, None, None, ctypes.byref(gp),
+                                ctypes.byref(st), dummy, ctypes.byref(fr2), ctypes.c_float(0.0),
+                                None, dummy, None) == 2          # the mesh's n_layers is 1
+    m2 = hm.HairMesh(dummy, dummy, dummy, dummy, dummy, dummy, 4, 4, 10)
+    assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
+                                ctypes.byref(st), dummy, ctypes.byref(fr2), ctypes.c_float(0.0),
+                                None, dummy, None) == 1
+    assert b"n_scenes" in L.hm_last_error()
+    assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
+                                ctypes.byref(st), dummy, ctypes.byref(fr), ctypes.c_float(-1.0),
+                                None, dummy, None) == 2
     # shadows: single scene, layer count and opacity ranges, workspace
     dp = hm.DomParams(64, 64, 4, 1000, 0.5, 0.05)
     ws = hm.workspace_size(hm.CALL_DOM, fr, cap=1000)

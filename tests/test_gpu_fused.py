@@ -1,0 +1,96 @@
+"""GPU parity of strand generation fused with the raster (Sec. 3.1.1 with
+3.1.2: one workgroup per bundle generates, projects and rasterizes): the
+stream and the visibility buffer bit for bit against the oracle and against
+the separate generate + tiled raster calls, RGBA of the resolve within 1e-4."""
+import numpy as np
+import pytest
+
+from paper_2607_04230_amd import scenes
+from paper_2607_04230_amd.scenes import ResolveParams
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _fused(sc, torch, cap=None):
+    from paper_2607_04230_amd.render import DeviceScene
+    print(f"[fused] {sc.name} {sc.width}x{sc.height} scenes={sc.n_scenes} cap={cap}", flush=True)
+    ds = DeviceScene(sc, cap=cap)
+    ds.render_fused()
+    torch.cuda.synchronize()
+    return ds
+
+
+def _separate(sc, torch, cap=None):
+    from paper_2607_04230_amd.render import DeviceScene
+    ds = DeviceScene(sc, cap=cap)
+    ds.render()
+    torch.cuda.synchronize()
+    return ds
+
+
+def test_tiny_fused_matches_oracle(O, torch):
+    sc = scenes.config_tiny()
+    ref = O.render(sc)
+    ds = _fused(sc, torch)
+    pos, rgb, fl = ds.host_stream()
+    assert np.array_equal(fl, ref["flags"])
+    assert np.array_equal(pos.view(np.uint32), ref["pos_w"].view(np.uint32))
+    assert np.array_equal(rgb.view(np.uint32), ref["rgb"].view(np.uint32))
+    assert np.array_equal(ds.host_vis(), ref["vis"])
+    assert np.abs(ds.out.cpu().numpy().astype(np.float64) - ref["out"]).max() <= TOL
+
+
+def test_head_with_occluder_fused_matches_oracle_and_tiled(O, torch):
+    sc = scenes.config_head(width=640, height=360, strands_per_quad=16)
+    assert sc.scene_z is not None
+    ds = _fused(sc, torch)
+    sep = _separate(sc, torch)
+    assert np.array_equal(ds.host_vis(), sep.host_vis())
+    assert torch.equal(ds.out, sep.out)
+    pos, rgb, fl = ds.host_stream()
+    soff = ds.scene_off.cpu().numpy().view(np.uint32)
+    vis = O.raster(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+    assert np.array_equal(ds.host_vis(), vis)
+
+
+def test_batched_fused_matches_tiled_and_oracle(O, torch):
+    """Uneven scenes in one frame: every bundle rasterizes into its own scene."""
+    sc = scenes.config_batched(n_scenes=12, res=256, n_min=1e3, n_max=2e4)
+    ds = _fused(sc, torch)
+    sep = _separate(sc, torch)
+    assert np.array_equal(ds.host_vis(), sep.host_vis())
+    assert torch.equal(ds.out, sep.out)
+    pos, rgb, fl = ds.host_stream()
+    soff = ds.scene_off.cpu().numpy().view(np.uint32)
+    for s in (0, 5, 11):
+        order = np.arange(soff[s], soff[s + 1], dtype=np.uint32)
+        vis = O.raster(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z,
+                       order=order)
+        assert np.array_equal(ds.host_vis()[s], vis[s]), s
+
+
+@pytest.mark.parametrize("cap", [1001, 5000])
+def test_fused_truncated_stream(O, torch, cap):
+    sc = scenes.config_tiny()
+    table, soff, (ns, ncp) = O.lod_select(sc)
+    assert cap < ncp
+    pos, rgb, fl = O.generate(sc, table, ncp, cap=cap)
+    soff_c = np.minimum(soff, cap).astype(np.uint32)
+    vis = O.raster(pos, fl, soff_c, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+    ds = _fused(sc, torch, cap=cap)
+    gp, gr, gf = ds.host_stream()
+    assert np.array_equal(gf, fl)
+    assert np.array_equal(gp.view(np.uint32), pos.view(np.uint32))
+    assert np.array_equal(ds.host_vis(), vis)
+    out = O.resolve(pos, rgb, fl, vis, sc.cams, sc.width, sc.height, ResolveParams(), sc.mode,
+                    sc.bg)
+    assert np.abs(ds.out.cpu().numpy().astype(np.float64) - out).max() <= TOL
