@@ -190,7 +190,8 @@ typedef struct {
     int32_t algo;             /* HM_RASTER_TILED, HM_RASTER_DIRECT or HM_RASTER_TILED_ROWS */
     uint32_t tile;            /* tile edge in pixels: 8, 16 or 32 */
     uint32_t chunk;           /* segments per work item of a tile (>= 1) */
-    uint32_t max_tiles_per_seg; /* segments touching more tiles take the direct path (1..64) */
+    uint32_t max_tiles_per_seg; /* K: segments touching more than min(K, 24) tiles take
+                                   the direct path (1..64) */
     uint32_t block;           /* threads per workgroup: a multiple of 64 in [64, 1024]
                                  (at most 256 for HM_RASTER_TILED); the tile kernel's LDS
                                  (layers + per-lane records) must stay within 64 KiB */

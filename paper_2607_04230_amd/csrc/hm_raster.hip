@@ -284,91 +284,121 @@ __device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
 }
 
 // Per-tile segment lists.  Each workgroup takes nsub * blockDim consecutive
-// segments (consecutive segments belong to the same few strands, so they fall
-// in a few tiles) and aggregates its (segment, tile) pairs per tile in an LDS table:
-//   pass 0: counts per tile, flushed with one non-returning global add per
-//           (workgroup, tile); segments spanning more than K tiles go to the
-//           long list;
-//   pass 1: one returning global add per (workgroup, tile) reserves a range
-//           of the tile's list; pairs then take LDS-atomic ranks inside it.
+// segments (a "span"; consecutive segments belong to the same few strands, so
+// they fall in a few tiles) and aggregates its (segment, tile) pairs per tile
+// in an LDS table:
+//   pass 0: projects the control points (screen records), finds each
+//           segment's tiles (tile box + separating-axis test) and stores them
+//           as one 8-byte record per segment: the first tile of its box, the
+//           box width and a bit mask of the accepted tiles (segments with
+//           more than BIN_KMAX or K tiles go to the long list); counts pairs
+//           per tile in the table, flushes them with one non-returning
+//           global add per (span, tile) and saves the table;
+//   pass 1: restores the span's table, reserves a range of each tile's list
+//           with one returning global add per (span, tile), then walks the
+//           segment records and gives each pair an LDS-atomic rank inside
+//           its range -- no screen record is read again.
+// Pairs that found the table full go straight to global counters in both
+// passes.
+constexpr uint32_t BIN_KMAX = 24;         // tile-mask bits in a segment record
+constexpr uint32_t BIN_NONE = 0xFFFFFFFFu;
+
+__device__ __forceinline__ int bin_find(const uint32_t *keys, uint32_t tile)
+{
+    const uint32_t h = (tile * 2654435761u) >> 22;
+    for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
+        const uint32_t q = (h + i) & (BIN_SLOTS - 1);
+        const uint32_t kq = keys[q];
+        if (kq == tile) return (int)q;
+        if (kq == BIN_FREE) return -1;
+    }
+    return -1;
+}
+
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const float4 *pos_w,
                                                    const hm_camera *cams, const uint8_t *flags,
                                                    const uint32_t *scene_off, RasterK rk,
                                                    uint32_t cap, uint32_t *tile_cnt,
                                                    const uint32_t *tile_off, uint32_t *tile_cur,
                                                    uint32_t *entries, uint32_t *long_list,
-                                                   uint32_t *counters, uint32_t nsub)
+                                                   uint32_t *counters, uint32_t nsub,
+                                                   uint2 *segrec, uint32_t *saved)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
     const uint32_t span = BIN_BLOCK * nsub;        // segments per table flush
+    const uint32_t kmax = rk.K < BIN_KMAX ? rk.K : BIN_KMAX;
     // v below is a segment unit (see unit_map); lists store units
     for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
-        for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
-            keys[x] = BIN_FREE;
-            cnt[x] = 0;
-        }
-        __syncthreads();
-        for (uint32_t sub = 0; sub < nsub; ++sub) {
-            const uint32_t v = base + sub * blockDim.x + threadIdx.x;
-            SegTiles st;
-            bool ok = pass == 0
-                          ? seg_tiles<true>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st)
-                          : seg_tiles<false>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st);
-            if (ok && st.nt > rk.K) {
-                if (pass == 0) long_list[atomicAdd(&counters[0], 1u)] = v;
-                ok = false;
-            }
-            if (!ok) continue;
-            for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
-            for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
-                uint32_t tile;
-                if (!seg_tile_at(st, rk, kx, ky, tile)) continue;
-                const int sl = bin_slot(keys, tile);
-                if (sl >= 0) atomicAdd(&cnt[sl], 1u);
-                else if (pass == 0) atomicAdd(&tile_cnt[tile], 1u);
-                else entries[tile_off[tile] + atomicAdd(&tile_cur[tile], 1u)] = v;
-            }
-        }
-        __syncthreads();
-        for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
-            const uint32_t t = keys[x];
-            if (t == BIN_FREE) continue;
-            if (pass == 0) {
-                atomicAdd(&tile_cnt[t], cnt[x]);
-            } else {
-                basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], cnt[x]);
+        uint32_t *sv = saved + (size_t)(base / span) * (2 * BIN_SLOTS);
+        if (pass == 0) {
+            for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+                keys[x] = BIN_FREE;
                 cnt[x] = 0;
             }
-        }
-        __syncthreads();
-        if (pass == 1) {
+            __syncthreads();
             for (uint32_t sub = 0; sub < nsub; ++sub) {
                 const uint32_t v = base + sub * blockDim.x + threadIdx.x;
                 SegTiles st;
-                if (!seg_tiles<false>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st) ||
-                    st.nt > rk.K)
-                    continue;
-                for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
-                for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
-                    uint32_t tile;
-                    if (!seg_tile_at(st, rk, kx, ky, tile)) continue;
-                    // the slot exists already unless the table was full when
-                    // the pair was inserted (it was then written directly)
-                    const uint32_t h = (tile * 2654435761u) >> 22;
-                    int sl = -1;
-                    for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
-                        const uint32_t q = (h + i) & (BIN_SLOTS - 1);
-                        const uint32_t kq = keys[q];
-                        if (kq == tile) { sl = (int)q; break; }
-                        if (kq == BIN_FREE) break;
+                bool ok = seg_tiles<true>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st);
+                if (ok && st.nt > kmax) {
+                    long_list[atomicAdd(&counters[0], 1u)] = v;
+                    ok = false;
+                }
+                uint2 rec = make_uint2(BIN_NONE, 0u);
+                if (ok) {
+                    uint32_t mask = 0, tile0 = 0;
+                    for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
+                    for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
+                        uint32_t tile;
+                        const bool hit = seg_tile_at(st, rk, kx, ky, tile);
+                        if (k == 0) tile0 = tile;
+                        if (!hit) continue;
+                        mask |= 1u << k;
+                        const int sl = bin_slot(keys, tile);
+                        if (sl >= 0) atomicAdd(&cnt[sl], 1u);
+                        else atomicAdd(&tile_cnt[tile], 1u);
                     }
+                    if (mask) rec = make_uint2(tile0, st.bw | (mask << 8));
+                }
+                if (v < nu) segrec[v] = rec;
+            }
+            __syncthreads();
+            for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+                const uint32_t t = keys[x], c = cnt[x];
+                sv[x] = t;
+                sv[BIN_SLOTS + x] = c;
+                if (t != BIN_FREE) atomicAdd(&tile_cnt[t], c);
+            }
+            __syncthreads();
+        } else {
+            for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+                const uint32_t t = sv[x];
+                keys[x] = t;
+                cnt[x] = 0;
+                if (t != BIN_FREE) basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], sv[BIN_SLOTS + x]);
+            }
+            __syncthreads();
+            for (uint32_t sub = 0; sub < nsub; ++sub) {
+                const uint32_t v = base + sub * blockDim.x + threadIdx.x;
+                if (v >= nu) continue;
+                const uint2 rec = segrec[v];
+                if (rec.x == BIN_NONE) continue;
+                const uint32_t bw = rec.y & 0xFFu;
+                uint32_t mask = rec.y >> 8;
+                while (mask) {
+                    const uint32_t k = (uint32_t)__builtin_ctz(mask);
+                    mask &= mask - 1u;
+                    const uint32_t ky = k / bw, kx = k - ky * bw;
+                    const uint32_t tile = rec.x + ky * rk.ntx + kx;
+                    const int sl = bin_find(keys, tile);
                     if (sl >= 0) entries[basev[sl] + atomicAdd(&cnt[sl], 1u)] = v;
+                    else entries[tile_off[tile] + atomicAdd(&tile_cur[tile], 1u)] = v;
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
@@ -914,8 +944,23 @@ struct RasterWs {
     uint32_t *counters;   // [0] long count, [1] work counter
     uint32_t *long_list;  // cap
     uint32_t *entries;    // cap * K
+    uint2 *segrec;        // per unit: first tile of its box, box width | tile mask << 8
+    uint32_t *saved;      // per binning span: its LDS table (keys, counts)
+    uint32_t nsub;        // segments per thread and span
     size_t bytes;
 };
+
+// Segments per thread between table flushes: up to BIN_SUB, fewer when that
+// would leave fewer than BIN_WGS workgroups.  Measured: a 9 k-segment frame
+// bins in 9 us with one segment per thread against 34 us with 8 (5
+// workgroups); more workgroups than ~1024 cost more in contended per-tile
+// global adds than they gain (2 M segments: 58 us at 1024 or fewer, 62 us at
+// 2048, 78 us at 4096).
+static uint32_t bin_nsub(size_t units)
+{
+    const size_t per_sub = (size_t)BIN_BLOCK * BIN_WGS;
+    return (uint32_t)std::min<size_t>(std::max<size_t>(units / per_sub, 1), BIN_SUB);
+}
 
 static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster_params &p)
 {
@@ -935,9 +980,16 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
     if (p.algo != HM_RASTER_DIRECT) {
         w.long_list = (uint32_t *)take(sizeof(uint32_t) * units);
         w.entries = (uint32_t *)take(sizeof(uint32_t) * units * p.max_tiles_per_seg);
+        w.nsub = bin_nsub(units);
+        const size_t spans = (units + (size_t)BIN_BLOCK * w.nsub - 1) / ((size_t)BIN_BLOCK * w.nsub);
+        w.segrec = (uint2 *)take(sizeof(uint2) * units);
+        w.saved = (uint32_t *)take(sizeof(uint32_t) * 2 * BIN_SLOTS * spans);
     } else {
         w.long_list = nullptr;
         w.entries = nullptr;
+        w.segrec = nullptr;
+        w.saved = nullptr;
+        w.nsub = 1;
     }
     w.bytes = o;
     return w;
@@ -998,20 +1050,12 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     }
     // pass 0 of the binning also writes every unit's screen record
     const uint32_t nt = rk.n_tiles;
-    // segments per thread between flushes: up to BIN_SUB, fewer when that
-    // would leave fewer than BIN_WGS workgroups.  Measured: a 9 k-segment
-    // frame bins in 9 us with one segment per thread against 34 us with 8
-    // (5 workgroups); more workgroups than ~1024 cost more in contended
-    // per-tile global adds than they gain (2 M segments: 58 us at 1024 or
-    // fewer, 62 us at 2048, 78 us at 4096)
-    const size_t per_sub = (size_t)BIN_BLOCK * BIN_WGS;
-    const uint32_t nsub =
-        (uint32_t)std::min<size_t>(std::max<size_t>(units / per_sub, 1), BIN_SUB);
+    const uint32_t nsub = w.nsub;
     const uint32_t gb = stride_grid((units + nsub - 1) / nsub, BIN_BLOCK);
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters,
-                       nsub);
+                       nsub, w.segrec, w.saved);
     const bool small = nt <= PLAN_SMALL;
     if (small) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), 0, st, w.tile_cnt, nt, rk.chunk,
@@ -1024,7 +1068,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
-                       w.counters, nsub);
+                       w.counters, nsub, w.segrec, w.saved);
     if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
