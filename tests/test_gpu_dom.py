@@ -106,3 +106,39 @@ def test_shadow_calls_are_repeatable(O, torch):
     ds.shadows(shp)
     torch.cuda.synchronize()
     assert torch.equal(c1, ds.dom_counts) and torch.equal(t1, ds.shadow)
+
+
+def test_light_seeing_nothing_leaves_the_frame_unshadowed(O, torch):
+    """A light camera whose depth range ends before the groom sees no strand:
+    the map is empty, every T is 1 and the shadowed frame equals the
+    unshadowed one bit for bit."""
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_tiny()
+    shp = ShadowParams(width=64, height=64, distance=-3.0, znear=0.1, zfar=0.5)
+    ds = DeviceScene(sc)
+    ds.render()
+    torch.cuda.synchronize()
+    plain = ds.out.clone()
+    ds.shadows(shp)
+    ds.resolve()
+    torch.cuda.synchronize()
+    assert (ds.light_vis.cpu().numpy().view(np.uint64) == np.uint64(0xFFFFFFFFFFFFFFFF)).all()
+    assert int(ds.dom_counts.sum().item()) == 0
+    assert bool((ds.shadow == 1.0).all())
+    assert torch.equal(ds.out, plain)
+
+
+def test_empty_camera_view_has_unit_shadow(O, torch):
+    """Every segment behind the camera: no centre hit, so T = 1 everywhere
+    while the light's map still counts the groom's fragments."""
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_tiny()
+    sc.cams = scenes.look_at_camera((0.0, 1.3, 2.6), (0.0, 1.3, 6.0), sc.width,
+                                    sc.height)[None].astype(np.float32)
+    shp = ShadowParams(width=128, height=128, distance=3.0, layer_world=0.02)
+    ds = DeviceScene(sc)
+    ds.render_shadowed(shp)
+    torch.cuda.synchronize()
+    assert int(ds.dom_counts.sum().item()) > 0
+    assert bool((ds.shadow == 1.0).all())
+    assert (ds.out.cpu().numpy()[..., 3] == 0.0).all()
