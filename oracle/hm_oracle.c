@@ -398,8 +398,19 @@ uint32_t orc_qdepth_export(float z, float znear, float zfar)
 /* Centre-sample and conservative coverage of pixel (i, j) by the projected
  * segment a -> b (each (x, y, pixel width, 1/z)).  Writes the key depth code
  * when either test passes.  Returns bit0 = centre, bit1 = conservative. */
+static int orc_cover_tz(const float a[4], const float b[4], int i, int j, float r_min,
+                        float znear, float inv_range, uint32_t *q, float *ts_out, float *z_out);
+
 static int orc_cover(const float a[4], const float b[4], int i, int j, float r_min,
                      float znear, float inv_range, uint32_t *q)
+{
+    return orc_cover_tz(a, b, i, j, r_min, znear, inv_range, q, NULL, NULL);
+}
+
+/* As orc_cover; also returns the clamped closest-point parameter ts and the
+ * linear depth z the depth code is taken from (binary32). */
+static int orc_cover_tz(const float a[4], const float b[4], int i, int j, float r_min,
+                        float znear, float inv_range, uint32_t *q, float *ts_out, float *z_out)
 {
     float x0 = a[0], y0 = a[1], w0 = a[2], iz0 = a[3];
     float x1 = b[0], y1 = b[1], w1 = b[2], iz1 = b[3];
@@ -453,6 +464,8 @@ static int orc_cover(const float a[4], const float b[4], int i, int j, float r_m
     float iz = iz0 + ts * (iz1 - iz0);
     float z = 1.0f / iz;
     *q = orc_qdepth(z, znear, inv_range);
+    if (ts_out) *ts_out = ts;
+    if (z_out) *z_out = z;
     return (center ? 1 : 0) | (cons ? 2 : 0);
 }
 
@@ -638,6 +651,9 @@ static v3d orc_cp_tangent(const float *pos_w, const uint8_t *flags, uint64_t v)
 /* Deferred 1-spp shading of segment v seen through pixel centre (px, py):
  * Kajiya-Kay style diffuse sin(T, L) term plus a sin^(2^(n+1)) specular lobe
  * about the half vector, one directional light (Sec. 3.4, simplified). */
+static void orc_shade_point(const orc_cam *c, const orc_shade_params *sp, v3d X, v3d T,
+                            const double albv[3], double shadow, double ao, double out[3]);
+
 static void orc_shade_px(const float *pos_w, const float *rgb, const uint8_t *flags,
                          const orc_cam *c, const orc_shade_params *sp, uint64_t v,
                          double px, double py, double shadow, double out[3])
@@ -660,6 +676,16 @@ static void orc_shade_px(const float *pos_w, const float *rgb, const uint8_t *fl
     v3d T = d3_norm(d3_add(T0, d3_scale(d3_sub(T1, T0), t3)));
     v3d c0 = d3_loadf(rgb + 4 * v), c1 = d3_loadf(rgb + 4 * (v + 1));
     v3d alb = d3_add(c0, d3_scale(d3_sub(c1, c0), t3));
+    double albv[3] = {alb.x, alb.y, alb.z};
+    orc_shade_point(c, sp, X, T, albv, shadow, 1.0, out);
+}
+
+/* Kajiya-Kay style shading of point X with unit tangent T and albedo alb
+ * (Sec. 3.4, simplified): ambient (scaled by the occlusion ao) plus diffuse
+ * and specular terms (scaled by the light's transmittance). */
+static void orc_shade_point(const orc_cam *c, const orc_shade_params *sp, v3d X, v3d T,
+                            const double albv[3], double shadow, double ao, double out[3])
+{
     v3d eye = d3(c->eye[0], c->eye[1], c->eye[2]);
     v3d V = d3_norm(d3_sub(eye, X));
     v3d L = d3_norm(d3(sp->light_dir[0], sp->light_dir[1], sp->light_dir[2]));
@@ -671,10 +697,9 @@ static void orc_shade_px(const float *pos_w, const float *rgb, const uint8_t *fl
     sh = sh > 0.0 ? sh : 0.0;
     double spec = sh;
     for (int k = 0; k < sp->spec_squarings; ++k) spec = spec * spec;
-    double albv[3] = {alb.x, alb.y, alb.z};
     /* the light's transmittance scales the direct terms, not the ambient one */
     for (int ch = 0; ch < 3; ++ch)
-        out[ch] = albv[ch] * sp->light_rgb[ch] * (sp->ka + shadow * sp->kd * diff) +
+        out[ch] = albv[ch] * sp->light_rgb[ch] * (sp->ka * ao + shadow * sp->kd * diff) +
                   shadow * sp->ks * sp->light_rgb[ch] * spec;
 }
 
@@ -967,5 +992,213 @@ int orc_dom_shadow(const float *pos_w, const uint8_t *flags, const uint64_t *vis
             shadow[p] = exp(-alpha * o);
         }
     (void)flags;
+    return 0;
+}
+
+/* ------------------------------------------------------------ compressed G-buffer
+ * The paper's 64-bit deferred-shading word (Sec. 3.1.2, deferred atomic
+ * shading): the 24-bit depth code in the high bits (so that the atomic
+ * minimum still keeps the nearest fragment), then 40 bits of shading inputs
+ * quantised to 8 or 6 bits.  Reading (the bit layout is not printed):
+ *   bits 39..32, 31..24  octahedral tangent (u, v), 8 bits each
+ *   bits 23..18, 17..12, 11..6  albedo r, g, b, 6 bits each (the appearance
+ *                                parameters; the paper stores uvw to look
+ *                                them up, here they are the colours)
+ *   bits 5..0   ambient occlusion, 6 bits (no baked AO: always 63)
+ * Position is not stored: the resolve reconstructs it from the depth at the
+ * pixel centre.  Every step that decides bits is binary32, in the order
+ * written. */
+
+/* unit tangent of CP v as the resolve computes it (binary32); zero for a CP
+ * that is both root and tip (it starts no segment) */
+static v3f orc_cp_tangent32(const float *pos_w, const uint8_t *flags, uint64_t v)
+{
+    const uint8_t f = flags[v];
+    v3f d = {0.0f, 0.0f, 0.0f};
+    if ((f & ORC_ROOT) && (f & ORC_TIP)) return d;
+    if (f & ORC_ROOT) d = v3_sub(v3_load(pos_w + 4 * (v + 1)), v3_load(pos_w + 4 * v));
+    else if (f & ORC_TIP) d = v3_sub(v3_load(pos_w + 4 * v), v3_load(pos_w + 4 * (v - 1)));
+    else d = v3_sub(v3_load(pos_w + 4 * (v + 1)), v3_load(pos_w + 4 * (v - 1)));
+    return v3_norm(d);
+}
+
+/* x in [-1, 1] -> 0 .. 255 (round to nearest) */
+static uint32_t orc_q8(float x)
+{
+    float f = (x * 0.5f + 0.5f) * 255.0f + 0.5f;
+    f = f > 0.0f ? f : 0.0f;
+    f = f < 255.0f ? f : 255.0f;
+    return (uint32_t)f;
+}
+
+/* c in [0, 1] -> 0 .. 63 (round to nearest) */
+static uint32_t orc_q6(float c)
+{
+    float f = c * 63.0f + 0.5f;
+    f = f > 0.0f ? f : 0.0f;
+    f = f < 63.0f ? f : 63.0f;
+    return (uint32_t)f;
+}
+
+/* Octahedral map of a direction (Meyer et al. 2010; survey by Cigolle et
+ * al. 2014): project onto the octahedron |x| + |y| + |z| = 1, fold the lower
+ * half (z < 0) over the diagonals, keep (x, y).  A zero vector maps to the
+ * centre. */
+static uint32_t orc_oct16(v3f t)
+{
+    float l1 = (fabsf(t.x) + fabsf(t.y)) + fabsf(t.z);
+    float px = 0.0f, py = 0.0f;
+    if (l1 > 0.0f) {
+        px = t.x / l1;
+        py = t.y / l1;
+        if (t.z < 0.0f) {
+            float ax = fabsf(px), ay = fabsf(py);
+            float sx = px >= 0.0f ? 1.0f : -1.0f, sy = py >= 0.0f ? 1.0f : -1.0f;
+            px = (1.0f - ay) * sx;
+            py = (1.0f - ax) * sy;
+        }
+    }
+    return (orc_q8(px) << 8) | orc_q8(py);
+}
+
+uint32_t orc_oct16_export(const float t[3])
+{
+    v3f v = {t[0], t[1], t[2]};
+    return orc_oct16(v);
+}
+
+/* 40-bit payload of segment v at closest-point parameter ts with linear depth
+ * z: perspective-correct segment parameter t3 = ts * (1/z_1) * z, tangent and
+ * albedo interpolated at t3 */
+static uint64_t orc_payload(const v3f *T, const float *rgb, uint64_t v, float ts, float z,
+                            float iz1)
+{
+    float t3 = (ts * iz1) * z;
+    v3f t = v3_lerp(T[v], T[v + 1], t3);
+    v3f c = v3_lerp(v3_load(rgb + 4 * v), v3_load(rgb + 4 * (v + 1)), t3);
+    uint64_t w = (uint64_t)orc_oct16(t) << 24;
+    w |= (uint64_t)orc_q6(c.x) << 18;
+    w |= (uint64_t)orc_q6(c.y) << 12;
+    w |= (uint64_t)orc_q6(c.z) << 6;
+    w |= 63u;
+    return w;
+}
+
+/* Visibility buffer with G-buffer payloads: as orc_raster (bounding-box
+ * enumeration), every covering segment's key being depth << 40 | payload. */
+int orc_raster_gbuf(const float *pos_w, const float *rgb, const uint8_t *flags,
+                    const uint32_t *scene_off, const float *cams, uint32_t n_scenes, int width,
+                    int height, float r_min, const float *scene_z, uint64_t *vis)
+{
+    size_t npix = (size_t)width * (size_t)height;
+    uint64_t n_cp = scene_off[n_scenes];
+    v3f *T = (v3f *)malloc(sizeof(v3f) * (n_cp ? n_cp : 1));
+    if (!T) return -1;
+    for (uint64_t v = 0; v < n_cp; ++v) T[v] = orc_cp_tangent32(pos_w, flags, v);
+    for (uint32_t s = 0; s < n_scenes; ++s) {
+        const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)s);
+        float inv_range = 1.0f / (c->zfar - c->znear);
+        uint64_t *v0 = vis + (size_t)s * 2 * npix, *v1 = v0 + npix;
+        for (size_t p = 0; p < npix; ++p) {
+            uint64_t k = ORC_EMPTY;
+            if (scene_z) {
+                float z = scene_z[(size_t)s * npix + p];
+                if (z > c->znear && z < c->zfar)
+                    k = ((uint64_t)orc_qdepth(z, c->znear, inv_range) << ORC_ID_BITS) | ORC_ID_OPAQUE;
+            }
+            v0[p] = k;
+            v1[p] = k;
+        }
+    }
+    uint32_t s = 0;
+    for (uint64_t v = 0; v + 1 < n_cp; ++v) {
+        if (flags[v] & ORC_TIP) continue;
+        while (s + 1 < n_scenes && v >= scene_off[s + 1]) s++;
+        const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)s);
+        float inv_range = 1.0f / (c->zfar - c->znear);
+        float a[4], b[4];
+        if (!orc_proj(c, pos_w + 4 * v, a) || !orc_proj(c, pos_w + 4 * (v + 1), b)) continue;
+        float iz1 = a[3] + (b[3] - a[3]);
+        uint64_t *v0 = vis + (size_t)s * 2 * npix, *v1 = v0 + npix;
+        float ra = 0.5f * (a[2] > b[2] ? a[2] : b[2]);
+        ra = ra > r_min ? ra : r_min;
+        float xmn = (a[0] < b[0] ? a[0] : b[0]) - ra - 2.0f;
+        float xmx = (a[0] > b[0] ? a[0] : b[0]) + ra + 2.0f;
+        float ymn = (a[1] < b[1] ? a[1] : b[1]) - ra - 2.0f;
+        float ymx = (a[1] > b[1] ? a[1] : b[1]) + ra + 2.0f;
+        if (xmx < 0.0f || ymx < 0.0f || xmn > (float)width || ymn > (float)height) continue;
+        int i0 = xmn > 0.0f ? (int)xmn : 0, j0 = ymn > 0.0f ? (int)ymn : 0;
+        int i1 = xmx < (float)(width - 1) ? (int)xmx : width - 1;
+        int j1 = ymx < (float)(height - 1) ? (int)ymx : height - 1;
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) {
+                uint32_t q;
+                float ts, z;
+                int m = orc_cover_tz(a, b, i, j, r_min, c->znear, inv_range, &q, &ts, &z);
+                if (!m) continue;
+                uint64_t key = ((uint64_t)q << ORC_ID_BITS) | orc_payload(T, rgb, v, ts, z, iz1);
+                size_t p = (size_t)j * width + i;
+                if ((m & 1) && key < v0[p]) v0[p] = key;
+                if ((m & 2) && key < v1[p]) v1[p] = key;
+            }
+    }
+    free(T);
+    return 0;
+}
+
+/* Shading of one G-buffer pixel (binary64): the position is reconstructed
+ * at the pixel centre from the depth code (the middle of its code interval),
+ * the tangent from its octahedral code, the albedo and AO from their 6-bit
+ * codes; then the shading of the resolve (AO scales the ambient term). */
+static void orc_gbuf_decode(const orc_cam *c, uint64_t key, double px, double py, v3d *X,
+                            v3d *T, double alb[3], double *ao)
+{
+    uint64_t w = key & ORC_ID_MASK;
+    double q = (double)(key >> ORC_ID_BITS);
+    double z = c->znear + (q + 0.5) / 16777216.0 * ((double)c->zfar - c->znear);
+    double xc = (px - c->cx) * z / c->fx, yc = -(py - c->cy) * z / c->fy;
+    /* world = eye + R^T (xc, yc, z) */
+    X->x = c->eye[0] + (c->R[0] * xc + c->R[3] * yc + c->R[6] * z);
+    X->y = c->eye[1] + (c->R[1] * xc + c->R[4] * yc + c->R[7] * z);
+    X->z = c->eye[2] + (c->R[2] * xc + c->R[5] * yc + c->R[8] * z);
+    double u = (double)((w >> 32) & 0xFFu) / 255.0 * 2.0 - 1.0;
+    double v = (double)((w >> 24) & 0xFFu) / 255.0 * 2.0 - 1.0;
+    double tz = 1.0 - fabs(u) - fabs(v);
+    if (tz < 0.0) {
+        double au = fabs(u), av = fabs(v);
+        u = (1.0 - av) * (u >= 0.0 ? 1.0 : -1.0);
+        v = (1.0 - au) * (v >= 0.0 ? 1.0 : -1.0);
+    }
+    *T = d3_norm(d3(u, v, tz));
+    alb[0] = (double)((w >> 18) & 63u) / 63.0;
+    alb[1] = (double)((w >> 12) & 63u) / 63.0;
+    alb[2] = (double)((w >> 6) & 63u) / 63.0;
+    *ao = (double)(w & 63u) / 63.0;
+}
+
+/* Centre-only resolve of a G-buffer visibility buffer (decode, shade, alpha 1
+ * over the background; empty and opaque pixels show the background). */
+int orc_resolve_gbuf(const uint64_t *vis, const float *cams, uint32_t n_scenes, int width,
+                     int height, const orc_shade_params *sp, double *out_rgba)
+{
+    size_t npix = (size_t)width * height;
+    for (uint32_t s = 0; s < n_scenes; ++s) {
+        const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)s);
+        const uint64_t *g = vis + (size_t)s * 2 * npix;
+        for (int j = 0; j < height; ++j)
+            for (int i = 0; i < width; ++i) {
+                size_t p = (size_t)j * width + i;
+                double *o = out_rgba + ((size_t)s * npix + p) * 4;
+                if (!orc_is_hit(g[p])) {
+                    o[0] = sp->bg[0]; o[1] = sp->bg[1]; o[2] = sp->bg[2]; o[3] = 0.0;
+                    continue;
+                }
+                v3d X, T;
+                double alb[3], ao;
+                orc_gbuf_decode(c, g[p], i + 0.5, j + 0.5, &X, &T, alb, &ao);
+                orc_shade_point(c, sp, X, T, alb, 1.0, ao, o);
+                o[3] = 1.0;
+            }
+    }
     return 0;
 }

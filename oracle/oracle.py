@@ -85,6 +85,12 @@ def lib():
         L.orc_dom_shadow.restype = i32
         L.orc_dom_shadow.argtypes = [P, P, P, P, i32, i32, P, i32, i32, P, P, u32, u32, P, P,
                                      u32, ctypes.c_double, P]
+        L.orc_oct16_export.restype = u32
+        L.orc_oct16_export.argtypes = [P]
+        L.orc_raster_gbuf.restype = i32
+        L.orc_raster_gbuf.argtypes = [P, P, P, P, P, u32, i32, i32, f32, P, P]
+        L.orc_resolve_gbuf.restype = i32
+        L.orc_resolve_gbuf.argtypes = [P, P, u32, i32, i32, P, P]
         _lib = L
     return _lib
 
@@ -321,6 +327,38 @@ def resolve(pos_w, rgb, flags, vis, cams, width, height, rp, mode=0, bg=(0.0, 0.
     if rc != 0:
         raise ValueError(f"oracle resolve failed ({rc})")
     return (out, cc) if want_center else out
+
+
+# ----------------------------------------------------------------- compressed G-buffer
+def oct16(t) -> int:
+    """16-bit octahedral code (u << 8 | v) of a binary32 direction."""
+    return int(lib().orc_oct16_export(_p(_c(t, np.float32))))
+
+
+def raster_gbuf(pos_w, rgb, flags, scene_off, cams, width, height, r_min=0.0, scene_z=None):
+    """Visibility buffer [S][2][H][W] whose keys carry the compressed shading
+    payload (depth << 40 | tangent, albedo, AO) instead of the segment id."""
+    cams = _c(cams, np.float32).reshape(-1, 18)
+    S = cams.shape[0]
+    vis = np.zeros((S, 2, height, width), np.uint64)
+    sz = None if scene_z is None else _c(scene_z, np.float32)
+    rc = lib().orc_raster_gbuf(_p(_c(pos_w, np.float32)), _p(_c(rgb, np.float32)),
+                               _p(_c(flags, np.uint8)), _p(_c(scene_off, np.uint32)), _p(cams),
+                               S, width, height, r_min, _p(sz), _p(vis))
+    if rc != 0:
+        raise MemoryError("oracle G-buffer raster failed")
+    return vis
+
+
+def resolve_gbuf(vis, cams, width, height, rp, bg=(0.0, 0.0, 0.0)):
+    """Centre-only resolve of a G-buffer visibility buffer: RGBA [S][H][W][4]."""
+    cams = _c(cams, np.float32).reshape(-1, 18)
+    S = cams.shape[0]
+    out = np.zeros((S, height, width, 4), np.float64)
+    sp = _shade_struct(rp, 2, bg)
+    lib().orc_resolve_gbuf(_p(_c(vis, np.uint64)), _p(cams), S, width, height, ctypes.byref(sp),
+                           _p(out))
+    return out
 
 
 # ----------------------------------------------------------------- soft coverage (binary64)
