@@ -291,6 +291,36 @@ def extra_fused(steps):
     return r
 
 
+def extra_gbuffer(steps):
+    """Compressed G-buffer keys against segment-id keys on the 1080p head: the
+    raster call, the centre resolve (decode vs gather) and the frame."""
+    import torch
+    from paper_2607_04230_amd import hm, scenes
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_head()
+    r = {}
+    for name, gb in (("segment", False), ("gbuffer", True)):
+        ds = DeviceScene(sc, mode=hm.RESOLVE_CENTER)
+        if gb:
+            ds.use_gbuffer()
+        ds.render()
+        torch.cuda.synchronize()
+        r[name] = {"raster_ms": _time_ms(ds.raster, steps, 2),
+                   "center_resolve_ms": _time_ms(ds.resolve, steps, 2),
+                   "frame_ms": _time_ms(ds.render, steps, 2)}
+        hm.timing_enable(True)
+        hm.timing_collect()
+        for _ in range(steps):
+            ds.render()
+        torch.cuda.synchronize()
+        t = hm.timing_collect()
+        hm.timing_enable(False)
+        r[name]["kernel_ms"] = {k: v[0] / max(v[1], 1) for k, v in sorted(t.items())}
+        del ds
+        torch.cuda.empty_cache()
+    return r
+
+
 def extra_shadow(steps):
     """Deep-opacity-map shadows on the 1080p head: light-view raster, layer
     counts and per-pixel lookup (with the LOD depth correction), and the
@@ -459,7 +489,8 @@ def main():
         del ds
         torch.cuda.empty_cache()
         for name, fn in (("lod", extra_lod), ("batched", extra_batched), ("diff", extra_diff),
-                         ("shadow", extra_shadow), ("fused", extra_fused)):
+                         ("shadow", extra_shadow), ("fused", extra_fused),
+                         ("gbuffer", extra_gbuffer)):
             print(f"[bench] extra workload: {name}", file=sys.stderr, flush=True)
             line[name] = fn(max(args.steps // 2, 5))
     if not args.no_cpu:

@@ -184,6 +184,23 @@ hm_status hm_generate_raster(const hm_hair_mesh *mesh, const uint32_t *table,
  * HM_RASTER_TILED_ROWS: screen tiles, each lane walks whole pixel rows. */
 enum { HM_RASTER_TILED = 0, HM_RASTER_DIRECT = 1, HM_RASTER_TILED_ROWS = 2 };
 
+/* Low 40 bits of a visibility key.
+ * HM_PAYLOAD_SEGMENT: the segment id (the stream index of its first point).
+ * HM_PAYLOAD_GBUFFER: the paper's compressed deferred-shading data (Sec.
+ *   3.1.2, deferred atomic shading) at the covered point: bits 39..24 the
+ *   octahedral code of the tangent (u, v: 8 bits each, each component
+ *   rounded from (c + 1) / 2 * 255), bits 23..6 the albedo r, g, b (6 bits
+ *   each, rounded from c * 63), bits 5..0 the ambient occlusion (63: none
+ *   baked).  Tangent and albedo are the control points' values interpolated
+ *   at the perspective-correct segment parameter t3 = ts * (1/z_1) * z of the
+ *   closest point (ts) at depth z; the control-point tangent is the resolve's
+ *   (central difference, one-sided at root and tip).  The position is not
+ *   stored: the resolve rebuilds it from the depth code at the pixel centre.
+ *   Depth bits, coverage and the opaque prefill are those of SEGMENT keys;
+ *   equal depths break ties by payload.  Needs shared_views = 0 and
+ *   strands.rgb. */
+enum { HM_PAYLOAD_SEGMENT = 0, HM_PAYLOAD_GBUFFER = 1 };
+
 typedef struct {
     float r_min;              /* minimum coverage half width (px): the centre sample's
                                  "configurable diameter" / 2 (Sec. 3.1.2); 0 = exact width */
@@ -199,6 +216,7 @@ typedef struct {
     uint32_t shared_views;    /* 0: scene s draws its own stream range scene_off[s..s+1];
                                  1: multiview -- one stream (strands.n_scenes = 1) drawn
                                  into every scene of the frame, each with its camera */
+    uint32_t payload;         /* HM_PAYLOAD_SEGMENT (default) or HM_PAYLOAD_GBUFFER */
 } hm_raster_params;
 
 /* Visibility buffer (Sec. 3.1.2).  vis[s][0] = centre-sample layer,
@@ -242,6 +260,13 @@ typedef struct {
                               transmittance at each pixel's shaded point (from
                               hm_dom_shadow); scales the diffuse and specular
                               terms of the centre shading.  NULL: unshadowed */
+    int32_t payload;       /* what vis holds: HM_PAYLOAD_SEGMENT, or HM_PAYLOAD_GBUFFER
+                              (CENTER mode only, no shadow): each centre-hit pixel is
+                              shaded from its decoded key -- position rebuilt at the
+                              pixel centre from the middle of its depth code's
+                              interval, unit tangent from the octahedral code,
+                              albedo and AO (which scales the ambient term) from
+                              their 6-bit codes -- with no read of the stream */
 } hm_shade_params;
 
 /* Deferred resolve, out_rgba[S][height][width][4] float (straight colour

@@ -147,6 +147,10 @@ static hm_status check_raster_params(const hm_raster_params *p)
             "block must be a multiple of 64 in [64, 1024]");
     REQUIRE(p->grid <= 65536, HM_ERR_RANGE, "grid outside [0, 65536]");
     REQUIRE(p->shared_views <= 1, HM_ERR_INVALID, "shared_views must be 0 or 1");
+    REQUIRE(p->payload == HM_PAYLOAD_SEGMENT || p->payload == HM_PAYLOAD_GBUFFER,
+            HM_ERR_INVALID, "unknown payload %u", p->payload);
+    REQUIRE(p->payload == HM_PAYLOAD_SEGMENT || !p->shared_views, HM_ERR_INVALID,
+            "G-buffer keys need shared_views = 0");
     REQUIRE(p->algo != HM_RASTER_TILED || p->block <= 256, HM_ERR_RANGE,
             "HM_RASTER_TILED takes at most 256 threads per workgroup (got %u)", p->block);
     REQUIRE(p->algo == HM_RASTER_DIRECT || raster_lds_bytes(*p) <= 65536u, HM_ERR_RANGE,
@@ -203,6 +207,11 @@ static hm_status make_shade(const hm_shade_params *p, ShadeK &k)
     REQUIRE(!p->shadow || p->mode != HM_RESOLVE_SOFT, HM_ERR_INVALID,
             "shadow applies to the FILTER and CENTER resolves only");
     k.shadow = p->shadow;
+    REQUIRE(p->payload == HM_PAYLOAD_SEGMENT || p->payload == HM_PAYLOAD_GBUFFER,
+            HM_ERR_INVALID, "unknown payload %d", p->payload);
+    REQUIRE(p->payload == HM_PAYLOAD_SEGMENT || (p->mode == HM_RESOLVE_CENTER && !p->shadow),
+            HM_ERR_INVALID, "G-buffer keys resolve in CENTER mode only, without shadow");
+    k.payload = p->payload;
     return HM_OK;
 }
 

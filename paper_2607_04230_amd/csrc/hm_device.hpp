@@ -140,8 +140,22 @@ __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
 // Coverage of pixel (i, j): `centre` (centre sample) and `cons`
 // (conservative); q gets the depth code at the clamped closest point.  Returns
 // centre || cons.
+__device__ __forceinline__ bool cover_tz(const Seg &s, int i, int j, float r_min, float zn,
+                                         float inv_range, bool &centre, bool &cons, uint32_t &q,
+                                         float &ts_out, float &z_out);
+
 __device__ __forceinline__ bool cover(const Seg &s, int i, int j, float r_min, float zn,
                                       float inv_range, bool &centre, bool &cons, uint32_t &q)
+{
+    float ts, z;
+    return cover_tz(s, i, j, r_min, zn, inv_range, centre, cons, q, ts, z);
+}
+
+// As cover; also returns the clamped closest-point parameter ts and the linear
+// depth z of the depth code.
+__device__ __forceinline__ bool cover_tz(const Seg &s, int i, int j, float r_min, float zn,
+                                         float inv_range, bool &centre, bool &cons, uint32_t &q,
+                                         float &ts_out, float &z_out)
 {
     // Evaluated without branches except for the rare degenerate segment: the
     // two tests, the closest point and the depth code are computed for every
@@ -178,8 +192,75 @@ __device__ __forceinline__ bool cover(const Seg &s, int i, int j, float r_min, f
     const float iz = s.iz0 + ts * s.diz;
     const float z = 1.0f / iz;
     q = depth_code(z, zn, inv_range);
+    ts_out = ts;
+    z_out = z;
     return centre | cons;
 }
+
+// ----------------------------------------------------------------- compressed G-buffer
+// The 64-bit deferred-shading word of Sec. 3.1.2: depth code << 40, then
+// octahedral tangent (u, v: 8 bits each), albedo r, g, b (6 bits each) and
+// ambient occlusion (6 bits, 63: none baked).  Quantisation rounds to
+// nearest; every step is binary32 in the order written.
+__device__ __forceinline__ uint32_t gb_q8(float x)
+{
+    float f = (x * 0.5f + 0.5f) * 255.0f + 0.5f;
+    f = f > 0.0f ? f : 0.0f;
+    f = f < 255.0f ? f : 255.0f;
+    return (uint32_t)f;
+}
+
+__device__ __forceinline__ uint32_t gb_q6(float c)
+{
+    float f = c * 63.0f + 0.5f;
+    f = f > 0.0f ? f : 0.0f;
+    f = f < 63.0f ? f : 63.0f;
+    return (uint32_t)f;
+}
+
+// Octahedral map: project onto |x| + |y| + |z| = 1, fold the lower half
+// (z < 0) across the diagonals, keep (x, y); the zero vector maps to the centre.
+__device__ __forceinline__ uint32_t gb_oct16(float tx, float ty, float tz)
+{
+    const float l1 = (fabsf(tx) + fabsf(ty)) + fabsf(tz);
+    float px = 0.0f, py = 0.0f;
+    if (l1 > 0.0f) {
+        px = tx / l1;
+        py = ty / l1;
+        if (tz < 0.0f) {
+            const float ax = fabsf(px), ay = fabsf(py);
+            const float sx = px >= 0.0f ? 1.0f : -1.0f, sy = py >= 0.0f ? 1.0f : -1.0f;
+            px = (1.0f - ay) * sx;
+            py = (1.0f - ax) * sy;
+        }
+    }
+    return (gb_q8(px) << 8) | gb_q8(py);
+}
+
+// Payload of segment v (stream point v) at closest-point parameter ts and
+// linear depth z: the perspective-correct segment parameter
+// t3 = ts * (1/z_1) * z, then tangent and albedo interpolated at t3.
+__device__ __forceinline__ uint64_t gb_payload(const float4 *tan, const float4 *rgb, uint32_t v,
+                                               float ts, float z, float iz1)
+{
+    const float t3 = (ts * iz1) * z;
+    const float4 T0 = tan[v], T1 = tan[v + 1];
+    const float4 c0 = rgb[v], c1 = rgb[v + 1];
+    const float tx = T0.x + t3 * (T1.x - T0.x);
+    const float ty = T0.y + t3 * (T1.y - T0.y);
+    const float tz = T0.z + t3 * (T1.z - T0.z);
+    const float cr = c0.x + t3 * (c1.x - c0.x);
+    const float cg = c0.y + t3 * (c1.y - c0.y);
+    const float cb = c0.z + t3 * (c1.z - c0.z);
+    return ((uint64_t)gb_oct16(tx, ty, tz) << 24) | ((uint64_t)gb_q6(cr) << 18) |
+           ((uint64_t)gb_q6(cg) << 12) | ((uint64_t)gb_q6(cb) << 6) | 63u;
+}
+
+// Raster-side inputs of the G-buffer keys (null tan: segment-id keys).
+struct GbK {
+    const float4 *tan;      // unit tangent per control point
+    const float4 *rgb;      // albedo per control point
+};
 
 // Candidate pixel box of a segment (superset of every pixel either predicate
 // can accept), clipped to the image.  Returns false if empty.

@@ -26,6 +26,7 @@ struct ShadeK {
     float bgr, bgg, bgb;
     int mode;
     const float *shadow;       // light transmittance per pixel, or nullptr
+    int payload;               // HM_PAYLOAD_SEGMENT or HM_PAYLOAD_GBUFFER keys
 };
 
 size_t align_up(size_t x, size_t a = 256);

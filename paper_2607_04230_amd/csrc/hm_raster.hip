@@ -134,10 +134,11 @@ __device__ __forceinline__ void scene_depth_consts(const hm_camera *cams, uint32
 }
 
 // ------------------------------------------------------------------ direct path
+template <bool GB>
 __global__ __launch_bounds__(256) void k_raster_direct(const float4 *proj, const uint8_t *flags,
                                                        const uint32_t *scene_off,
                                                        const hm_camera *cams, RasterK rk,
-                                                       uint32_t cap, uint64_t *vis)
+                                                       uint32_t cap, uint64_t *vis, GbK gk)
 {
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
@@ -161,14 +162,47 @@ __global__ __launch_bounds__(256) void k_raster_direct(const float4 *proj, const
             for (int i = a0; i <= a1; ++i) {
                 uint32_t q;
                 bool cc, ca;
-                const bool msk = cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                float ts, z;
+                const bool msk = cover_tz(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q, ts, z);
                 if (!msk) continue;
-                const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
+                const uint64_t low =
+                    GB ? gb_payload(gk.tan, gk.rgb, v, ts, z, sg.iz0 + sg.diz) : (uint64_t)v;
+                const uint64_t key = ((uint64_t)q << HM_ID_BITS) | low;
                 const size_t p = (size_t)j * rk.W + i;
                 if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
                 if (ca) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
             }
         }
+    }
+}
+
+// ------------------------------------------------------------------ G-buffer tangents
+// Unit tangent of every stream point for the compressed G-buffer keys, as the
+// resolve computes it: root -> next, tip <- previous, else the central
+// difference; zero for a point that is both root and tip (no segment).
+__global__ __launch_bounds__(256) void k_cp_tangent(const float4 *pos, const uint8_t *flags,
+                                                    const uint32_t *scene_off, RasterK rk,
+                                                    uint32_t cap, float4 *tan)
+{
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n;
+         v += gridDim.x * blockDim.x) {
+        const uint8_t f = flags[v];
+        float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+        if (!((f & HM_ROOT) && (f & HM_TIP))) {
+            const float4 a = (f & HM_ROOT) ? pos[v] : pos[v - 1];
+            const float4 b = (f & HM_TIP) ? pos[v] : pos[v + 1];
+            dx = b.x - a.x;
+            dy = b.y - a.y;
+            dz = b.z - a.z;
+        }
+        const float n2 = (dx * dx + dy * dy) + dz * dz;
+        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (n2 > 0.0f) {
+            const float inv = 1.0f / sqrtf(n2);
+            t = make_float4(dx * inv, dy * inv, dz * inv, 0.0f);
+        }
+        tan[v] = t;
     }
 }
 
@@ -578,12 +612,12 @@ __device__ __forceinline__ void dom_count(uint32_t *cnt, const uint32_t *q0t, ui
     atomicAdd(&cnt[k * TT + x], 1u);
 }
 
-template <bool FLAT, uint32_t NBC, bool DOM>
+template <bool FLAT, uint32_t NBC, bool DOM, bool GB>
 __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
                                uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
                                const uint32_t *entries, uint32_t *counters, uint64_t *vis,
-                               DomK dk)
+                               DomK dk, GbK gk)
 {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t sh_item;
@@ -757,14 +791,20 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                 const Seg sp = rec_load(rf, nb, ow);
                                 uint32_t q;
                                 bool cc, ca;
-                                const bool msk = cover(sp, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                                float ts, z;
+                                const bool msk = cover_tz(sp, i, j, rk.r_min, zn, inv_range, cc,
+                                                          ca, q, ts, z);
                                 const uint32_t x =
                                     (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
                                 if (DOM) {
                                     if (ca) dom_count(cnt, q0t, x, TT, q, dk);
                                 } else if (msk) {
+                                    const uint64_t low =
+                                        GB ? gb_payload(gk.tan, gk.rgb, r_sid[ow], ts, z,
+                                                        sp.iz0 + sp.diz)
+                                           : (uint64_t)r_sid[ow];
                                     const unsigned long long key =
-                                        ((unsigned long long)q << HM_ID_BITS) | r_sid[ow];
+                                        ((unsigned long long)q << HM_ID_BITS) | low;
                                     if (cc) atomicMin((unsigned long long *)&lc[x], key);
                                     if (ca) atomicMin((unsigned long long *)&la[x], key);
                                 }
@@ -807,14 +847,19 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     for (int i = a0; i <= a1; ++i) {
                         uint32_t q;
                         bool cc, ca;
-                        const bool msk = cover(sr, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                        float ts, z;
+                        const bool msk =
+                            cover_tz(sr, i, j, rk.r_min, zn, inv_range, cc, ca, q, ts, z);
                         const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
                         if (DOM) {
                             if (ca) dom_count(cnt, q0t, x, TT, q, dk);
                             continue;
                         }
                         if (!msk) continue;
-                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | vo;
+                        const uint64_t low =
+                            GB ? gb_payload(gk.tan, gk.rgb, vo, ts, z, sr.iz0 + sr.diz)
+                               : (uint64_t)vo;
+                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
                         if (cc) atomicMin((unsigned long long *)&lc[x], key);
                         if (ca) atomicMin((unsigned long long *)&la[x], key);
                     }
@@ -849,13 +894,13 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
 
 // One wave per long segment: lanes stride over its candidate rows (DOM: the
 // counting pass, one global add per accepted conservative pair).
-template <bool DOM>
+template <bool DOM, bool GB>
 __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const uint8_t *flags,
                                                      const uint32_t *scene_off,
                                                      const hm_camera *cams, RasterK rk,
                                                      uint32_t cap, const uint32_t *long_list,
                                                      const uint32_t *counters, uint64_t *vis,
-                                                     DomK dk)
+                                                     DomK dk, GbK gk)
 {
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_long = counters[0];
@@ -882,7 +927,8 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
             for (int i = a0; i <= a1; ++i) {
                 uint32_t q;
                 bool cc, ca;
-                const bool msk = cover(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q);
+                float ts, z;
+                const bool msk = cover_tz(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q, ts, z);
                 const size_t p = (size_t)j * rk.W + i;
                 if (DOM) {
                     if (!ca) continue;
@@ -893,7 +939,9 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
                     continue;
                 }
                 if (!msk) continue;
-                const uint64_t key = ((uint64_t)q << HM_ID_BITS) | v;
+                const uint64_t low =
+                    GB ? gb_payload(gk.tan, gk.rgb, v, ts, z, sg.iz0 + sg.diz) : (uint64_t)v;
+                const uint64_t key = ((uint64_t)q << HM_ID_BITS) | low;
                 if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
                 if (ca) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
             }
@@ -944,6 +992,7 @@ struct RasterWs {
     uint32_t *counters;   // [0] long count, [1] work counter
     uint32_t *long_list;  // cap
     uint32_t *entries;    // cap * K
+    float4 *tan;          // G-buffer keys: unit tangent per stream point (else null)
     uint2 *segrec;        // per unit: first tile of its box, box width | tile mask << 8
     uint32_t *saved;      // per binning span: its LDS table (keys, counts)
     uint32_t nsub;        // segments per thread and span
@@ -977,6 +1026,7 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
     w.items = (uint32_t *)take(sizeof(uint32_t) * (nt + 1));
     w.partials = (uint32_t *)take(sizeof(uint32_t) * (scan_blocks((uint32_t)nt) + 1));
     w.counters = (uint32_t *)take(sizeof(uint32_t) * 64);
+    w.tan = p.payload == HM_PAYLOAD_GBUFFER ? (float4 *)take(sizeof(float4) * (size_t)cap) : nullptr;
     if (p.algo != HM_RASTER_DIRECT) {
         w.long_list = (uint32_t *)take(sizeof(uint32_t) * units);
         w.entries = (uint32_t *)take(sizeof(uint32_t) * units * p.max_tiles_per_seg);
@@ -1016,6 +1066,7 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.block = 256;
     p.grid = 0;
     p.shared_views = 0;
+    p.payload = HM_PAYLOAD_SEGMENT;
 }
 
 void launch_prefill(uint64_t *vis, const float *scene_z, const hm_camera *cams,
@@ -1040,12 +1091,22 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                        tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
     const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
     const size_t units = (size_t)s.cap * units_per_cp(f, p);
+    const bool gbuf = p.payload == HM_PAYLOAD_GBUFFER;
+    const GbK gk{w.tan, reinterpret_cast<const float4 *>(s.rgb)};
+    if (gbuf)
+        hipLaunchKernelGGL(k_cp_tangent, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st, pos,
+                           (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tan);
     if (p.algo == HM_RASTER_DIRECT) {
         hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
                            s.scene_off, rk, cams, s.cap, w.proj);
-        hipLaunchKernelGGL(k_raster_direct, dim3(stride_grid(units, 256)), dim3(256), 0, st,
-                           (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
-                           rk, s.cap, vis);
+        if (gbuf)
+            hipLaunchKernelGGL(k_raster_direct<true>, dim3(stride_grid(units, 256)), dim3(256), 0,
+                               st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off,
+                               cams, rk, s.cap, vis, gk);
+        else
+            hipLaunchKernelGGL(k_raster_direct<false>, dim3(stride_grid(units, 256)), dim3(256),
+                               0, st, (const float4 *)w.proj, (const uint8_t *)s.flags,
+                               s.scene_off, cams, rk, s.cap, vis, gk);
         return;
     }
     // pass 0 of the binning also writes every unit's screen record
@@ -1072,25 +1133,39 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
-#define HM_TILES_LAUNCH(FL, NB)                                                                \
-    hipLaunchKernelGGL((k_raster_tiles<FL, NB, false>), dim3(grid), dim3(p.block), lds, st,      \
+#define HM_TILES_LAUNCH(FL, NB, GB)                                                            \
+    hipLaunchKernelGGL((k_raster_tiles<FL, NB, false, GB>), dim3(grid), dim3(p.block), lds, st,  \
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,  \
                        s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,          \
-                       (const uint32_t *)w.entries, w.counters, vis, DomK{nullptr, 1u, 1u})
-    if (p.algo == HM_RASTER_TILED) {
-        if (p.block == 256) HM_TILES_LAUNCH(true, 256);
-        else if (p.block == 128) HM_TILES_LAUNCH(true, 128);
-        else HM_TILES_LAUNCH(true, 0);
+                       (const uint32_t *)w.entries, w.counters, vis, DomK{nullptr, 1u, 1u}, gk)
+    if (gbuf) {
+        // G-buffer keys: the default shape compiled for its block size, others generic
+        if (p.algo == HM_RASTER_TILED) {
+            if (p.block == 256) HM_TILES_LAUNCH(true, 256, true);
+            else HM_TILES_LAUNCH(true, 0, true);
+        } else {
+            HM_TILES_LAUNCH(false, 0, true);
+        }
+    } else if (p.algo == HM_RASTER_TILED) {
+        if (p.block == 256) HM_TILES_LAUNCH(true, 256, false);
+        else if (p.block == 128) HM_TILES_LAUNCH(true, 128, false);
+        else HM_TILES_LAUNCH(true, 0, false);
     } else {
-        if (p.block == 512) HM_TILES_LAUNCH(false, 512);
-        else if (p.block == 256) HM_TILES_LAUNCH(false, 256);
-        else HM_TILES_LAUNCH(false, 0);
+        if (p.block == 512) HM_TILES_LAUNCH(false, 512, false);
+        else if (p.block == 256) HM_TILES_LAUNCH(false, 256, false);
+        else HM_TILES_LAUNCH(false, 0, false);
     }
 #undef HM_TILES_LAUNCH
-    hipLaunchKernelGGL(k_raster_long<false>, dim3(256), dim3(256), 0, st,
-                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,
-                       s.cap, (const uint32_t *)w.long_list, (const uint32_t *)w.counters, vis,
-                       DomK{nullptr, 1u, 1u});
+    if (gbuf)
+        hipLaunchKernelGGL((k_raster_long<false, true>), dim3(256), dim3(256), 0, st,
+                           (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
+                           rk, s.cap, (const uint32_t *)w.long_list, (const uint32_t *)w.counters,
+                           vis, DomK{nullptr, 1u, 1u}, gk);
+    else
+        hipLaunchKernelGGL((k_raster_long<false, false>), dim3(256), dim3(256), 0, st,
+                           (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
+                           rk, s.cap, (const uint32_t *)w.long_list, (const uint32_t *)w.counters,
+                           vis, DomK{nullptr, 1u, 1u}, gk);
 }
 
 }  // namespace hm
@@ -1139,14 +1214,15 @@ void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_
     const uint32_t TT = rp.tile * rp.tile;
     const uint32_t lds = tile_lds_bytes(rp.tile, rp.block, true) - 4u * TT * 4u +
                          tile_words(TT, true, p.n_layers) * 4u;
-    hipLaunchKernelGGL((k_raster_tiles<true, 256, true>), dim3(256u * 8u), dim3(256), lds, st,
+    hipLaunchKernelGGL((k_raster_tiles<true, 256, true, false>), dim3(256u * 8u), dim3(256), lds,
+                       st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light,
+                       rk, s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
+                       (const uint32_t *)w.entries, w.counters, light_vis, dk,
+                       GbK{nullptr, nullptr});
+    hipLaunchKernelGGL((k_raster_long<true, false>), dim3(256), dim3(256), 0, st,
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light, rk,
-                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
-                       (const uint32_t *)w.entries, w.counters, light_vis, dk);
-    hipLaunchKernelGGL(k_raster_long<true>, dim3(256), dim3(256), 0, st, (const float4 *)w.proj,
-                       (const uint8_t *)s.flags, s.scene_off, light, rk, s.cap,
-                       (const uint32_t *)w.long_list, (const uint32_t *)w.counters, light_vis,
-                       dk);
+                       s.cap, (const uint32_t *)w.long_list, (const uint32_t *)w.counters,
+                       light_vis, dk, GbK{nullptr, nullptr});
 }
 
 }  // namespace hm

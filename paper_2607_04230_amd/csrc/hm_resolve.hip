@@ -95,7 +95,7 @@ __device__ __forceinline__ SegShade seg_shade_point(const float4 *pos, const flo
 // Kajiya-Kay style diffuse sin(T, L) plus a specular lobe (1 - (T.H)^2)^(2^n);
 // sh (the light's transmittance) scales both direct terms, not the ambient one.
 __device__ __forceinline__ V3 shade(const SegShade &g, const Cam &c, const ShadeK &k,
-                                    float sh = 1.0f)
+                                    float sh = 1.0f, float ao = 1.0f)
 {
     const V3 L = v3(k.Lx, k.Ly, k.Lz);
     const V3 V = nrm(v3(c.ex, c.ey, c.ez) - g.X);
@@ -105,7 +105,7 @@ __device__ __forceinline__ V3 shade(const SegShade &g, const Cam &c, const Shade
     const float diff = sd > 0.0f ? sqrtf(sd) : 0.0f;
     float sp = fmaxx(1.0f - th * th, 0.0f);
     for (int i = 0; i < k.nsq; ++i) sp = sp * sp;
-    const float dd = k.ka + (sh * k.kd) * diff;
+    const float dd = k.ka * ao + (sh * k.kd) * diff;
     const float ks = sh * k.ks;
     return v3(g.alb.x * k.Er * dd + ks * k.Er * sp, g.alb.y * k.Eg * dd + ks * k.Eg * sp,
               g.alb.z * k.Eb * dd + ks * k.Eb * sp);
@@ -142,6 +142,59 @@ __global__ __launch_bounds__(256) void k_shade(const float4 *pos, const float4 *
             out[p] = hc ? make_float4(col.x, col.y, col.z, 1.0f)
                         : make_float4(k.bgr, k.bgg, k.bgb, 0.0f);
         }
+    }
+}
+
+// ------------------------------------------------------------------ G-buffer shading
+// Centre resolve of a buffer of compressed keys: each centre-hit pixel is
+// shaded from its key alone (no stream read): position rebuilt at the pixel
+// centre from the middle of its depth code's interval (binary64), unit
+// tangent from the octahedral code (unfold the lower half, normalise),
+// albedo and occlusion from their 6-bit codes.
+__global__ __launch_bounds__(256) void k_shade_gbuf(const uint64_t *vis, const hm_camera *cams,
+                                                    uint32_t S, uint32_t W, uint32_t H, ShadeK k,
+                                                    float4 *out)
+{
+    const size_t hw = (size_t)W * H;
+    const size_t n = hw * S;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
+         p += (size_t)gridDim.x * blockDim.x) {
+        const uint32_t s = (uint32_t)(p / hw);
+        const size_t loc = p - (size_t)s * hw;
+        const uint64_t kc = vis[(size_t)s * 2 * hw + loc];
+        float4 o = make_float4(k.bgr, k.bgg, k.bgb, 0.0f);
+        if (is_hit(kc)) {
+            const hm_camera *cp = cams + s;
+            const Cam c = load_cam(cp);
+            const uint64_t w = kc & HM_ID_MASK;
+            const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
+            const double px = (double)i + 0.5, py = (double)j + 0.5;
+            const double zn = cp->znear, zf = cp->zfar;
+            const double z = zn + ((double)(kc >> HM_ID_BITS) + 0.5) / 16777216.0 * (zf - zn);
+            const double xc = (px - (double)cp->cx) * z / (double)cp->fx;
+            const double yc = -(py - (double)cp->cy) * z / (double)cp->fy;
+            const double R[9] = {cp->R[0], cp->R[1], cp->R[2], cp->R[3], cp->R[4],
+                                 cp->R[5], cp->R[6], cp->R[7], cp->R[8]};
+            SegShade g;
+            g.X = v3((float)((double)cp->eye[0] + (R[0] * xc + R[3] * yc + R[6] * z)),
+                     (float)((double)cp->eye[1] + (R[1] * xc + R[4] * yc + R[7] * z)),
+                     (float)((double)cp->eye[2] + (R[2] * xc + R[5] * yc + R[8] * z)));
+            float u = (float)((w >> 32) & 0xFFu) / 255.0f * 2.0f - 1.0f;
+            float v = (float)((w >> 24) & 0xFFu) / 255.0f * 2.0f - 1.0f;
+            const float tz = (1.0f - fabsf(u)) - fabsf(v);
+            if (tz < 0.0f) {
+                const float au = fabsf(u), av = fabsf(v);
+                u = (1.0f - av) * (u >= 0.0f ? 1.0f : -1.0f);
+                v = (1.0f - au) * (v >= 0.0f ? 1.0f : -1.0f);
+            }
+            g.T = nrm(v3(u, v, tz));
+            g.alb = v3((float)((w >> 18) & 63u) / 63.0f, (float)((w >> 12) & 63u) / 63.0f,
+                       (float)((w >> 6) & 63u) / 63.0f);
+            const float ao = (float)(w & 63u) / 63.0f;
+            const V3 col = shade(g, c, k, 1.0f, ao);
+            o = make_float4(col.x, col.y, col.z, 1.0f);
+        }
+        out[p] = o;
     }
 }
 
@@ -416,6 +469,11 @@ void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *c
         hipLaunchKernelGGL(k_soft, dim3(stride_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
                            (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k,
                            o);
+        return;
+    }
+    if (k.payload == HM_PAYLOAD_GBUFFER) {
+        hipLaunchKernelGGL(k_shade_gbuf, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis,
+                           cams, f.n_scenes, f.width, f.height, k, o);
         return;
     }
     if (k.mode == HM_RESOLVE_CENTER) {

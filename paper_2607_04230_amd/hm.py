@@ -20,6 +20,7 @@ HM_OK = 0
 LOD_OFF, LOD_ON = 0, 1
 RASTER_TILED, RASTER_DIRECT, RASTER_TILED_ROWS = 0, 1, 2
 RESOLVE_FILTER, RESOLVE_SOFT, RESOLVE_CENTER = 0, 1, 2
+PAYLOAD_SEGMENT, PAYLOAD_GBUFFER = 0, 1
 CALL_LOD, CALL_RASTER, CALL_RESOLVE, CALL_DOM = 0, 1, 2, 3
 
 _u32, _i32, _f32, _vp, _sz = ctypes.c_uint32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
@@ -57,7 +58,7 @@ class GenParams(ctypes.Structure):
 class RasterParams(ctypes.Structure):
     _fields_ = [("r_min", _f32), ("algo", _i32), ("tile", _u32), ("chunk", _u32),
                 ("max_tiles_per_seg", _u32), ("block", _u32), ("grid", _u32),
-                ("shared_views", _u32)]
+                ("shared_views", _u32), ("payload", _u32)]
 
 
 class ShadeParams(ctypes.Structure):
@@ -65,7 +66,8 @@ class ShadeParams(ctypes.Structure):
                 ("ks", _f32), ("spec_squarings", _i32), ("filter_radius", _i32), ("s_par", _f32),
                 ("s_perp", _f32), ("sigma_c", _f32), ("iso_scale", _f32), ("depth_reject", _f32),
                 ("depth_mismatch", _f32), ("strip_half", _f32), ("iso_len", _f32),
-                ("soft_sigma", _f32), ("bg", _f32 * 3), ("mode", _i32), ("shadow", _vp)]
+                ("soft_sigma", _f32), ("bg", _f32 * 3), ("mode", _i32), ("shadow", _vp),
+                ("payload", _i32)]
 
 
 class DomParams(ctypes.Structure):

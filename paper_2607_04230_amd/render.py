@@ -89,6 +89,18 @@ class DeviceScene:
         hm.raster_vis(self.st, self.cams, self.fr, self.rparams, self.scene_z, self.vis,
                       self.ws_raster)
 
+    def use_gbuffer(self, on: bool = True):
+        """Compressed G-buffer keys (depth | tangent, albedo, AO) instead of
+        segment ids; the resolve then shades each centre hit from its key
+        alone (centre mode)."""
+        rp = hm.RasterParams.from_buffer_copy(self.rparams)
+        rp.payload = hm.PAYLOAD_GBUFFER if on else hm.PAYLOAD_SEGMENT
+        self.set_raster_params(rp)
+        self.sp.payload = rp.payload
+        if on:
+            self.sp.mode = hm.RESOLVE_CENTER
+            self.mode = hm.RESOLVE_CENTER
+
     def generate_raster(self):
         """Generation and raster in one pass (fused, direct atomics)."""
         hm.generate_raster(self.mesh, self.table, self.strand_base, self.strand_rgb, self.gp,

@@ -121,6 +121,28 @@ def test_validation_errors_are_reported():
     assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
                                 ctypes.byref(st), dummy, ctypes.byref(fr), ctypes.c_float(-1.0),
                                 None, dummy, None) == 2
+    # compressed G-buffer keys: known payloads only, no shared views, CENTER resolve
+    rp = hm.raster_defaults(fr)
+    rp.payload = 2
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 10, ctypes.byref(rp),
+                               ctypes.byref(out)) == 1
+    rp.payload, rp.shared_views = hm.PAYLOAD_GBUFFER, 1
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 10, ctypes.byref(rp),
+                               ctypes.byref(out)) == 1
+    rp.shared_views = 0
+    a = ctypes.c_size_t()
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 1000, ctypes.byref(rp),
+                               ctypes.byref(a)) == 0
+    rp.payload = hm.PAYLOAD_SEGMENT
+    b = ctypes.c_size_t()
+    assert L.hm_workspace_size(hm.CALL_RASTER, ctypes.byref(fr), 0, 1000, ctypes.byref(rp),
+                               ctypes.byref(b)) == 0
+    assert a.value >= b.value + 16 * 1000          # per-point tangents
+    sp = hm.shade_params(ResolveParams(), hm.RESOLVE_FILTER)
+    sp.payload = hm.PAYLOAD_GBUFFER
+    assert L.hm_resolve_shade(ctypes.byref(st), dummy, dummy, ctypes.byref(fr), ctypes.byref(sp),
+                              dummy, dummy, 1 << 30, None) == 1
+    assert b"CENTER" in L.hm_last_error()
     # shadows: single scene, layer count and opacity ranges, workspace
     dp = hm.DomParams(64, 64, 4, 1000, 0.5, 0.05)
     ws = hm.workspace_size(hm.CALL_DOM, fr, cap=1000)
