@@ -2,12 +2,15 @@
 //
 // The paper dispatches one workgroup per strand indirectly from the LOD
 // buffer.  HIP has no indirect dispatch, so the LOD pass writes the per-bundle
-// counts, a device prefix sum turns them into offsets, and generation is a
-// grid-stride loop over control points (one thread per CP, coalesced 16-byte
-// stores) that locates its bundle by binary search in the offset table.  The
-// per-CP work (four bilinear layer points, two tangents, a Hermite step and
-// the curl) reads the bundle's mesh data from cache, so no shuffles or LDS
-// staging are needed to avoid redundant memory traffic.
+// counts and a device prefix sum turns them into offsets (the table of
+// {N_LOD, C, first strand, first CP}); generation then launches one
+// 256-thread workgroup per bundle that reads its (possibly zero) row of the
+// table.  A bundle's strand parameters, bilinear layer points and
+// finite-difference layer tangents are computed once into LDS per chunk of
+// strands; lanes then evaluate consecutive control points (Hermite + curl)
+// and store them coalesced.  The fused variant also projects each control
+// point and rasterizes the chunk's segments from LDS (the paper's
+// assembly-and-raster in one pass).
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
 #include "hm_scan.hpp"

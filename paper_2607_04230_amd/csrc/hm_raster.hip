@@ -5,20 +5,26 @@
 //   1. k_prefill writes both layers (empty or the opaque scene depth);
 //   2. each control point's screen record is computed once, by the first
 //      binning pass (or by k_project on the direct path);
-//   3. TILED path: k_bin counts, then scatters, segment ids into per-screen-
-//      tile lists (T x T pixels), with wave-level ballot aggregation of the
-//      list atomics; an exclusive scan turns counts into offsets and each tile
-//      is cut into work items of `chunk` segments;
+//   3. TILED path: k_bin pass 0 finds each segment's screen tiles (T x T
+//      pixels), stores them as an 8-byte record and counts (segment, tile)
+//      pairs in LDS tables flushed once per (span, tile); an exclusive scan
+//      turns counts into offsets and each tile is cut into work items of
+//      `chunk` segments; pass 1 walks the records and scatters the segment
+//      ids into the per-tile lists;
 //   4. k_raster_tiles is a persistent kernel: each workgroup pulls work items
 //      from a device counter, keeps the tile's two layers in LDS, resolves all
 //      coverage with LDS ds_min_u64, then merges the touched pixels into the
-//      global buffer with one 64-bit atomic min each;
-//   5. segments touching more than `max_tiles_per_seg` tiles go to a list
-//      rasterized by k_raster_long (one wave per segment, global atomics).
+//      global buffer with one 64-bit atomic min each (plain stores when the
+//      tile is a single work item);
+//   5. segments touching more than min(max_tiles_per_seg, 24) tiles go to a
+//      list rasterized by k_raster_long (one wave per segment, global atomics).
 // The DIRECT path (one thread per segment, global atomics everywhere) is kept
 // as the reference launch shape.  Every path evaluates the same binary32
 // predicates per pixel, and min is order-independent, so the buffer is
-// bit-identical across paths and tuning parameters.
+// bit-identical across paths and tuning parameters.  The same kernels also
+// build compressed G-buffer keys (depth | tangent, albedo, AO; k_cp_tangent
+// supplies the per-point tangents) and, for deep-opacity-map shadows, walk
+// a light view's work items a second time to count fragments per layer.
 #include <algorithm>
 
 #include "hm_device.hpp"

@@ -1,12 +1,15 @@
 // Deferred resolve (Sec. 3.3, 3.4, Code 2) for gfx950.
 //
-//   k_shade   one thread per pixel: shades the centre-sample hit once
-//             (deferred, 1 spp) and writes a 16-byte record
-//             {r, g, b, bits(depth24 | centre-hit << 24 | any-hit << 25)};
-//   k_filter  16 x 16 pixel workgroups stage the records of their tile plus
-//             an r-pixel halo in LDS and run strand connection, the elliptical
-//             bilateral filter and alpha estimation out of LDS;
-//   k_soft    soft-coverage resolve (one thread per pixel).
+//   k_shade       one thread per pixel: shades the centre-sample hit once
+//                 (deferred, 1 spp) and writes a 16-byte record
+//                 {r, g, b, bits(depth24 | centre-hit << 24 | any-hit << 25)};
+//   k_filter      16 x 16 pixel workgroups stage the records of their tile
+//                 plus an r-pixel halo in LDS and run strand connection, the
+//                 elliptical bilateral filter and alpha estimation out of LDS;
+//   k_shade_gbuf  centre shading of compressed G-buffer keys (decode only);
+//   k_soft        soft-coverage resolve (one thread per pixel), and
+//   k_soft_bwd    its binary64 backward, summed per 16 x 16 tile in LDS;
+//   k_dom_shadow  deep-opacity-map transmittance of each pixel's shaded point.
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
 
