@@ -566,10 +566,12 @@ __device__ __forceinline__ void atomic_add3(float *base, D3 g)
 struct SoftGrad {
     uint32_t v;
     bool root, tip;
-    D3 gP0, gP1, gPm, gPp;        // positions of v, v + 1, v - 1, v + 2
-    double g_ww0, g_ww1;          // widths of v, v + 1
-    D3 gc0, gc1;                  // colours of v, v + 1
+    float3 gP0, gP1, gPm, gPp;    // positions of v, v + 1, v - 1, v + 2
+    float g_ww0, g_ww1;           // widths of v, v + 1
+    float3 gc0, gc1;              // colours of v, v + 1
 };
+
+__device__ __forceinline__ float3 f3of(D3 a) { return make_float3((float)a.x, (float)a.y, (float)a.z); }
 
 __device__ __forceinline__ bool soft_bwd_pixel(const float4 *pos, const float4 *rgb,
                                                const uint8_t *flags, const uint64_t *vis,
@@ -705,9 +707,9 @@ __device__ __forceinline__ bool soft_bwd_pixel(const float4 *pos, const float4 *
     o.v = v;
     o.root = root;
     o.tip = tip;
-    o.gP0 = gP0; o.gP1 = gP1; o.gPm = gPm; o.gPp = gPp;
-    o.g_ww0 = g_ww0; o.g_ww1 = g_ww1;
-    o.gc0 = gc0; o.gc1 = gc1;
+    o.gP0 = f3of(gP0); o.gP1 = f3of(gP1); o.gPm = f3of(gPm); o.gPp = f3of(gPp);
+    o.g_ww0 = (float)g_ww0; o.g_ww1 = (float)g_ww1;
+    o.gc0 = f3of(gc0); o.gc1 = f3of(gc1);
     return true;
 }
 
@@ -716,8 +718,8 @@ __device__ __forceinline__ bool soft_bwd_pixel(const float4 *pos, const float4 *
 constexpr uint32_t BWD_SLOTS = 1024;      // >= 4 points x 256 pixels: never full
 constexpr uint32_t BWD_FREE = 0xFFFFFFFFu;
 
-__device__ __forceinline__ void bwd_add(uint32_t *keys, float *vals, uint32_t cp, D3 gp,
-                                        double gw, D3 gc)
+__device__ __forceinline__ void bwd_add(uint32_t *keys, float *vals, uint32_t cp, float3 gp,
+                                        float gw, float3 gc)
 {
     uint32_t sl = (cp * 2654435761u) >> 22;
     for (;;) {
@@ -726,8 +728,7 @@ __device__ __forceinline__ void bwd_add(uint32_t *keys, float *vals, uint32_t cp
         sl = (sl + 1u) & (BWD_SLOTS - 1u);
     }
     float *o = vals + sl * 8u;
-    const float g[7] = {(float)gp.x, (float)gp.y, (float)gp.z, (float)gw,
-                        (float)gc.x, (float)gc.y, (float)gc.z};
+    const float g[7] = {gp.x, gp.y, gp.z, gw, gc.x, gc.y, gc.z};
 #pragma unroll
     for (int q = 0; q < 7; ++q)
         if (g[q] != 0.0f) atomicAdd(o + q, g[q]);
@@ -736,7 +737,7 @@ __device__ __forceinline__ void bwd_add(uint32_t *keys, float *vals, uint32_t cp
 // One 16 x 16 pixel tile per workgroup iteration: every pixel's contributions
 // to the control points v - 1 .. v + 2 are summed in LDS (neighbouring pixels
 // mostly share segments), then added to the global gradients.
-__global__ __launch_bounds__(256) void k_soft_bwd(const float4 *pos, const float4 *rgb,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_soft_bwd(const float4 *pos, const float4 *rgb,
                                                   const uint8_t *flags, const uint64_t *vis,
                                                   const hm_camera *cams, uint32_t S, uint32_t W,
                                                   uint32_t H, ShadeK k, const float4 *dout,
@@ -761,8 +762,9 @@ __global__ __launch_bounds__(256) void k_soft_bwd(const float4 *pos, const float
                            g)) {
             bwd_add(keys, vals, g.v, g.gP0, g.g_ww0, g.gc0);
             bwd_add(keys, vals, g.v + 1u, g.gP1, g.g_ww1, g.gc1);
-            if (!g.root) bwd_add(keys, vals, g.v - 1u, g.gPm, 0.0, d3(0, 0, 0));
-            if (!g.tip) bwd_add(keys, vals, g.v + 2u, g.gPp, 0.0, d3(0, 0, 0));
+            const float3 z3 = make_float3(0.0f, 0.0f, 0.0f);
+            if (!g.root) bwd_add(keys, vals, g.v - 1u, g.gPm, 0.0f, z3);
+            if (!g.tip) bwd_add(keys, vals, g.v + 2u, g.gPp, 0.0f, z3);
         }
         __syncthreads();
         for (uint32_t x = tid; x < BWD_SLOTS; x += blockDim.x) {
