@@ -46,19 +46,44 @@ __device__ __forceinline__ void lod_entry(const hm_hair_mesh &m, const hm_camera
         const uint32_t qi[4] = {q.x, q.y, q.z, q.w};
         float xmn = INFINITY, xmx = -INFINITY, ymn = INFINITY, ymx = -INFINITY;
         uint32_t n_near = 0;
-        for (uint32_t l = 0; l < m.n_layers; ++l) {
-            const float *lay = m.layer_pos + (size_t)l * m.n_verts * 3;
+        auto vertex = [&](float px, float py, float pz) {
+            float X, Y, Z;
+            to_camera(c, px, py, pz, X, Y, Z);
+            if (Z <= c.zn) { n_near++; return; }
+            float iz = 1.0f / Z;
+            float x = c.cx + c.fx * (X * iz);
+            float y = c.cy - c.fy * (Y * iz);
+            xmn = fminx(x, xmn); xmx = fmaxx(x, xmx);
+            ymn = fminx(y, ymn); ymx = fmaxx(y, ymx);
+        };
+        constexpr uint32_t LPRE = 6;          // layers whose vertices are loaded up front
+        if (m.n_layers <= LPRE) {
+            // all loads first (one memory latency per bundle), then the projections
+            float P[LPRE][4][3];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float *P = lay + (size_t)qi[k] * 3;
-                float X, Y, Z;
-                to_camera(c, P[0], P[1], P[2], X, Y, Z);
-                if (Z <= c.zn) { n_near++; continue; }
-                float iz = 1.0f / Z;
-                float x = c.cx + c.fx * (X * iz);
-                float y = c.cy - c.fy * (Y * iz);
-                xmn = fminx(x, xmn); xmx = fmaxx(x, xmx);
-                ymn = fminx(y, ymn); ymx = fmaxx(y, ymx);
+            for (uint32_t l = 0; l < LPRE; ++l) {
+                const float *lay = m.layer_pos + (size_t)(l < m.n_layers ? l : 0) * m.n_verts * 3;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float *q3 = lay + (size_t)qi[k] * 3;
+                    P[l][k][0] = q3[0]; P[l][k][1] = q3[1]; P[l][k][2] = q3[2];
+                }
+            }
+#pragma unroll
+            for (uint32_t l = 0; l < LPRE; ++l) {
+                if (l < m.n_layers) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) vertex(P[l][k][0], P[l][k][1], P[l][k][2]);
+                }
+            }
+        } else {
+            for (uint32_t l = 0; l < m.n_layers; ++l) {
+                const float *lay = m.layer_pos + (size_t)l * m.n_verts * 3;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float *q3 = lay + (size_t)qi[k] * 3;
+                    vertex(q3[0], q3[1], q3[2]);
+                }
             }
         }
         bool keep = true;

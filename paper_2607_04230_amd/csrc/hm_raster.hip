@@ -82,24 +82,42 @@ __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *sce
         if (i < n0) clr0[i] = 0u;
         if (i < n1) clr1[i] = 0u;
     }
+    // scene by scene (no division per pixel), two pixels per 16-byte store
+    // when the scene has an even pixel count and the buffers are aligned
     const size_t hw = (size_t)W * H;
-    const size_t n = hw * S;
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
-         p += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t s = (uint32_t)(p / hw);
-        const size_t loc = p - (size_t)s * hw;
-        uint64_t key = HM_EMPTY;
-        if (scene_z) {
-            const float z = scene_z[p];
-            const float zn = cams[s].znear, zf = cams[s].zfar;
-            if (z > zn && z < zf) {
-                const float inv_range = 1.0f / (zf - zn);
-                key = ((uint64_t)depth_code(z, zn, inv_range) << HM_ID_BITS) | HM_ID_OPAQUE;
+    const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (uint32_t s = 0; s < S; ++s) {
+        const float *zs = scene_z ? scene_z + (size_t)s * hw : nullptr;
+        const float zn = cams[s].znear, zf = cams[s].zfar;
+        const float inv_range = 1.0f / (zf - zn);
+        auto key_of = [&](float z) -> uint64_t {
+            return (z > zn && z < zf)
+                       ? ((uint64_t)depth_code(z, zn, inv_range) << HM_ID_BITS) | HM_ID_OPAQUE
+                       : HM_EMPTY;
+        };
+        uint64_t *base = vis + (size_t)s * 2 * hw;
+        const bool pairs = (hw & 1) == 0 && ((uintptr_t)vis & 15u) == 0 &&
+                           ((uintptr_t)scene_z & 7u) == 0;
+        if (pairs) {
+            for (size_t q = tid; q < hw / 2; q += stride) {
+                uint64_t k0 = HM_EMPTY, k1 = HM_EMPTY;
+                if (zs) {
+                    const float2 z2 = reinterpret_cast<const float2 *>(zs)[q];
+                    k0 = key_of(z2.x);
+                    k1 = key_of(z2.y);
+                }
+                const ulonglong2 kk = make_ulonglong2(k0, k1);
+                reinterpret_cast<ulonglong2 *>(base)[q] = kk;
+                reinterpret_cast<ulonglong2 *>(base + hw)[q] = kk;
+            }
+        } else {
+            for (size_t loc = tid; loc < hw; loc += stride) {
+                const uint64_t key = zs ? key_of(zs[loc]) : HM_EMPTY;
+                base[loc] = key;
+                base[hw + loc] = key;
             }
         }
-        uint64_t *base = vis + (size_t)s * 2 * hw;
-        base[loc] = key;
-        base[hw + loc] = key;
     }
 }
 
