@@ -346,7 +346,11 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
     const uint32_t NL = m.n_layers;
     const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
     uint32_t chunk = GEN_LDS_FLOATS / stride;              // >= 15 strands for L <= 64
-    if (FUSED) chunk = min(chunk, FUSE_CPS / C);           // >= 8 strands for C <= 127
+    // screen records of a chunk stay in LDS when a strand fits (C <= 1024);
+    // longer strands are projected again from the stream they were just
+    // written to (same bits, no LDS limit)
+    const bool in_lds = C <= FUSE_CPS;
+    if (FUSED && in_lds) chunk = min(chunk, FUSE_CPS / C);   // >= 8 strands for C <= 127
     Cam cam;
     uint32_t sc = 0;
     if (FUSED) {
@@ -442,7 +446,7 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             pw.z = X[2] + amp * (cth * e1.z + sth * e2.z);
             pw.w = g.width;
             pos_w[c] = pw;
-            if (FUSED) pr[r] = project(cam, pw);
+            if (FUSED && in_lds) pr[r] = project(cam, pw);
             float4 col;
             if (strand_rgb) {
                 const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k0 + kk);
@@ -468,7 +472,8 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
                 const uint32_t kk = r / C, j = r - kk * C;
                 const uint32_t c = cp0 + (k0 + kk) * C + j;
                 if (j + 1u >= C || c + 1u >= limit) continue;
-                const float4 pa = pr[r], pb = pr[r + 1];
+                const float4 pa = in_lds ? pr[r] : project(cam, pos_w[c]);
+                const float4 pb = in_lds ? pr[r + 1] : project(cam, pos_w[c + 1]);
                 if (pa.w == 0.0f || pb.w == 0.0f) continue;
                 const Seg sg = make_seg(pa, pb, fk.r_min);
                 int i0, i1, j0, j1;

@@ -94,3 +94,16 @@ def test_fused_truncated_stream(O, torch, cap):
     out = O.resolve(pos, rgb, fl, vis, sc.cams, sc.width, sc.height, ResolveParams(), sc.mode,
                     sc.bg)
     assert np.abs(ds.out.cpu().numpy().astype(np.float64) - out).max() <= TOL
+
+
+def test_fused_strands_longer_than_the_lds_chunk(O, torch):
+    """1500 control points per strand do not fit the chunk's screen records
+    in LDS: those segments are projected again from the stream; the buffer
+    is still bit-identical to the oracle's."""
+    sc = scenes.micro_scene(5, n_cp=1500, res=48)
+    ref = O.render(sc)
+    ds = _fused(sc, torch)
+    pos, rgb, fl = ds.host_stream()
+    assert np.array_equal(pos.view(np.uint32), ref["pos_w"].view(np.uint32))
+    assert np.array_equal(ds.host_vis(), ref["vis"])
+    assert (ref["vis"][:, 0] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum() > 50
