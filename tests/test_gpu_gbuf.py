@@ -77,3 +77,13 @@ def test_gbuffer_depth_and_coverage_equal_segment_keys(torch):
     va, vb = a.host_vis(), b.host_vis()
     assert np.array_equal(va >> np.uint64(40), vb >> np.uint64(40))
     assert np.array_equal(va == EMPTY, vb == EMPTY)
+
+
+def test_gbuffer_keys_multi_scene(O, torch):
+    """Uneven scenes in one frame: every scene's compressed keys and centre
+    resolve match the oracle's."""
+    sc = scenes.config_batched(n_scenes=6, res=128, n_min=1e3, n_max=1e4)
+    vis, out = _ref(O, sc)
+    ds = _gpu(sc, torch)
+    assert np.array_equal(ds.host_vis(), vis)
+    assert np.abs(ds.out.cpu().numpy().astype(np.float64) - out).max() <= TOL
