@@ -132,9 +132,19 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
         hbm = (n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes) / s / 1e9
         if pairs:
             ach = pairs * RASTER_OPS_PER_PAIR / s / 1e12
-            return {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                    "frac": ach / PEAK_VALU_TOPS, "traffic": _traffic(kernel),
-                    "pairs_per_s": pairs / s, "hbm_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
+            r = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                 "frac": ach / PEAK_VALU_TOPS, "traffic": _traffic(kernel),
+                 "pairs_per_s": pairs / s, "hbm_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
+            # the atomic roofline: one LDS 64-bit min per covered (segment,
+            # pixel, layer), against the measured peak of that operation
+            centre = work_counts().get(workload, {}).get("centre_pairs")
+            if centre and ATOMIC_PEAKS:
+                rate = (pairs + centre) / s
+                r.update({"lds_atomic_per_s": rate,
+                          "lds_atomic_peak_per_s": ATOMIC_PEAKS["lds"],
+                          "lds_atomic_frac": rate / ATOMIC_PEAKS["lds"],
+                          "global_atomic_peak_per_s": ATOMIC_PEAKS["global"]})
+            return r
         b = n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes
     elif kernel == "k_prefill":
         b = vis_bytes
@@ -143,6 +153,26 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
     ach = b / s / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": ach / PEAK_HBM_GBS, "traffic": _traffic(kernel)}
+
+
+ATOMIC_PEAKS = {}
+
+
+def measure_atomic_peaks(vis_words: int):
+    """Peak rates of 64-bit atomic minima (microkernels of the library): in LDS
+    with lane-distinct addresses, and in global memory at pseudo-random
+    addresses over a buffer the size of one visibility layer."""
+    import torch
+    from paper_2607_04230_amd import hm
+    grid = 256 * 8
+    sink = torch.empty(grid, dtype=torch.int64, device="cuda")
+    glob = torch.full((vis_words,), -1, dtype=torch.int64, device="cuda")
+    for kind, buf, iters, name in ((0, sink, 4096, "lds"), (1, glob, 256, "global")):
+        ms = _time_ms(lambda: hm.bench_atomics(kind, buf, iters, grid), 3, 1)
+        ATOMIC_PEAKS[name] = grid * 256 * iters / (ms * 1e-3)
+    del sink, glob
+    torch.cuda.empty_cache()
+    return dict(ATOMIC_PEAKS)
 
 
 def _time_ms(fn, steps, warmup):
@@ -445,6 +475,7 @@ def main():
     # dominant kernel: largest total time per step
     dom = max(kt.items(), key=lambda kv: kv[1][0])[0]
     dom_avg = kt[dom][0] / kt[dom][1]
+    measure_atomic_peaks(sc.width * sc.height)
     roof = roofline(dom, dom_avg, n_cp, n_seg, vis_bytes, hair_px, (2 * r + 1) ** 2)
     roof["kernel"] = dom
     for k in ("k_generate_bundle", "k_project", "k_bin", "k_raster_tiles", "k_prefill",

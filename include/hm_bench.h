@@ -1,0 +1,34 @@
+/* Measurement helpers of libhm (not part of the rendering method).
+ *
+ * The tile raster resolves each covered (segment, pixel, layer) pair with one
+ * 64-bit atomic minimum in LDS and merges split tiles with 64-bit global
+ * atomic minima (Sec. 3.1.2's atomic-min visibility buffer); these kernels
+ * measure the device's peak rates of those two operations so that the
+ * benchmark can place the raster against them. */
+#ifndef HM_BENCH_H
+#define HM_BENCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "hm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Enqueue grid workgroups of 256 threads, each thread doing `iters` 64-bit
+ * atomic minima, on `stream` (the caller times it).
+ * kind 0: in LDS, lane-distinct consecutive addresses; buf (device, at
+ *   least grid words) receives one word per workgroup.
+ * kind 1: in global memory over buf[n_words] (device, caller-owned, its
+ *   contents are overwritten by minima), pseudo-random addresses.
+ * Returns HM_ERR_INVALID / HM_ERR_RANGE for bad arguments, HM_ERR_HIP if the
+ * launch failed.  Atomics performed: grid * 256 * iters. */
+hm_status hm_bench_atomics(int32_t kind, uint64_t *buf, size_t n_words, uint32_t iters,
+                           uint32_t grid, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HM_BENCH_H */

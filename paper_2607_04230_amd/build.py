@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhm.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["hm_api.hip", "hm_lod_gen.hip", "hm_raster.hip", "hm_resolve.hip", "hm_batch.hip"]
+SOURCES = ["hm_api.hip", "hm_lod_gen.hip", "hm_raster.hip", "hm_resolve.hip", "hm_batch.hip",
+           "hm_microbench.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")

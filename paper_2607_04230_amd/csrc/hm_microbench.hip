@@ -1,0 +1,63 @@
+// Peak-rate microkernels for the raster's rooflines: 64-bit atomic minima in
+// LDS (lane-distinct, consecutive addresses, as the tile raster's candidate
+// pixels are) and in global memory (addresses spread pseudo-randomly over the
+// caller's buffer).  Measurement helpers only; nothing on the rendering path
+// calls them.
+#include <hip/hip_runtime.h>
+
+#include "hm_bench.h"
+#include "hm_internal.hpp"
+
+namespace hm {
+
+constexpr uint32_t BENCH_LDS_WORDS = 2048;
+
+__global__ __launch_bounds__(256) void k_bench_lds_min(uint32_t iters, unsigned long long *sink)
+{
+    __shared__ unsigned long long t[BENCH_LDS_WORDS];
+    for (uint32_t x = threadIdx.x; x < BENCH_LDS_WORDS; x += blockDim.x) t[x] = ~0ull;
+    __syncthreads();
+    unsigned long long v = (unsigned long long)(blockIdx.x * blockDim.x + threadIdx.x) *
+                           0x9E3779B97F4A7C15ull;
+    for (uint32_t i = 0; i < iters; ++i) {
+        atomicMin(&t[(threadIdx.x + i * blockDim.x) & (BENCH_LDS_WORDS - 1)], v);
+        v = v * 6364136223846793005ull + 1442695040888963407ull;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = t[blockIdx.x & (BENCH_LDS_WORDS - 1)];
+}
+
+__global__ __launch_bounds__(256) void k_bench_global_min(unsigned long long *buf, uint64_t n,
+                                                          uint32_t iters)
+{
+    uint64_t h = (uint64_t)(blockIdx.x * blockDim.x + threadIdx.x) * 0x9E3779B97F4A7C15ull + 1;
+    for (uint32_t i = 0; i < iters; ++i) {
+        h ^= h >> 33;
+        h *= 0xff51afd7ed558ccdull;
+        h ^= h >> 29;
+        atomicMin(buf + (h % n), (unsigned long long)h);
+    }
+}
+
+}  // namespace hm
+
+using namespace hm;
+
+extern "C" hm_status hm_bench_atomics(int32_t kind, uint64_t *buf, size_t n_words, uint32_t iters,
+                                      uint32_t grid, void *stream)
+{
+    if (!buf || iters == 0 || grid == 0 || grid > 65536) return HM_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    if (kind == 0) {
+        if (n_words < grid) return HM_ERR_RANGE;
+        hipLaunchKernelGGL(k_bench_lds_min, dim3(grid), dim3(256), 0, st, iters,
+                           reinterpret_cast<unsigned long long *>(buf));
+    } else if (kind == 1) {
+        if (n_words == 0) return HM_ERR_RANGE;
+        hipLaunchKernelGGL(k_bench_global_min, dim3(grid), dim3(256), 0, st,
+                           reinterpret_cast<unsigned long long *>(buf), (uint64_t)n_words, iters);
+    } else {
+        return HM_ERR_INVALID;
+    }
+    return hipGetLastError() == hipSuccess ? HM_OK : HM_ERR_HIP;
+}

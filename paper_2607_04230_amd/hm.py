@@ -91,6 +91,16 @@ def lod_depth_offset(table, bundle_nstrands, delta_out):
                                  _ptr(delta_out), _stream()), "hm_lod_depth_offset")
 
 
+def bench_atomics(kind: int, buf, iters: int, grid: int):
+    """Enqueue the atomic-rate microkernel (0: LDS, 1: global over buf) on the
+    current stream; grid * 256 * iters 64-bit atomic minima."""
+    L = load()
+    L.hm_bench_atomics.argtypes = [_i32, _vp, _sz, _u32, _u32, _vp]
+    L.hm_bench_atomics.restype = _i32
+    _check(L.hm_bench_atomics(kind, _ptr(buf), buf.numel(), iters, grid, _stream()),
+           "hm_bench_atomics")
+
+
 def generate_raster(mesh, table, strand_base, strand_rgb, gp, st, cams, fr, r_min, scene_z,
                     vis):
     """Strand generation fused with the direct raster (stream and visibility)."""

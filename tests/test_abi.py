@@ -121,6 +121,12 @@ def test_validation_errors_are_reported():
     assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
                                 ctypes.byref(st), dummy, ctypes.byref(fr), ctypes.c_float(-1.0),
                                 None, dummy, None) == 2
+    # atomic-rate microkernels: argument checks before any launch
+    L.hm_bench_atomics.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+    assert L.hm_bench_atomics(5, dummy, 4096, 1, 16, None) == 1
+    assert L.hm_bench_atomics(0, None, 4096, 1, 16, None) == 1
+    assert L.hm_bench_atomics(0, dummy, 8, 1, 16, None) == 2
     # compressed G-buffer keys: known payloads only, no shared views, CENTER resolve
     rp = hm.raster_defaults(fr)
     rp.payload = 2
