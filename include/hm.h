@@ -8,7 +8,10 @@
  * segment is rasterized into two 64-bit visibility layers with an atomic
  * minimum on (depth, segment id); a deferred per-pixel resolve shades the
  * visible segments and reconstructs / filters the strands, or evaluates the
- * differentiable soft-coverage resolve.
+ * differentiable soft-coverage resolve.  Also: deep-opacity-map shadows with
+ * the LOD depth correction (hm_dom_accumulate, hm_dom_shadow), the paper's
+ * compressed G-buffer keys (hm_raster_params.payload), and generation fused
+ * with the raster (hm_generate_raster).
  *
  * General conventions
  *   - Every pointer inside a struct or passed as an array argument is a DEVICE
