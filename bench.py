@@ -462,6 +462,26 @@ def main():
         ms_graph = timed(graph.launch, side)
         graph.close()
     ms = min(ms_eager, ms_graph)
+    # (d) per-frame spread (one event pair per frame, outside the timed
+    #     region) and cold frames: a 512 MiB scrub between frames evicts the
+    #     buffers from the 256 MiB Infinity Cache and the L2s
+    def per_frame(n, scrub=None):
+        out = []
+        for _ in range(n):
+            if scrub is not None:
+                scrub.add_(1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ds.render()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return np.percentile(np.array(out), [10, 50, 90]).tolist()
+    warm_pct = per_frame(max(args.steps, 10))
+    scrub = torch.zeros(128 << 20, dtype=torch.float32, device="cuda")
+    cold_pct = per_frame(max(args.steps // 2, 5), scrub)
+    del scrub
+    torch.cuda.empty_cache()
     tot = ds.totals.cpu().numpy()
     n_strands, n_cp = int(tot[0]), int(tot[1])
     n_seg = n_cp - n_strands
@@ -499,6 +519,8 @@ def main():
         "ms_per_step_eager": ms_eager,
         "ms_per_step_graph": ms_graph,
         "ms_per_step_instrumented": ms_instr,
+        "ms_per_frame_p10_p50_p90": warm_pct,
+        "ms_per_frame_cold_p10_p50_p90": cold_pct,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
