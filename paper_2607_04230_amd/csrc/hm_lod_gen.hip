@@ -3,9 +3,9 @@
 // The paper dispatches one workgroup per strand indirectly from the LOD
 // buffer.  HIP has no indirect dispatch, so the LOD pass writes the per-bundle
 // counts and a device prefix sum turns them into offsets (the table of
-// {N_LOD, C, first strand, first CP}); generation then launches one
-// 256-thread workgroup per bundle that reads its (possibly zero) row of the
-// table.  A bundle's strand parameters, bilinear layer points and
+// {N_LOD, C, first strand, first CP}); generation then gives each bundle a
+// workgroup, or one wave of one when there are many or small bundles, that
+// reads its (possibly zero) row of the table.  A bundle's strand parameters, bilinear layer points and
 // finite-difference layer tangents are computed once into LDS per chunk of
 // strands; lanes then evaluate consecutive control points (Hermite + curl)
 // and store them coalesced.  The fused variant also projects each control
@@ -319,15 +319,35 @@ struct FuseK {
     uint32_t W, H;
     float r_min;
 };
-constexpr uint32_t FUSE_CPS = 1024;        // screen records of one strand chunk in LDS (16 KB)
+constexpr uint32_t FUSE_CPS = 1024;        // screen records of strand chunks in LDS (16 KB)
+constexpr uint32_t GEN_WAVES = 4;          // waves of a generation workgroup
 
-// One workgroup per bundle.  FUSED: every control point is also projected
-// where it is generated (screen record in LDS, as the raster's projection
+// Orders the LDS and global accesses of the threads that share a bundle
+// around a hand-off between stages: its one wave (WAVE), else the workgroup.
+template <bool WAVE>
+__device__ __forceinline__ void gen_sync()
+{
+    if (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        __syncthreads();
+    }
+}
+
+// WAVE: one wave per bundle, four bundles per workgroup (each wave works in
+// its own quarter of the LDS and synchronises only its own lanes, so a bundle
+// left with a few short strands by the LOD does not hold a whole workgroup).
+// Otherwise one workgroup per bundle: all 256 threads share its work, which
+// keeps the chip busy when there are few bundles with many strands each.
+// The two shapes compute the same values.  FUSED: every control point is
+// also projected where it is generated (screen record in LDS, as the raster's projection
 // computes it), and once a chunk of strands is complete each of its segments
 // is rasterized from LDS by one thread with global atomic minima on both
 // layers -- the paper's assembly-and-raster in one pass, with the same
 // coverage tests, depth codes and keys as the raster call.
-template <bool FUSED>
+template <bool FUSED, bool WAVE>
 __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
                                                         const uint32_t *strand_base,
                                                         const float *strand_rgb, GenK g,
@@ -335,9 +355,17 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
                                                         uint8_t *flags, const uint32_t *scene_off,
                                                         uint32_t S, uint32_t cap, FuseK fk)
 {
-    __shared__ float sm[GEN_LDS_FLOATS];
-    __shared__ float4 pr[FUSED ? FUSE_CPS : 1];
-    const uint32_t b = blockIdx.x;
+    constexpr uint32_t NB = WAVE ? GEN_WAVES : 1u;      // bundles per workgroup
+    constexpr uint32_t NT = 256u / NB;                  // threads per bundle
+    constexpr uint32_t SM_FLOATS = GEN_LDS_FLOATS / NB, PR_CPS = FUSE_CPS / NB;
+    __shared__ float sm_all[GEN_LDS_FLOATS];
+    __shared__ float4 pr_all[FUSED ? FUSE_CPS : GEN_WAVES];
+    const uint32_t wv = WAVE ? threadIdx.x >> 6 : 0u;
+    const uint32_t lane = WAVE ? threadIdx.x & 63u : threadIdx.x;
+    const uint32_t b = blockIdx.x * NB + wv;
+    if (b >= m.n_bundles) return;                  // the whole wave / workgroup
+    float *sm = sm_all + wv * SM_FLOATS;
+    float4 *pr = pr_all + (FUSED ? wv * PR_CPS : 0u);
     const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
     const uint32_t n = tb.x, C = tb.y, cp0 = tb.w;
     if (n == 0) return;
@@ -345,12 +373,12 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
     const uint32_t limit = total < cap ? total : cap;
     const uint32_t NL = m.n_layers;
     const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
-    uint32_t chunk = GEN_LDS_FLOATS / stride;              // >= 15 strands for L <= 64
-    // screen records of a chunk stay in LDS when a strand fits (C <= 1024);
-    // longer strands are projected again from the stream they were just
-    // written to (same bits, no LDS limit)
-    const bool in_lds = C <= FUSE_CPS;
-    if (FUSED && in_lds) chunk = min(chunk, FUSE_CPS / C);   // >= 8 strands for C <= 127
+    uint32_t chunk = SM_FLOATS / stride;     // >= 3 (WAVE) / 15 strands for L <= 64
+    // screen records of a chunk stay in LDS when a strand fits (C <= 256
+    // (WAVE) / 1024); longer strands are projected again from the stream
+    // they were just written to (same bits, no LDS limit)
+    const bool in_lds = C <= PR_CPS;
+    if (FUSED && in_lds) chunk = min(chunk, PR_CPS / C);   // >= 2 strands for C <= 127
     Cam cam;
     uint32_t sc = 0;
     if (FUSED) {
@@ -378,27 +406,25 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
 
     for (uint32_t k0 = 0; k0 < n; k0 += chunk) {
         const uint32_t nk = (n - k0) < chunk ? (n - k0) : chunk;
-        // strand hashes
-        for (uint32_t kk = threadIdx.x; kk < nk; kk += blockDim.x) {
-            const uint32_t h1 = pcg(hb + (k0 + kk));
-            const uint32_t h2 = pcg(h1);
-            const uint32_t h3 = pcg(h2);
-            float *o = sm + kk * stride + 6u * NL;
-            o[0] = unit24(h1);
-            o[1] = unit24(h2);
-            o[2] = unit24(h3);
-        }
-        __syncthreads();
-        // base layer points
-        for (uint32_t x = threadIdx.x; x < nk * NL; x += blockDim.x) {
+        // base layer points; the strand's (u, v) and curl phase come from its
+        // hash, recomputed by each of its layers' threads (no separate stage)
+        for (uint32_t x = lane; x < nk * NL; x += NT) {
             const uint32_t kk = x / NL, l = x - kk * NL;
             float *o = sm + kk * stride;
-            const F3 P = layer_point(m.layer_pos, m.n_verts, l, q, o[6u * NL], o[6u * NL + 1]);
+            const uint32_t h1 = pcg(hb + (k0 + kk));
+            const uint32_t h2 = pcg(h1);
+            const float u = unit24(h1), v = unit24(h2);
+            if (l == 0) {
+                o[6u * NL] = u;
+                o[6u * NL + 1] = v;
+                o[6u * NL + 2] = unit24(pcg(h2));
+            }
+            const F3 P = layer_point(m.layer_pos, m.n_verts, l, q, u, v);
             o[6 * l + 0] = P.x; o[6 * l + 1] = P.y; o[6 * l + 2] = P.z;
         }
-        __syncthreads();
+        gen_sync<WAVE>();
         // finite-difference layer tangents
-        for (uint32_t x = threadIdx.x; x < nk * NL; x += blockDim.x) {
+        for (uint32_t x = lane; x < nk * NL; x += NT) {
             const uint32_t kk = x / NL, l = x - kk * NL;
             float *o = sm + kk * stride;
             const uint32_t la = l == 0 ? 1u : (l == NL - 1 ? l : l + 1);
@@ -406,9 +432,9 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             const F3 T = f3norm(f3sub(ld3(o + 6 * la), ld3(o + 6 * lb)));
             o[6 * l + 3] = T.x; o[6 * l + 4] = T.y; o[6 * l + 5] = T.z;
         }
-        __syncthreads();
+        gen_sync<WAVE>();
         // control points of strands k0 .. k0+nk-1 (contiguous in the stream)
-        for (uint32_t r = threadIdx.x; r < nk * C; r += blockDim.x) {
+        for (uint32_t r = lane; r < nk * C; r += NT) {
             const uint32_t kk = r / C, j = r - kk * C;
             const uint32_t c = cp0 + (k0 + kk) * C + j;
             if (c >= limit) continue;
@@ -461,14 +487,14 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             if (j == C - 1u || c == limit - 1u) fl |= (uint8_t)HM_TIP;
             flags[c] = fl;
         }
-        __syncthreads();
+        gen_sync<WAVE>();
         if (FUSED) {
             // segments of the chunk: CP j of strand kk joins j + 1 unless j
             // is a tip (last CP of its strand, or of a truncated stream)
             const size_t hw = (size_t)fk.W * fk.H;
             uint64_t *vc = fk.vis + (size_t)sc * 2 * hw, *va = vc + hw;
             const float zn = cam.zn, inv_range = 1.0f / (cam.zf - zn);
-            for (uint32_t r = threadIdx.x; r < nk * C; r += blockDim.x) {
+            for (uint32_t r = lane; r < nk * C; r += NT) {
                 const uint32_t kk = r / C, j = r - kk * C;
                 const uint32_t c = cp0 + (k0 + kk) * C + j;
                 if (j + 1u >= C || c + 1u >= limit) continue;
@@ -494,9 +520,38 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
                     }
                 }
             }
-            // pr is rewritten only after the next chunk's three barriers
+            // pr is rewritten only after the next chunk's two barriers
         }
     }
+}
+
+// Launch shape of the generator: one wave per bundle when the bundles alone
+// give every SIMD of the chip (256 CUs x 4) several waves, or when a bundle
+// at full detail averages at most two control points per thread of a
+// workgroup (a workgroup would idle); otherwise one workgroup per bundle.
+// cap bounds the stream, so cap / n_bundles bounds the average bundle.
+static bool gen_wave(const hm_hair_mesh &m, uint32_t cap)
+{
+    return m.n_bundles >= 4096u || (uint64_t)cap <= 512ull * m.n_bundles;
+}
+
+template <bool FUSED>
+static void launch_gen_kernel(const hm_hair_mesh &m, const uint32_t *table,
+                              const uint32_t *strand_base, const float *strand_rgb, GenK g,
+                              const hm_strands &s, FuseK fk, hipStream_t st)
+{
+    const bool wave = gen_wave(m, s.cap);
+    const uint32_t grid = wave ? (m.n_bundles + GEN_WAVES - 1) / GEN_WAVES : m.n_bundles;
+#define HM_GEN_LAUNCH(W)                                                                    \
+    hipLaunchKernelGGL((k_generate_bundle<FUSED, W>), dim3(grid), dim3(256), 0, st, m, table,  \
+                       strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),        \
+                       reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,    \
+                       s.cap, fk)
+    if (wave)
+        HM_GEN_LAUNCH(true);
+    else
+        HM_GEN_LAUNCH(false);
+#undef HM_GEN_LAUNCH
 }
 
 void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
@@ -505,10 +560,8 @@ void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_
 {
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    hipLaunchKernelGGL(k_generate_bundle<false>, dim3(m.n_bundles), dim3(256), 0, st, m, table,
-                       strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
-                       reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
-                       s.cap, FuseK{nullptr, nullptr, 0u, 0u, 0.0f});
+    launch_gen_kernel<false>(m, table, strand_base, strand_rgb, g, s,
+                             FuseK{nullptr, nullptr, 0u, 0u, 0.0f}, st);
 }
 
 void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
@@ -520,10 +573,8 @@ void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
     launch_prefill(vis, scene_z, cams, f, st);
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    hipLaunchKernelGGL(k_generate_bundle<true>, dim3(m.n_bundles), dim3(256), 0, st, m, table,
-                       strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),
-                       reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,
-                       s.cap, FuseK{cams, vis, f.width, f.height, r_min});
+    launch_gen_kernel<true>(m, table, strand_base, strand_rgb, g, s,
+                            FuseK{cams, vis, f.width, f.height, r_min}, st);
 }
 
 }  // namespace hm

@@ -37,10 +37,15 @@ def _separate(sc, torch, cap=None):
     return ds
 
 
-def test_tiny_fused_matches_oracle(O, torch):
+# The generator runs one wave per bundle when the bundles are many or small
+# (tiny: 64 bundles, 9216 CPs <= 512 per bundle) and one workgroup per bundle
+# otherwise; a stream bound of 40000 CPs (> 512 per bundle) selects the
+# workgroup shape for the same scene.
+@pytest.mark.parametrize("cap", [None, 40000], ids=["wave", "workgroup"])
+def test_tiny_fused_matches_oracle(O, torch, cap):
     sc = scenes.config_tiny()
     ref = O.render(sc)
-    ds = _fused(sc, torch)
+    ds = _fused(sc, torch, cap=cap)
     pos, rgb, fl = ds.host_stream()
     assert np.array_equal(fl, ref["flags"])
     assert np.array_equal(pos.view(np.uint32), ref["pos_w"].view(np.uint32))
@@ -107,3 +112,24 @@ def test_fused_strands_longer_than_the_lds_chunk(O, torch):
     assert np.array_equal(pos.view(np.uint32), ref["pos_w"].view(np.uint32))
     assert np.array_equal(ds.host_vis(), ref["vis"])
     assert (ref["vis"][:, 0] != np.uint64(0xFFFFFFFFFFFFFFFF)).sum() > 50
+
+
+def test_fused_wave_shape_with_strands_longer_than_its_lds_slice(O, torch):
+    """3 bundles of 300-CP strands with the stream bound at 1500 CPs (<= 512
+    per bundle): one wave per bundle, whose quarter of the LDS holds at most
+    256 screen records, so every segment is projected again from the stream;
+    the truncated stream and the buffer match the oracle bit for bit."""
+    sc = scenes.micro_scene(5, n_cp=300, res=48)
+    cap = 1500
+    table, soff, (ns, ncp) = O.lod_select(sc)
+    assert cap < ncp and cap <= 512 * sc.quads.shape[0]
+    pos, rgb, fl = O.generate(sc, table, ncp, cap=cap)
+    soff_c = np.minimum(soff, cap).astype(np.uint32)
+    vis = O.raster(pos, fl, soff_c, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+    ds = _fused(sc, torch, cap=cap)
+    gp, gr, gf = ds.host_stream()
+    assert np.array_equal(gf, fl)
+    assert np.array_equal(gp.view(np.uint32), pos.view(np.uint32))
+    assert np.array_equal(gr.view(np.uint32), rgb.view(np.uint32))
+    assert np.array_equal(ds.host_vis(), vis)
+    assert (vis != np.uint64(0xFFFFFFFFFFFFFFFF)).sum() > 80      # 105 keys in both layers

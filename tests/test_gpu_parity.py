@@ -155,6 +155,19 @@ def test_empty_frame_camera_facing_away(O, torch):
     assert (out[..., 3] == 0.0).all()
 
 
+def test_tiny_stream_with_the_workgroup_generator(O, torch):
+    """A stream bound of 40000 CPs (> 512 per bundle of the 64) selects one
+    workgroup per bundle instead of one wave; the stream is the same."""
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_tiny()
+    ref = O.render(sc, want=("vis",))
+    ds = DeviceScene(sc, cap=40000)
+    ds.render()
+    torch.cuda.synchronize()
+    _compare_stream(ds, ref)
+    assert np.array_equal(ds.host_vis(), ref["vis"])
+
+
 @pytest.mark.parametrize("cap", [2, 1001, 5000])
 def test_stream_truncated_to_capacity(O, torch, cap):
     # a stream capacity below the LOD total keeps the first cap control
