@@ -158,7 +158,9 @@ typedef struct {
  * table: the LOD table of hm_lod_select.  strand_base[b]: index of bundle b's
  * first record in strand_rgb ([.][3], per full strand); strand_rgb may be
  * NULL (base_rgb for all).  out->pos_w/rgb/flags receive n_cp CPs;
- * out->scene_off must already hold the LOD output. */
+ * out->scene_off must already hold the LOD output.  Launch shape (the
+ * output does not depend on it): one wave per bundle when n_bundles >= 4096
+ * or out->cap <= 512 * n_bundles, else one workgroup per bundle. */
 hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
                               const uint32_t *strand_base, const float *strand_rgb,
                               const hm_gen_params *p, const hm_strands *out, void *stream);
@@ -166,9 +168,10 @@ hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
 /* ------------------------------------------------------------------ rasterization */
 /* Strand generation fused with the raster (Sec. 3.1.1 with 3.1.2: the paper
  * assembles strands and rasterizes their segments in the same workgroup,
- * without a separate pass over a stored stream).  One workgroup per bundle
- * generates its control points exactly as hm_generate_strands (and writes
- * them to out, for the resolve), projects each one where it is made, and
+ * without a separate pass over a stored stream).  One workgroup or one
+ * wave per bundle (the rule of hm_generate_strands) generates its control
+ * points exactly as hm_generate_strands (and writes them to out, for the
+ * resolve), projects each one where it is made, and
  * rasterizes every segment of a finished chunk of strands from LDS with
  * global atomic minima on both layers.  vis receives exactly what
  * hm_raster_vis writes for the same stream (frame->n_scenes scenes, scene

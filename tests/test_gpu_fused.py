@@ -1,5 +1,5 @@
 """GPU parity of strand generation fused with the raster (Sec. 3.1.1 with
-3.1.2: one workgroup per bundle generates, projects and rasterizes): the
+3.1.2: one workgroup or wave per bundle generates, projects and rasterizes): the
 stream and the visibility buffer bit for bit against the oracle and against
 the separate generate + tiled raster calls, RGBA of the resolve within 1e-4."""
 import numpy as np
