@@ -128,6 +128,21 @@ __global__ __launch_bounds__(256) void k_lod(hm_hair_mesh m, const hm_camera *ca
     cnt_c[b] = (uint64_t)n * cp;
 }
 
+// scene_off[t] is the first CP of the first bundle whose scene is >= t (the
+// total when there is none).  bundle_scene is non-decreasing, so bundle b
+// starts the scenes t in (bundle_scene[b - 1], bundle_scene[b]] (t from 0 for
+// b = 0): each bundle writes those entries from its neighbour's scene, one
+// coalesced load instead of a binary search of dependent loads per scene.
+// Entries stay below S + 1 for any input.
+__device__ __forceinline__ void scene_starts(const uint32_t *bundle_scene, uint32_t b, uint32_t S,
+                                             uint32_t off, uint32_t *scene_off)
+{
+    const uint32_t sb = bundle_scene[b];
+    const uint32_t t0 = b == 0 ? 0u : bundle_scene[b - 1] + 1u;
+    const uint32_t t1 = sb < S ? sb : S;
+    for (uint32_t t = t0; t <= t1; ++t) scene_off[t] = off;
+}
+
 // Whole LOD pass in one workgroup (meshes of up to LOD_SMALL bundles): counts,
 // both exclusive prefix sums, scene offsets and totals in a single launch.
 constexpr uint32_t LOD_SMALL = 8192;
@@ -149,24 +164,20 @@ __global__ __launch_bounds__(1024) void k_lod_small(hm_hair_mesh m, const hm_cam
         const uint64_t os = block_exclusive_scan<uint64_t>(n, lds_s, ts) + carry_s;
         const uint64_t oc = block_exclusive_scan<uint64_t>((uint64_t)n * cp, lds_c, tc) + carry_c;
         if (b < B) {
+            const uint32_t oc32 = (uint32_t)(oc < lim ? oc : lim);
             table[4 * (size_t)b + 0] = n;
             table[4 * (size_t)b + 1] = cp;
             table[4 * (size_t)b + 2] = (uint32_t)(os < lim ? os : lim);
-            table[4 * (size_t)b + 3] = (uint32_t)(oc < lim ? oc : lim);
+            table[4 * (size_t)b + 3] = oc32;
+            scene_starts(m.bundle_scene, b, S, oc32, scene_off);
         }
         carry_s += ts;
         carry_c += tc;
     }
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t <= S; t += blockDim.x) {
-        uint32_t lo = 0, hi = B;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (m.bundle_scene[mid] < t) lo = mid + 1; else hi = mid;
-        }
-        const uint64_t o = lo < B ? (uint64_t)table[4 * (size_t)lo + 3] : carry_c;
-        scene_off[t] = (uint32_t)(o < lim ? o : lim);
-    }
+    // scenes after the last bundle's start at the total
+    const uint32_t tot32 = (uint32_t)(carry_c < lim ? carry_c : lim);
+    for (uint32_t t = m.bundle_scene[B - 1] + 1u + threadIdx.x; t <= S; t += blockDim.x)
+        scene_off[t] = tot32;
     if (threadIdx.x == 0) {
         totals[0] = carry_s;
         totals[1] = carry_c;
@@ -181,19 +192,13 @@ __global__ __launch_bounds__(256) void k_lod_finish(uint32_t *table, const uint6
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t lim = 0xFFFFFFFFull;
     if (t < B) {
+        const uint32_t oc32 = (uint32_t)(off_c[t] < lim ? off_c[t] : lim);
         table[4 * (size_t)t + 2] = (uint32_t)(off_s[t] < lim ? off_s[t] : lim);
-        table[4 * (size_t)t + 3] = (uint32_t)(off_c[t] < lim ? off_c[t] : lim);
+        table[4 * (size_t)t + 3] = oc32;
+        scene_starts(bundle_scene, t, S, oc32, scene_off);
     }
-    if (t <= S) {
-        // first bundle with scene >= t (bundle_scene is non-decreasing)
-        uint32_t lo = 0, hi = B;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi) >> 1;
-            if (bundle_scene[mid] < t) lo = mid + 1; else hi = mid;
-        }
-        uint64_t o = off_c[lo];   // off_c[B] is the total
-        scene_off[t] = (uint32_t)(o < lim ? o : lim);
-    }
+    if (t <= S && t > bundle_scene[B - 1])       // after the last bundle's scene: the total
+        scene_off[t] = (uint32_t)(off_c[B] < lim ? off_c[B] : lim);
     if (t == 0) {
         totals[0] = off_s[B];
         totals[1] = off_c[B];

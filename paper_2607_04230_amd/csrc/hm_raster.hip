@@ -326,6 +326,7 @@ constexpr uint32_t BIN_SLOTS = 1024;      // LDS hash slots per workgroup
 #endif
 constexpr uint32_t BIN_SUB = HM_BIN_SUB;      // most segments per thread between table flushes
 constexpr uint32_t BIN_BLOCK = HM_BIN_BLOCK;  // threads per binning workgroup
+static_assert(BIN_BLOCK % 64 == 0 && BIN_BLOCK <= 1024, "binning workgroups are whole waves");
 constexpr uint32_t BIN_WGS = HM_BIN_WGS;      // workgroups the segments are spread over (at least)
 constexpr uint32_t BIN_FREE = 0xFFFFFFFFu;
 
@@ -380,13 +381,26 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                                                    const uint32_t *tile_off, uint32_t *tile_cur,
                                                    uint32_t *entries, uint32_t *long_list,
                                                    uint32_t *counters, uint32_t nsub,
-                                                   uint2 *segrec, uint32_t *saved)
+                                                   uint2 *segrec, uint32_t *saved,
+                                                   const uint32_t *item_off, uint32_t *item_tile,
+                                                   uint32_t max_items)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
     const uint32_t span = BIN_BLOCK * nsub;        // segments per table flush
     const uint32_t kmax = rk.K < BIN_KMAX ? rk.K : BIN_KMAX;
+    if (pass == 1) {
+        // the tile of every work item of the raster (item_tile[i] = t for
+        // item_off[t] <= i < item_off[t + 1]), one wave per tile, so that a
+        // raster workgroup finds its tile with one load
+        const uint32_t nw = blockDim.x >> 6, lane = threadIdx.x & 63u;
+        for (uint32_t t = blockIdx.x * nw + (threadIdx.x >> 6); t < rk.n_tiles;
+             t += gridDim.x * nw) {
+            const uint32_t i1 = min(item_off[t + 1], max_items);
+            for (uint32_t i = item_off[t] + lane; i < i1; i += 64u) item_tile[i] = t;
+        }
+    }
     // v below is a segment unit (see unit_map); lists store units
     for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
         uint32_t *sv = saved + (size_t)(base / span) * (2 * BIN_SLOTS);
@@ -640,7 +654,7 @@ template <bool FLAT, uint32_t NBC, bool DOM, bool GB>
 __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
                                uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
-                               const uint32_t *entries, uint32_t *counters, uint64_t *vis,
+                               const uint32_t *item_tile, const uint32_t *entries, uint32_t *counters, uint64_t *vis,
                                DomK dk, GbK gk)
 {
     extern __shared__ uint64_t lds[];
@@ -680,13 +694,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
         __syncthreads();
         const uint32_t item = sh_item;
         if (item >= n_items) break;
-        // tile of the item: last t with item_off[t] <= item
-        uint32_t lo = 0, hi = rk.n_tiles;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (item_off[mid] <= item) lo = mid; else hi = mid;
-        }
-        const uint32_t t = lo;
+        const uint32_t t = item_tile[item];         // item_off[t] <= item < item_off[t + 1]
         const uint32_t beg = tile_off[t] + (item - item_off[t]) * rk.chunk;
         const uint32_t end0 = beg + rk.chunk, tend = tile_off[t + 1];
         const uint32_t end = end0 < tend ? end0 : tend;
@@ -1018,6 +1026,8 @@ struct RasterWs {
     uint32_t *entries;    // cap * K
     float4 *tan;          // G-buffer keys: unit tangent per stream point (else null)
     uint2 *segrec;        // per unit: first tile of its box, box width | tile mask << 8
+    uint32_t *item_tile;  // per work item: its tile
+    uint32_t max_items;   // bound on the work items: n_tiles + units * K / chunk
     uint32_t *saved;      // per binning span: its LDS table (keys, counts)
     uint32_t nsub;        // segments per thread and span
     size_t bytes;
@@ -1058,11 +1068,18 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
         const size_t spans = (units + (size_t)BIN_BLOCK * w.nsub - 1) / ((size_t)BIN_BLOCK * w.nsub);
         w.segrec = (uint2 *)take(sizeof(uint2) * units);
         w.saved = (uint32_t *)take(sizeof(uint32_t) * 2 * BIN_SLOTS * spans);
+        // every list entry belongs to one item of its tile: sum over tiles of
+        // ceil(count / chunk) <= n_tiles + entries / chunk
+        const size_t mi = nt + (units * p.max_tiles_per_seg + p.chunk - 1) / p.chunk;
+        w.max_items = (uint32_t)std::min<size_t>(mi, 0xFFFFFFFFu);
+        w.item_tile = (uint32_t *)take(sizeof(uint32_t) * w.max_items);
     } else {
         w.long_list = nullptr;
         w.entries = nullptr;
         w.segrec = nullptr;
         w.saved = nullptr;
+        w.item_tile = nullptr;
+        w.max_items = 0;
         w.nsub = 1;
     }
     w.bytes = o;
@@ -1140,7 +1157,7 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters,
-                       nsub, w.segrec, w.saved);
+                       nsub, w.segrec, w.saved, (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
     const bool small = nt <= PLAN_SMALL;
     if (small) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), 0, st, w.tile_cnt, nt, rk.chunk,
@@ -1149,19 +1166,20 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
         scan_exclusive<uint32_t>(w.tile_cnt, w.tile_cnt, nt, w.partials, st);
         hipLaunchKernelGGL(k_tile_items, dim3((nt + 255) / 256), dim3(256), 0, st,
                            (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
+        scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
     }
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
-                       w.counters, nsub, w.segrec, w.saved);
-    if (!small) scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
+                       w.counters, nsub, w.segrec, w.saved, (const uint32_t *)w.items, w.item_tile,
+                       w.max_items);
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
 #define HM_TILES_LAUNCH(FL, NB, GB)                                                            \
     hipLaunchKernelGGL((k_raster_tiles<FL, NB, false, GB>), dim3(grid), dim3(p.block), lds, st,  \
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,  \
                        s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,          \
-                       (const uint32_t *)w.entries, w.counters, vis, DomK{nullptr, 1u, 1u}, gk)
+                       (const uint32_t *)w.item_tile, (const uint32_t *)w.entries, w.counters, vis, DomK{nullptr, 1u, 1u}, gk)
     if (gbuf) {
         // G-buffer keys: the default shape compiled for its block size, others generic
         if (p.algo == HM_RASTER_TILED) {
@@ -1241,8 +1259,8 @@ void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_
     hipLaunchKernelGGL((k_raster_tiles<true, 256, true, false>), dim3(256u * 8u), dim3(256), lds,
                        st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light,
                        rk, s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
-                       (const uint32_t *)w.entries, w.counters, light_vis, dk,
-                       GbK{nullptr, nullptr});
+                       (const uint32_t *)w.item_tile, (const uint32_t *)w.entries, w.counters,
+                       light_vis, dk, GbK{nullptr, nullptr});
     hipLaunchKernelGGL((k_raster_long<true, false>), dim3(256), dim3(256), 0, st,
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light, rk,
                        s.cap, (const uint32_t *)w.long_list, (const uint32_t *)w.counters,
