@@ -195,3 +195,39 @@ def test_multiview_one_stream_many_views(O, torch):
         assert np.array_equal(gvis[v], ref[0]), v
         o = O.resolve(pos, rgb, fl, ref, views[v:v + 1], 640, 360, rp_, base.mode, base.bg)
         assert np.abs(gout[v] - o[0]).max() <= TOL, v
+
+
+def _with_empty_scenes(n_used):
+    """A batch whose scenes 0, 2, 4, ... and the last have no bundles: scene s
+    of the builder becomes scene 2s + 1 of 2 n_used + 2 (every scene keeps a
+    valid camera)."""
+    sc = scenes.config_batched(n_scenes=n_used, res=64, n_min=1e3, n_max=4e3)
+    S = 2 * n_used + 2
+    cams = np.repeat(sc.cams[:1], S, axis=0).copy()
+    cams[1::2][:n_used] = sc.cams
+    sc.cams = cams
+    sc.bundle_scene = (2 * sc.bundle_scene.astype(np.int64) + 1).astype(np.uint32)
+    sc.scene_z = None
+    return sc
+
+
+@pytest.mark.parametrize("n_used", [3, 5], ids=["one-workgroup-lod", "multi-workgroup-lod"])
+def test_scene_offsets_with_scenes_without_bundles(O, torch, n_used):
+    """Scenes without bundles start at the next used scene's first CP (the
+    total after the last bundle). 6000 bundles take the one-workgroup LOD
+    pass, 10000 the multi-workgroup one; both match the oracle's table and
+    offsets, and the stream generated from them matches too."""
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = _with_empty_scenes(n_used)
+    assert sc.n_bundles == 2000 * n_used
+    table, soff, (ns, ncp) = O.lod_select(sc)
+    assert soff[0] == 0 and soff[-1] == ncp
+    assert all(soff[2 * s] == soff[2 * s + 1] for s in range(n_used + 1))
+    pos, rgb, fl = O.generate(sc, table, ncp)
+    ds = DeviceScene(sc)
+    ds.lod()
+    ds.generate()
+    torch.cuda.synchronize()
+    tot = ds.totals.cpu().numpy()
+    assert (int(tot[0]), int(tot[1])) == (ns, ncp)
+    _check_stream(ds, table, soff, ncp, pos, rgb, fl)
