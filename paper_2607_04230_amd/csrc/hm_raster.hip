@@ -256,31 +256,48 @@ struct SegTiles {
     uint32_t s, tx0, ty0, bw, nt;
 };
 
-// PROJECT: also compute this unit's screen record from the stream (and the
-// next control point's, for the segment) and store it in proj[u]; otherwise
-// read both records from proj.  Both give the same bits.
-template <bool PROJECT>
-__device__ __forceinline__ bool seg_tiles(const float4 *proj_in, float4 *proj_out,
-                                          const float4 *pos_w, const hm_camera *cams,
-                                          const uint8_t *flags, const uint32_t *scene_off,
-                                          const RasterK &rk, uint32_t u, uint32_t n, SegTiles &st)
+// Stream inputs of one unit's segment.  The binning loads them one step
+// ahead, so that their latency overlaps the previous segment's tile work.
+struct SegIn {
+    float4 p0, p1;      // control points v and v + 1 (world)
+    uint32_t s, v;      // scene, stream index
+    uint8_t f;          // flags of v
+    bool live;          // u < unit count
+};
+
+__device__ __forceinline__ SegIn seg_load(const float4 *pos_w, const uint8_t *flags,
+                                          const uint32_t *scene_off, const RasterK &rk,
+                                          uint32_t u, uint32_t n)
+{
+    SegIn in;
+    in.live = u < unit_count(n, rk);
+    in.s = 0;
+    in.v = 0;
+    in.f = 0;
+    in.p0 = in.p1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (in.live) {
+        unit_map(scene_off, rk, n, u, in.s, in.v);
+        in.p0 = pos_w[in.v];
+        in.f = flags[in.v];
+        if (in.v + 1 < n) in.p1 = pos_w[in.v + 1];
+    }
+    return in;
+}
+
+// The unit's screen record (stored in proj[u]), and, when it starts a
+// segment, the segment's tile box.
+__device__ __forceinline__ bool seg_tiles(const SegIn &in, const hm_camera *cams, float4 *proj,
+                                          const RasterK &rk, uint32_t u, uint32_t n,
+                                          SegTiles &st)
 {
     st.nt = 0;
-    if (u >= unit_count(n, rk)) return false;
-    uint32_t v;
-    unit_map(scene_off, rk, n, u, st.s, v);
-    float4 a, b;
-    if (PROJECT) {
-        const Cam cam = load_cam(cams + st.s);
-        a = project(cam, pos_w[v]);
-        proj_out[u] = a;
-        if (v + 1 >= n || (flags[v] & HM_TIP)) return false;
-        b = project(cam, pos_w[v + 1]);
-    } else {
-        if (v + 1 >= n || (flags[v] & HM_TIP)) return false;
-        a = proj_in[u];
-        b = proj_in[u + 1];
-    }
+    if (!in.live) return false;
+    st.s = in.s;
+    const Cam cam = load_cam(cams + st.s);
+    const float4 a = project(cam, in.p0);
+    proj[u] = a;
+    if (in.v + 1 >= n || (in.f & HM_TIP)) return false;
+    const float4 b = project(cam, in.p1);
     if (a.w == 0.0f || b.w == 0.0f) return false;
     // the fields of make_seg that the tile tests read, computed the same way
     Seg &sg = st.sg;
@@ -410,10 +427,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                 cnt[x] = 0;
             }
             __syncthreads();
+            SegIn nxt = seg_load(pos_w, flags, scene_off, rk, base + threadIdx.x, n);
             for (uint32_t sub = 0; sub < nsub; ++sub) {
                 const uint32_t v = base + sub * blockDim.x + threadIdx.x;
+                const SegIn cur = nxt;
+                if (sub + 1 < nsub) nxt = seg_load(pos_w, flags, scene_off, rk, v + blockDim.x, n);
                 SegTiles st;
-                bool ok = seg_tiles<true>(proj, proj, pos_w, cams, flags, scene_off, rk, v, n, st);
+                bool ok = seg_tiles(cur, cams, proj, rk, v, n, st);
                 if (ok && st.nt > kmax) {
                     long_list[atomicAdd(&counters[0], 1u)] = v;
                     ok = false;
@@ -452,10 +472,14 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                 if (t != BIN_FREE) basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], sv[BIN_SLOTS + x]);
             }
             __syncthreads();
+            // records loaded one step ahead (see SegIn)
+            const uint2 none = make_uint2(BIN_NONE, 0u);
+            uint2 nrec = base + threadIdx.x < nu ? segrec[base + threadIdx.x] : none;
             for (uint32_t sub = 0; sub < nsub; ++sub) {
                 const uint32_t v = base + sub * blockDim.x + threadIdx.x;
+                const uint2 rec = nrec;
+                if (sub + 1 < nsub) nrec = v + blockDim.x < nu ? segrec[v + blockDim.x] : none;
                 if (v >= nu) continue;
-                const uint2 rec = segrec[v];
                 if (rec.x == BIN_NONE) continue;
                 const uint32_t bw = rec.y & 0xFFu;
                 uint32_t mask = rec.y >> 8;
