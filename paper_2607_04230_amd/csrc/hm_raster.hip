@@ -150,6 +150,39 @@ __device__ __forceinline__ bool load_seg(const float4 *proj, const uint8_t *flag
     return true;
 }
 
+// Stream inputs of one bin entry's segment (unit u, stream point v): loaded
+// one batch ahead by the tile raster.  proj[u + 1] is read only when v + 1 is
+// a stream point; seg_from gives what load_seg gives for the same unit.
+struct EntryIn {
+    float4 a, b;
+    uint32_t v;
+    uint8_t f;
+};
+
+__device__ __forceinline__ EntryIn entry_load(const float4 *proj, const uint8_t *flags,
+                                              const uint32_t *scene_off, const RasterK &rk,
+                                              uint32_t n, uint32_t u)
+{
+    EntryIn in;
+    uint32_t s;
+    unit_map(scene_off, rk, n, u, s, in.v);
+    in.f = flags[in.v];
+    in.a = in.b = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (in.v + 1 < n) {
+        in.a = proj[u];
+        in.b = proj[u + 1];
+    }
+    return in;
+}
+
+__device__ __forceinline__ bool seg_from(const EntryIn &in, uint32_t n_cp, float r_min, Seg &sg)
+{
+    if (in.v + 1 >= n_cp || (in.f & HM_TIP)) return false;
+    if (in.a.w == 0.0f || in.b.w == 0.0f) return false;
+    sg = make_seg(in.a, in.b, r_min);
+    return true;
+}
+
 __device__ __forceinline__ void scene_depth_consts(const hm_camera *cams, uint32_t s, float &zn,
                                                    float &inv_range)
 {
@@ -757,17 +790,27 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             __syncthreads();
         }
 
+        // each batch's stream inputs are loaded during the previous batch:
+        // its entry (segment unit) at the start, the screen records and flags
+        // once the previous batch's records are built, so that both latencies
+        // overlap the previous batch's pixel work
+        uint32_t nx_u = 0;
+        EntryIn nx{};
+        if (beg + threadIdx.x < end) {
+            nx_u = entries[beg + threadIdx.x];
+            nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
+        }
         for (uint32_t e0 = beg; e0 < end; e0 += nb) {
             const uint32_t e = e0 + threadIdx.x;
+            const EntryIn cur = nx;
+            const bool more = e0 + nb < end;
+            if (more && e + nb < end) nx_u = entries[e + nb];
             uint32_t nr = 0, vu = 0;
             Seg sg;
             int i0, i1, j0, j1;
             if (e < end) {
-                const uint32_t u = entries[e];                  // segment unit
-                uint32_t su;
-                unit_map(scene_off, rk, n, u, su, vu);
-                if (load_seg(proj, flags, u, vu, n, rk.r_min, sg) &&
-                    seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
+                vu = cur.v;
+                if (seg_from(cur, n, rk.r_min, sg) && seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
                     j0 = max(j0, py0);
                     j1 = min(j1, py1);
                     i0 = max(i0, px0);
@@ -793,6 +836,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                 if (FLAT) atomicOr(&bmp[r0 >> 5], 1u << (r0 & 31u));
             }
             __syncthreads();
+            if (more && e + nb < end) nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
             if (FLAT) {
                 // contiguous 64-slot groups per wave, so that the count of
                 // segments starting before a group carries from one to the next
