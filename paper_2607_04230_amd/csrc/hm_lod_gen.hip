@@ -315,7 +315,7 @@ struct GenK {
 // LDS, then every lane evaluates control points (Hermite + curl) from LDS and
 // stores them coalesced.  Strands are processed in chunks that fit the LDS
 // budget.
-constexpr uint32_t GEN_LDS_FLOATS = 6144;   // 24 KB
+constexpr uint32_t GEN_LDS_FLOATS = 4096;   // 16 KB: ten workgroups fit a CU
 
 // Raster side of the fused generate + raster kernel.
 struct FuseK {
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
     const uint32_t limit = total < cap ? total : cap;
     const uint32_t NL = m.n_layers;
     const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
-    uint32_t chunk = SM_FLOATS / stride;     // >= 3 (WAVE) / 15 strands for L <= 64
+    uint32_t chunk = SM_FLOATS / stride;     // >= 2 (WAVE) / 10 strands for L <= 64
     // screen records of a chunk stay in LDS when a strand fits (C <= 256
     // (WAVE) / 1024); longer strands are projected again from the stream
     // they were just written to (same bits, no LDS limit)
