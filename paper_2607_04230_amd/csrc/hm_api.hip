@@ -28,6 +28,15 @@ uint32_t stride_grid(size_t n, uint32_t block)
     return (uint32_t)g;
 }
 
+uint32_t full_grid(size_t n, uint32_t block)
+{
+    size_t g = (n + block - 1) / block;
+    const size_t cap = size_t(1) << 20;  // grid-stride kernels cover what lies beyond
+    if (g > cap) g = cap;
+    if (g < 1) g = 1;
+    return (uint32_t)g;
+}
+
 // ------------------------------------------------------------------ kernel timing
 struct TimedRec {
     std::string name;

@@ -78,6 +78,9 @@ void launch_dom_shadow(const hm_strands &s, const uint64_t *vis, const hm_camera
 
 // number of workgroups for grid-stride kernels
 uint32_t stride_grid(size_t n, uint32_t block);
+// one thread per item (up to 2^20 workgroups), for latency-bound grid-stride
+// kernels that gain from every resident wave having a single item
+uint32_t full_grid(size_t n, uint32_t block);
 
 }  // namespace hm
 

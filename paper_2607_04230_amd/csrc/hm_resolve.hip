@@ -480,13 +480,13 @@ void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *c
         return;
     }
     if (k.mode == HM_RESOLVE_CENTER) {
-        hipLaunchKernelGGL(k_shade, dim3(stride_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
+        hipLaunchKernelGGL(k_shade, dim3(full_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
                            (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k,
                            (float4 *)nullptr, o);
         return;
     }
     float4 *rec = reinterpret_cast<float4 *>(ws);
-    hipLaunchKernelGGL(k_shade, dim3(stride_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
+    hipLaunchKernelGGL(k_shade, dim3(full_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
                        (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k, rec,
                        (float4 *)nullptr);
     const uint32_t tiles = ((f.width + FT - 1) / FT) * ((f.height + FT - 1) / FT) * f.n_scenes;
