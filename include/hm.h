@@ -77,8 +77,10 @@ typedef struct {
     const uint32_t *bundle_key;      /* [n_bundles] hash key: strand k of a bundle is
                                         determined by (seed, key, k) */
     const uint32_t *bundle_nstrands; /* [n_bundles] full strand count N_b */
-    const uint32_t *bundle_cmax;     /* [n_bundles] control points per strand (>= 2):
-                                        the cap C_max of eq. cp-lod, or the count when LOD is off */
+    const uint32_t *bundle_cmax;     /* [n_bundles] control points per strand: the cap
+                                        C_max of eq. cp-lod, or the count when LOD is off;
+                                        values below 2 are taken as 2 (a strand has at
+                                        least one segment) */
     const uint32_t *bundle_scene;    /* [n_bundles] scene index < n_scenes */
     uint32_t n_bundles;              /* >= 1 */
     uint32_t n_layers;               /* 2 .. 64 */

@@ -157,7 +157,9 @@ int orc_lod_select(const float *layer_pos, const uint32_t *quads, uint32_t n_bun
 {
     uint64_t s_off = 0, c_off = 0;
     for (uint32_t b = 0; b < n_bundles; ++b) {
-        uint32_t N = bundle_nstrands[b], cmax = bundle_cmax[b];
+        /* a strand has at least one segment: fewer than two control points per
+         * strand are taken as two */
+        uint32_t N = bundle_nstrands[b], cmax = bundle_cmax[b] < 2u ? 2u : bundle_cmax[b];
         uint32_t n = N, cp = cmax;
         if (mode == 1 && N > 0) {
             const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)bundle_scene[b]);
@@ -1118,7 +1120,7 @@ int orc_raster_gbuf(const float *pos_w, const float *rgb, const uint8_t *flags,
         float inv_range = 1.0f / (c->zfar - c->znear);
         float a[4], b[4];
         if (!orc_proj(c, pos_w + 4 * v, a) || !orc_proj(c, pos_w + 4 * (v + 1), b)) continue;
-        float iz1 = a[3] + (b[3] - a[3]);
+        float iz1 = b[3];     /* 1/z of the segment's second endpoint */
         uint64_t *v0 = vis + (size_t)s * 2 * npix, *v1 = v0 + npix;
         float ra = 0.5f * (a[2] > b[2] ? a[2] : b[2]);
         ra = ra > r_min ? ra : r_min;

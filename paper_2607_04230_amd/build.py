@@ -18,8 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhm.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["hm_api.hip", "hm_lod_gen.hip", "hm_raster.hip", "hm_resolve.hip", "hm_batch.hip",
-           "hm_microbench.hip"]
+SOURCES = ["hm_api.hip", "hm_lod_gen.hip", "hm_raster.hip", "hm_resolve.hip", "hm_microbench.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HM_OFFLOAD_ARCH", "gfx950")
@@ -45,7 +44,10 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise RuntimeError(f"missing HIP sources: {missing}")
+    srcs = list(SOURCES)
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"

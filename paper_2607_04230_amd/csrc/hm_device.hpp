@@ -106,6 +106,7 @@ struct Seg {
     float sxmn, sxmx, symn, symx;
     float idy;              // 1/dy for candidate enumeration (0 when |dy| <= 1e-3)
     float e;                // slack of candidate enumeration against binary32 rounding
+    float iz1;              // 1/z of the second endpoint (G-buffer payload parameter)
 };
 
 // Slack of candidate enumeration: 0.05 px, widened by ~8 ulp of the largest
@@ -134,6 +135,7 @@ __device__ __forceinline__ Seg make_seg(float4 a, float4 b, float r_min)
     s.symn = fminx(a.y, b.y); s.symx = fmaxx(a.y, b.y);
     s.idy = fabsf(s.dy) > 1e-3f ? 1.0f / s.dy : 0.0f;
     s.e = seg_slack(s);
+    s.iz1 = b.w;
     return s;
 }
 

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_raster_direct(const float4 *proj, const
                 const bool msk = cover_tz(sg, i, j, rk.r_min, zn, inv_range, cc, ca, q, ts, z);
                 if (!msk) continue;
                 const uint64_t low =
-                    GB ? gb_payload(gk.tan, gk.rgb, v, ts, z, sg.iz0 + sg.diz) : (uint64_t)v;
+                    GB ? gb_payload(gk.tan, gk.rgb, v, ts, z, sg.iz1) : (uint64_t)v;
                 const uint64_t key = ((uint64_t)q << HM_ID_BITS) | low;
                 const size_t p = (size_t)j * rk.W + i;
                 if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
@@ -592,25 +592,30 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint3
 // ------------------------------------------------------------------ tiled raster
 // Per-segment records of a batch, struct of arrays with stride nb (fields a
 // caller does not use are not read: the loads are plain LDS reads): the 16
-// geometric fields of Seg (the slack e is recomputed from them), then the
-// stream id, then the segment's first row slot (15 bits: at most 1024 * 32
-// slots) with its row / column clip inside the tile (5 bits each, T <= 32):
+// geometric fields of Seg (the slack e is recomputed from them), with
+// G-buffer keys also 1/z of the second endpoint, then the stream id, then the
+// segment's first row slot (15 bits: at most 1024 * 32 slots) with its row /
+// column clip inside the tile (5 bits each, T <= 32):
 // slot | (j0 - py0) << 15 | (i0 - px0) << 20 | (i1 - px0) << 25.
 constexpr uint32_t REC_FLOATS = 16;
-constexpr uint32_t REC_WORDS = REC_FLOATS + 2;
+__host__ __device__ constexpr uint32_t rec_floats(bool gb) { return gb ? REC_FLOATS + 1 : REC_FLOATS; }
+__host__ __device__ constexpr uint32_t rec_words(bool gb) { return rec_floats(gb) + 2; }
 __device__ __forceinline__ uint32_t rc_slot(uint32_t rc) { return rc & 0x7FFFu; }
 __device__ __forceinline__ int rc_j0(uint32_t rc) { return (int)((rc >> 15) & 31u); }
 __device__ __forceinline__ int rc_i0(uint32_t rc) { return (int)((rc >> 20) & 31u); }
 __device__ __forceinline__ int rc_i1(uint32_t rc) { return (int)(rc >> 25); }
 
+template <bool GB>
 __device__ __forceinline__ void rec_store(float *rf, uint32_t nb, uint32_t k, const Seg &s)
 {
     const float f[REC_FLOATS] = {s.x0,    s.y0, s.w0,   s.iz0,  s.dx,   s.dy,   s.dw,   s.diz,
                                  s.len2, s.ilen2, s.ra, s.sxmn, s.sxmx, s.symn, s.symx, s.idy};
 #pragma unroll
     for (uint32_t i = 0; i < REC_FLOATS; ++i) rf[i * nb + k] = f[i];
+    if (GB) rf[REC_FLOATS * nb + k] = s.iz1;
 }
 
+template <bool GB>
 __device__ __forceinline__ Seg rec_load(const float *rf, uint32_t nb, uint32_t k)
 {
     Seg s;
@@ -620,6 +625,7 @@ __device__ __forceinline__ Seg rec_load(const float *rf, uint32_t nb, uint32_t k
     s.sxmn = rf[11 * nb + k]; s.sxmx = rf[12 * nb + k]; s.symn = rf[13 * nb + k];
     s.symx = rf[14 * nb + k]; s.idy = rf[15 * nb + k];
     s.e = seg_slack(s);
+    s.iz1 = GB ? rf[REC_FLOATS * nb + k] : 0.0f;
     return s;
 }
 
@@ -658,9 +664,9 @@ constexpr uint32_t PIX_WINDOW = 256;
 // the row-start bitmap (block * T bits) and each wave's window of pixel
 // descriptors (one word each).  T = 32 with 256 threads takes 39936 B, so
 // four workgroups fit a CU's 160 KiB.
-static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat)
+static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat, bool gb)
 {
-    uint32_t b = 2u * T * T * 8u + block * 4u * REC_WORDS;
+    uint32_t b = 2u * T * T * 8u + block * 4u * rec_words(gb);
     if (flat) b += block * T / 8u + (block / 64u) * PIX_WINDOW * 4u;
     return b;
 }
@@ -723,7 +729,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
     uint32_t *q0t = reinterpret_cast<uint32_t *>(lds), *cnt = q0t + TT;    // DOM only
     float *rf = reinterpret_cast<float *>(lds) + tile_words(TT, DOM, dk.n_layers);
     uint32_t *rw = reinterpret_cast<uint32_t *>(rf);
-    uint32_t *r_sid = rw + REC_FLOATS * nb;          // stream id
+    uint32_t *r_sid = rw + rec_floats(GB) * nb;      // stream id
     uint32_t *r_rc = r_sid + nb;                     // first row slot + clip
     // per-pixel spread only
     const uint32_t wv = threadIdx.x >> 6;
@@ -829,7 +835,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
             const uint32_t tot = totp & 0xFFFFu, nseg = totp >> 16;
             if (nr) {
                 const uint32_t c = pre >> 16, r0 = pre & 0xFFFFu;
-                rec_store(rf, nb, c, sg);
+                rec_store<GB>(rf, nb, c, sg);
                 r_sid[c] = vu;
                 r_rc[c] = r0 | ((uint32_t)(j0 - py0) << 15) | ((uint32_t)(i0 - px0) << 20) |
                           ((uint32_t)(i1 - px0) << 25);
@@ -861,7 +867,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     before += (uint32_t)__popcll(M);
                     uint32_t c = 0, d0 = 0;
                     if (rr < tot) {
-                        const Seg sr = rec_load(rf, nb, o);
+                        const Seg sr = rec_load<GB>(rf, nb, o);
                         const uint32_t rc = r_rc[o];
                         const int j = py0 + rc_j0(rc) + (int)(rr - rc_slot(rc));
                         int a0, a1;
@@ -888,7 +894,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                 const uint32_t ow = d & 0xFFu;
                                 const int j = py0 + (int)((d >> 8) & 31u);
                                 const int i = px0 + (int)(d >> 13);
-                                const Seg sp = rec_load(rf, nb, ow);
+                                const Seg sp = rec_load<GB>(rf, nb, ow);
                                 uint32_t q;
                                 bool cc, ca;
                                 float ts, z;
@@ -900,8 +906,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                                     if (ca) dom_count(cnt, q0t, x, TT, q, dk);
                                 } else if (msk) {
                                     const uint64_t low =
-                                        GB ? gb_payload(gk.tan, gk.rgb, r_sid[ow], ts, z,
-                                                        sp.iz0 + sp.diz)
+                                        GB ? gb_payload(gk.tan, gk.rgb, r_sid[ow], ts, z, sp.iz1)
                                            : (uint64_t)r_sid[ow];
                                     const unsigned long long key =
                                         ((unsigned long long)q << HM_ID_BITS) | low;
@@ -933,7 +938,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                     while (ow + 1 < nseg && rc_slot(r_rc[ow + 1]) <= rr) ++ow;
                     if (ow != cur) {
                         cur = ow;
-                        sr = rec_load(rf, nb, ow);
+                        sr = rec_load<GB>(rf, nb, ow);
                         vo = r_sid[ow];
                         rc = r_rc[ow];
                         jb = py0 + rc_j0(rc);
@@ -957,7 +962,7 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                         }
                         if (!msk) continue;
                         const uint64_t low =
-                            GB ? gb_payload(gk.tan, gk.rgb, vo, ts, z, sr.iz0 + sr.diz)
+                            GB ? gb_payload(gk.tan, gk.rgb, vo, ts, z, sr.iz1)
                                : (uint64_t)vo;
                         const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
                         if (cc) atomicMin((unsigned long long *)&lc[x], key);
@@ -1040,7 +1045,7 @@ __global__ __launch_bounds__(256) void k_raster_long(const float4 *proj, const u
                 }
                 if (!msk) continue;
                 const uint64_t low =
-                    GB ? gb_payload(gk.tan, gk.rgb, v, ts, z, sg.iz0 + sg.diz) : (uint64_t)v;
+                    GB ? gb_payload(gk.tan, gk.rgb, v, ts, z, sg.iz1) : (uint64_t)v;
                 const uint64_t key = ((uint64_t)q << HM_ID_BITS) | low;
                 if (cc) atomicMin((unsigned long long *)(vc + p), (unsigned long long)key);
                 if (ca) atomicMin((unsigned long long *)(va + p), (unsigned long long)key);
@@ -1156,7 +1161,8 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
 
 uint32_t raster_lds_bytes(const hm_raster_params &p)
 {
-    return tile_lds_bytes(p.tile, p.block, p.algo == HM_RASTER_TILED);
+    return tile_lds_bytes(p.tile, p.block, p.algo == HM_RASTER_TILED,
+                          p.payload == HM_PAYLOAD_GBUFFER);
 }
 
 size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p)
@@ -1322,7 +1328,7 @@ void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_
                        (uint32_t)n, w.counters);
     const DomK dk{counts, p.layer_codes, p.n_layers};
     const uint32_t TT = rp.tile * rp.tile;
-    const uint32_t lds = tile_lds_bytes(rp.tile, rp.block, true) - 4u * TT * 4u +
+    const uint32_t lds = tile_lds_bytes(rp.tile, rp.block, true, false) - 4u * TT * 4u +
                          tile_words(TT, true, p.n_layers) * 4u;
     hipLaunchKernelGGL((k_raster_tiles<true, 256, true, false>), dim3(256u * 8u), dim3(256), lds,
                        st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light,
