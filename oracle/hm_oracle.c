@@ -30,6 +30,12 @@
  *     conservative; key = depth24 << 40 | segment id (the CP index of the
  *     segment's first endpoint); empty = all ones; opaque scene depth uses the
  *     id 2^40 - 2.
+ *
+ * Parity unpinned: the exact output bits of orc_pcg (the published PCG hash,
+ *   pinned only by bijectivity, avalanche and uniformity) and the curl styling
+ *   of orc_generate (the paper leaves the styling function unstated; pinned as
+ *   a helix of the stated radius and phase).  Every other function is pinned
+ *   by the tests/test_oracle_*.py checks.
  */
 #include <math.h>
 #include <stdint.h>

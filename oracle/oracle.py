@@ -7,8 +7,11 @@ hash, LOD, strand generation, rasterization and the filtered resolve, and this
 file adds the soft-coverage resolve in binary64 with plain torch CPU ops, whose
 autograd gradient is the reference gradient.
 
-Functions with no independent pin are marked "parity unpinned" below; at the
-time of writing there are none (see tests/test_oracle_*.py for the pins).
+Pins of every function are in tests/test_oracle_*.py.  Parity unpinned: the
+exact bits of the PCG hash in hm_oracle.c (written from its published
+definition; pinned only by bijectivity, avalanche and uniformity) and the
+curl styling function, which the paper leaves unstated (a reading, pinned as
+a helix of the stated radius and phase).
 """
 from __future__ import annotations
 
