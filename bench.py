@@ -36,9 +36,6 @@ GEN_BYTES_PER_CP = 16 + 16 + 1            # pos_w + rgb + flags written
 PROJ_BYTES_PER_CP = 16 + 16               # pos_w read, screen record written
 RASTER_BYTES_PER_SEG = 17                 # 16 B screen record + 1 B flags per CP
 FILTER_FLOPS_PER_TAP = 30
-# lane operations of one candidate-pixel evaluation of the raster: the centre
-# and conservative predicates, the closest-point depth and its 24-bit code
-RASTER_OPS_PER_PAIR = 64
 
 
 def _cpu_model():
@@ -52,33 +49,53 @@ def _cpu_model():
     return platform.processor() or "unknown"
 
 
-def cpu_baseline(sc, seconds: float):
-    """The CPU oracle (single-threaded C) on whole frames of the same workload,
-    repeated until `seconds` of work have run (at least one frame)."""
+def cpu_baseline(sc, seconds: float, all_core_seconds: float):
+    """The CPU oracle (plain C) on whole frames of the same workload, repeated
+    until `seconds` of work have run (at least one frame): single-threaded, and
+    with its raster segment loop (compare-and-swap minimum) and resolve rows on
+    every core of this process's CPU share, checked bit for bit against the
+    single-threaded buffer."""
+    import numpy as np
     from oracle import oracle as O
     from paper_2607_04230_amd.scenes import ResolveParams
     rp = ResolveParams()
-    frames, segs = 0, 0
-    t0 = time.perf_counter()
-    while True:
-        table, soff, (ns, ncp) = O.lod_select(sc)
-        pos, rgb, fl = O.generate(sc, table, ncp)
-        vis = O.raster(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
-        O.resolve(pos, rgb, fl, vis, sc.cams, sc.width, sc.height, rp, sc.mode, sc.bg)
-        frames += 1
-        segs += ncp - ns
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return {"value": segs / el, "unit": "segments/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} whole frame(s) of the full-head 1080p workload "
-                      f"(LOD table, generation, raster, filtered resolve), {el:.1f} s",
-            "ms_per_frame": 1e3 * el / frames, "cpu": _cpu_model()}
+
+    def frames(limit, n_threads):
+        n, segs, vis = 0, 0, None
+        t0 = time.perf_counter()
+        with O.threads(n_threads):
+            while True:
+                table, soff, (ns, ncp) = O.lod_select(sc)
+                pos, rgb, fl = O.generate(sc, table, ncp)
+                vis = O.raster(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min,
+                               sc.scene_z)
+                O.resolve(pos, rgb, fl, vis, sc.cams, sc.width, sc.height, rp, sc.mode, sc.bg)
+                n += 1
+                segs += ncp - ns
+                el = time.perf_counter() - t0
+                if el >= limit:
+                    return n, segs, el, vis
+
+    n1, s1, e1, v1 = frames(seconds, 1)
+    cores = O.host_threads()
+    nN, sN, eN, vN = frames(all_core_seconds, cores)
+    sample = ("whole frames of the full-head 1080p workload (LOD table, generation, raster, "
+              "filtered resolve)")
+    return {"value": s1 / e1, "unit": "segments/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n1} {sample}, {e1:.1f} s", "ms_per_frame": 1e3 * e1 / n1,
+            "cpu": _cpu_model(), "nproc": os.cpu_count(),
+            "all_cores": {"value": sN / eN, "unit": "segments/s", "cores": cores,
+                          "kind": "oracle, raster segment loop and resolve rows threaded "
+                                  "(compare-and-swap minimum)",
+                          "sample": f"{nN} {sample}, {eN:.1f} s",
+                          "ms_per_frame": 1e3 * eN / nN,
+                          "vis_equal_to_one_core": bool(np.array_equal(v1, vN))}}
 
 
-def _traffic(kernel: str):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source."""
+def _counters(kernel: str):
+    """Per-launch hardware counters of `kernel` from the committed rocprofv3
+    summaries (profiles/traffic.json), if they were taken on the current
+    kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -94,7 +111,13 @@ def _traffic(kernel: str):
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
     if sha != rec.get("source_sha"):
         return None
-    return rec["bytes_per_launch"]
+    return rec
+
+
+def _traffic(kernel: str):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, calibrated), or None."""
+    rec = _counters(kernel)
+    return None if rec is None else rec.get("bytes_per_launch")
 
 
 def work_counts() -> dict:
@@ -126,26 +149,34 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
         # pixel two 16 B control points and two colours gathered
         b = vis_bytes + vis_bytes + hair_px * 64
     elif kernel in ("k_raster_tiles", "k_raster_direct"):
-        # issue-bound: one predicate evaluation per conservatively covered
-        # (segment, pixel) pair, counted exactly by the oracle offline
-        pairs = work_counts().get(workload, {}).get("conservative_pairs")
-        hbm = (n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes) / s / 1e9
-        if pairs:
-            ach = pairs * RASTER_OPS_PER_PAIR / s / 1e12
-            r = {"bound": "alu", "achieved": ach, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                 "frac": ach / PEAK_VALU_TOPS, "traffic": _traffic(kernel),
-                 "pairs_per_s": pairs / s, "hbm_GBs": hbm, "hbm_frac": hbm / PEAK_HBM_GBS}
-            # the atomic roofline: one LDS 64-bit min per covered (segment,
-            # pixel, layer), against the measured peak of that operation
-            centre = work_counts().get(workload, {}).get("centre_pairs")
-            if centre and ATOMIC_PEAKS:
-                rate = (pairs + centre) / s
-                r.update({"lds_atomic_per_s": rate,
-                          "lds_atomic_peak_per_s": ATOMIC_PEAKS["lds"],
-                          "lds_atomic_frac": rate / ATOMIC_PEAKS["lds"],
-                          "global_atomic_peak_per_s": ATOMIC_PEAKS["global"]})
-            return r
+        # algorithmic work: 17 B per segment (screen record + flags) plus one
+        # read and one write of the two-layer buffer from HBM, and one 64-bit
+        # atomic minimum per covered (segment, pixel, layer) -- counted exactly
+        # by the oracle offline; the binding one of the two is reported
+        wc = work_counts().get(workload, {})
         b = n_seg * RASTER_BYTES_PER_SEG + 2 * vis_bytes
+        hbm = b / s / 1e9
+        r = {"bound": "hbm", "achieved": hbm, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+             "frac": hbm / PEAK_HBM_GBS, "traffic": _traffic(kernel),
+             "algorithmic_bytes": b, "hbm_frac": hbm / PEAK_HBM_GBS}
+        pairs, centre = wc.get("conservative_pairs"), wc.get("centre_pairs")
+        if pairs and centre and ATOMIC_PEAKS:
+            rate = (pairs + centre) / s
+            fr = rate / ATOMIC_PEAKS["lds"]
+            r.update({"lds_atomics": pairs + centre, "lds_atomic_per_s": rate,
+                      "lds_atomic_peak_per_s": ATOMIC_PEAKS["lds"], "lds_atomic_frac": fr,
+                      "global_atomic_peak_per_s": ATOMIC_PEAKS["global"],
+                      "pairs_per_s": pairs / s})
+            if fr > r["frac"]:
+                r.update({"bound": "lds_atomic", "achieved": rate,
+                          "peak": ATOMIC_PEAKS["lds"], "unit": "atomic/s", "frac": fr})
+        rec = _counters(kernel)
+        if rec and rec.get("valu_insts_per_launch"):
+            # VALU issue: wave64 VALU instructions (SQ_INSTS_VALU) against one
+            # per CU per cycle (four 16-lane SIMDs, four cycles per wave64 op)
+            r["valu_issue_frac"] = rec["valu_insts_per_launch"] / (PEAK_VALU_TOPS * 1e12 / 64
+                                                                    * s)
+        return r
     elif kernel == "k_prefill":
         b = vis_bytes
     else:
@@ -386,7 +417,92 @@ def extra_shadow(steps):
     return r
 
 
+# library kernels of the full-head frame -> the source file that holds them
+KERNEL_SOURCES = {
+    "k_raster_tiles": "paper_2607_04230_amd/csrc/hm_raster.hip",
+    "k_bin": "paper_2607_04230_amd/csrc/hm_raster.hip",
+    "k_prefill": "paper_2607_04230_amd/csrc/hm_raster.hip",
+    "k_raster_long": "paper_2607_04230_amd/csrc/hm_raster.hip",
+    "k_plan_small": "paper_2607_04230_amd/csrc/hm_raster.hip",
+    "k_shade": "paper_2607_04230_amd/csrc/hm_resolve.hip",
+    "k_filter": "paper_2607_04230_amd/csrc/hm_resolve.hip",
+    "k_generate_bundle": "paper_2607_04230_amd/csrc/hm_lod_gen.hip",
+    "k_lod_small": "paper_2607_04230_amd/csrc/hm_lod_gen.hip",
+}
+
+
+def _read_counter_csv(d: str):
+    """{(kernel short name, dispatch): {counter: value}} from a rocprofv3
+    counter-collection CSV under directory d."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    out = {}
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                name = row["Kernel_Name"]
+                short = name.split("<")[0].split("(")[0].split("::")[-1].strip()
+                key = (short, row.get("Dispatch_Id") or row.get("Correlation_Id"))
+                c = out.setdefault(key, {})
+                c[row["Counter_Name"]] = c.get(row["Counter_Name"], 0.0) + float(
+                    row["Counter_Value"])
+    return out
+
+
+def summarize_counters(fetch_dir: str, write_dir: str, valu_dir: str = None):
+    """Per-launch HBM bytes (FETCH_SIZE and WRITE_SIZE in KiB, each scaled by
+    what it reads for the known-size read-only / write-only kernels) and VALU
+    instructions of the library's kernels from three rocprofv3 --pmc runs of
+    `bench.py --profile`; writes profiles/traffic.json keyed by kernel with the
+    hash of its source file, and prints a markdown table."""
+    def per_kernel(d, counter):
+        acc = {}
+        for (k, _), c in _read_counter_csv(d).items():
+            if counter in c:
+                acc.setdefault(k, []).append(c[counter])
+        return {k: sum(v) / len(v) for k, v in acc.items()}
+    fetch = per_kernel(fetch_dir, "FETCH_SIZE")
+    write = per_kernel(write_dir, "WRITE_SIZE")
+    valu = per_kernel(valu_dir, "SQ_INSTS_VALU") if valu_dir else {}
+    known_kib = 256 * 1024
+    fscale = known_kib / fetch["k_bench_read"]
+    wscale = known_kib / write["k_bench_write"]
+    tab = {"_calibration": {
+        "read_only_kernel": "k_bench_read", "write_only_kernel": "k_bench_write",
+        "known_kib": known_kib, "fetch_kib_read": fetch["k_bench_read"],
+        "write_kib_write": write["k_bench_write"], "fetch_kib_of_write_kernel":
+            fetch.get("k_bench_write"), "write_kib_of_read_kernel": write.get("k_bench_read"),
+        "fetch_scale": fscale, "write_scale": wscale}}
+    print(f"calibration: FETCH_SIZE {fetch['k_bench_read']:.0f} KiB for {known_kib} KiB read "
+          f"(scale {fscale:.3f}); WRITE_SIZE {write['k_bench_write']:.0f} KiB for {known_kib} "
+          f"KiB written (scale {wscale:.3f})")
+    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM MB (read + write) | "
+          "SQ_INSTS_VALU |")
+    print("|---|---|---|---|---|")
+    for k, src in KERNEL_SOURCES.items():
+        if k not in fetch or k not in write:
+            continue
+        with open(os.path.join(ROOT, src), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()[:16]
+        b = (fetch[k] * fscale + write[k] * wscale) * 1024
+        tab[k] = {"source": src, "source_sha": sha, "bytes_per_launch": b,
+                  "fetch_kib": fetch[k], "write_kib": write[k], "fetch_scale": fscale,
+                  "write_scale": wscale, "valu_insts_per_launch": valu.get(k)}
+        v = valu.get(k)
+        print(f"| {k} | {fetch[k]:.1f} | {write[k]:.1f} | {b / 1e6:.1f} | "
+              f"{'' if v is None else f'{v:.4g}'} |")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
+        json.dump(tab, f, indent=1)
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--counters":
+        # python bench.py --counters FETCH_DIR WRITE_DIR [VALU_DIR]
+        summarize_counters(*sys.argv[2:5])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
@@ -417,12 +533,20 @@ def main():
     if args.profile:
         for _ in range(args.warmup + args.steps):
             ds.render()
-        # known-size reference for the byte counters: reads 256 MiB, writes 256 MiB
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
-        print("[bench] profile mode done: frames + one 256 MiB copy", file=sys.stderr)
+        # known-size traffic for the byte counters: a 256 MiB buffer written
+        # before a 512 MiB scrub (which evicts it from the L2s and the 256 MiB
+        # Infinity Cache), read once by a read-only kernel (k_bench_read), then
+        # overwritten once by a write-only kernel (k_bench_write)
+        buf = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        scrub = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+        sink = torch.empty(2048, dtype=torch.int32, device="cuda")
+        scrub.fill_(1.0)
+        hm.bench_traffic(0, buf, sink)
+        hm.bench_traffic(1, buf, sink)
+        torch.cuda.synchronize()
+        print("[bench] profile mode done: frames + 256 MiB read-only and write-only passes",
+              file=sys.stderr)
         return
     print(f"[bench] workload built: {sc.n_full_strands} strands, {sc.n_seg_full} segments, "
           f"{sc.width}x{sc.height}", file=sys.stderr, flush=True)
@@ -548,7 +672,7 @@ def main():
             line[name] = fn(max(args.steps // 2, 5))
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds, args.cpu_seconds / 2)
     print(json.dumps(line), flush=True)
 
 

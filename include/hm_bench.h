@@ -4,7 +4,8 @@
  * 64-bit atomic minimum in LDS and merges split tiles with 64-bit global
  * atomic minima (Sec. 3.1.2's atomic-min visibility buffer); these kernels
  * measure the device's peak rates of those two operations so that the
- * benchmark can place the raster against them. */
+ * benchmark can place the raster against them; the known-size streams
+ * calibrate the profiler's HBM byte counters. */
 #ifndef HM_BENCH_H
 #define HM_BENCH_H
 
@@ -27,6 +28,17 @@ extern "C" {
  * launch failed.  Atomics performed: grid * 256 * iters. */
 hm_status hm_bench_atomics(int32_t kind, uint64_t *buf, size_t n_words, uint32_t iters,
                            uint32_t grid, void *stream);
+
+/* Enqueue grid workgroups of 256 threads streaming `bytes` (a multiple of 16)
+ * of the device buffer buf once, on `stream`:
+ * kind 0: read only (16 B per lane per step); sink (device, at least grid
+ *   32-bit words) receives one word per workgroup;
+ * kind 1: write only, buf is overwritten.
+ * Known-size traffic for calibrating the profiler's byte counters (FETCH_SIZE,
+ * WRITE_SIZE).  Returns HM_ERR_INVALID for bad arguments, HM_ERR_HIP if the
+ * launch failed. */
+hm_status hm_bench_traffic(int32_t kind, void *buf, size_t bytes, uint32_t *sink, uint32_t grid,
+                           void *stream);
 
 #ifdef __cplusplus
 }

@@ -56,6 +56,14 @@ typedef struct {
     float fx, fy, cx, cy, znear, zfar;
 } orc_cam;
 
+/* Threads of the raster's segment loop and of the resolve's pixel rows (1 =
+ * the plain sequential loops).  Neither result depends on it: the resolve's
+ * pixels are independent, and the raster keeps each pixel's minimum with a
+ * compare-and-swap, so the order in which threads meet a pixel is invisible. */
+static int orc_nthreads = 1;
+void orc_set_threads(int n) { orc_nthreads = n > 1 ? n : 1; }
+int orc_get_threads(void) { return orc_nthreads; }
+
 /* ------------------------------------------------------------------ hashing
  * Per-strand uv "from a PCG generator seeded by the strand index" (Sec. 3.1.1,
  * Code 1).  The PCG hash of Jarzynski and Olano (JCGT 2020, "Hash functions
@@ -488,6 +496,73 @@ int orc_cover_export(const float a[4], const float b[4], int i, int j, float r_m
  * 64-bit atomic-min replaced by its definition).  brute != 0 tests every
  * pixel against every segment; otherwise only the segment's dilated bounding
  * box.  `order`, if given, is a permutation of segment ids to visit. */
+/* vis = min(vis, key) as one atomic step: compare-and-swap until the stored
+ * key is not larger (threaded raster only). */
+static void orc_atomic_min(uint64_t *p, uint64_t key)
+{
+    uint64_t cur = __atomic_load_n(p, __ATOMIC_RELAXED);
+    while (key < cur &&
+           !__atomic_compare_exchange_n(p, &cur, key, 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED)) {
+    }
+}
+
+/* Scene of stream point v: the s with scene_off[s] <= v < scene_off[s + 1]. */
+static uint32_t orc_scene_of(const uint32_t *scene_off, uint32_t n_scenes, uint64_t v)
+{
+    uint32_t lo = 0, hi = n_scenes - 1;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi + 1) / 2;
+        if (v >= scene_off[mid]) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+/* Segment v of scene s into the two layers over its dilated bounding box
+ * (optionally clipped to window win); atomic != 0 takes each minimum with
+ * orc_atomic_min. */
+static void orc_raster_seg(const float *pos_w, uint64_t v, const orc_cam *c, int width,
+                           int height, float r_min, const int *win, uint64_t *v0, uint64_t *v1,
+                           int atomic)
+{
+    float inv_range = 1.0f / (c->zfar - c->znear);
+    float a[4], b[4];
+    if (!orc_proj(c, pos_w + 4 * v, a) || !orc_proj(c, pos_w + 4 * (v + 1), b)) return;
+    int i0 = 0, i1 = width - 1, j0 = 0, j1 = height - 1;
+    float ra = 0.5f * (a[2] > b[2] ? a[2] : b[2]);
+    ra = ra > r_min ? ra : r_min;
+    float xmn = (a[0] < b[0] ? a[0] : b[0]) - ra - 2.0f;
+    float xmx = (a[0] > b[0] ? a[0] : b[0]) + ra + 2.0f;
+    float ymn = (a[1] < b[1] ? a[1] : b[1]) - ra - 2.0f;
+    float ymx = (a[1] > b[1] ? a[1] : b[1]) + ra + 2.0f;
+    if (xmx < 0.0f || ymx < 0.0f || xmn > (float)width || ymn > (float)height) return;
+    if (xmn > 0.0f) i0 = (int)xmn;
+    if (ymn > 0.0f) j0 = (int)ymn;
+    if (xmx < (float)(width - 1)) i1 = (int)xmx;
+    if (ymx < (float)(height - 1)) j1 = (int)ymx;
+    if (win) {
+        i0 = i0 > win[0] ? i0 : win[0];
+        j0 = j0 > win[1] ? j0 : win[1];
+        i1 = i1 < win[2] ? i1 : win[2];
+        j1 = j1 < win[3] ? j1 : win[3];
+    }
+    for (int j = j0; j <= j1; ++j) {
+        for (int i = i0; i <= i1; ++i) {
+            uint32_t q;
+            int m = orc_cover(a, b, i, j, r_min, c->znear, inv_range, &q);
+            if (!m) continue;
+            uint64_t key = ((uint64_t)q << ORC_ID_BITS) | (uint64_t)v;
+            size_t p = (size_t)j * width + i;
+            if (atomic) {
+                if (m & 1) orc_atomic_min(v0 + p, key);
+                if (m & 2) orc_atomic_min(v1 + p, key);
+            } else {
+                if ((m & 1) && key < v0[p]) v0[p] = key;
+                if ((m & 2) && key < v1[p]) v1[p] = key;
+            }
+        }
+    }
+}
+
 int orc_raster(const float *pos_w, const uint8_t *flags, const uint32_t *scene_off,
                const float *cams, uint32_t n_scenes, int width, int height, float r_min,
                const float *scene_z, int brute, const uint32_t *order, uint64_t n_order,
@@ -510,6 +585,20 @@ int orc_raster(const float *pos_w, const uint8_t *flags, const uint32_t *scene_o
         }
     }
     uint64_t n_cp = scene_off[n_scenes];
+    if (orc_nthreads > 1 && !brute && !order) {
+        /* the same segments, spread over threads */
+        int64_t n_seg = n_cp > 0 ? (int64_t)n_cp - 1 : 0;
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(orc_nthreads)
+        for (int64_t it = 0; it < n_seg; ++it) {
+            uint64_t v = (uint64_t)it;
+            if (flags[v] & ORC_TIP) continue;
+            uint32_t sv = orc_scene_of(scene_off, n_scenes, v);
+            const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)sv);
+            uint64_t *v0 = vis + (size_t)sv * 2 * npix;
+            orc_raster_seg(pos_w, v, c, width, height, r_min, win, v0, v0 + npix, 1);
+        }
+        return 0;
+    }
     uint64_t n_visit = order ? n_order : n_cp;
     uint32_t s = 0;
     for (uint64_t it = 0; it < n_visit; ++it) {
@@ -522,25 +611,17 @@ int orc_raster(const float *pos_w, const uint8_t *flags, const uint32_t *scene_o
             while (s + 1 < n_scenes && v >= scene_off[s + 1]) s++;
         }
         const orc_cam *c = (const orc_cam *)(cams + 18 * (size_t)s);
+        uint64_t *v0 = vis + (size_t)s * 2 * npix, *v1 = v0 + npix;
+        if (!brute) {
+            orc_raster_seg(pos_w, v, c, width, height, r_min, win, v0, v1, 0);
+            continue;
+        }
+        /* brute force: every pixel (of the window) against the segment */
         float inv_range = 1.0f / (c->zfar - c->znear);
         float a[4], b[4];
         if (!orc_proj(c, pos_w + 4 * v, a) || !orc_proj(c, pos_w + 4 * (v + 1), b)) continue;
-        uint64_t *v0 = vis + (size_t)s * 2 * npix, *v1 = v0 + npix;
         int i0 = 0, i1 = width - 1, j0 = 0, j1 = height - 1;
-        if (!brute) {
-            float ra = 0.5f * (a[2] > b[2] ? a[2] : b[2]);
-            ra = ra > r_min ? ra : r_min;
-            float xmn = (a[0] < b[0] ? a[0] : b[0]) - ra - 2.0f;
-            float xmx = (a[0] > b[0] ? a[0] : b[0]) + ra + 2.0f;
-            float ymn = (a[1] < b[1] ? a[1] : b[1]) - ra - 2.0f;
-            float ymx = (a[1] > b[1] ? a[1] : b[1]) + ra + 2.0f;
-            if (xmx < 0.0f || ymx < 0.0f || xmn > (float)width || ymn > (float)height) continue;
-            if (xmn > 0.0f) i0 = (int)xmn;
-            if (ymn > 0.0f) j0 = (int)ymn;
-            if (xmx < (float)(width - 1)) i1 = (int)xmx;
-            if (ymx < (float)(height - 1)) j1 = (int)ymx;
-        }
-        if (win) {   /* only the pixels of window [win0, win2] x [win1, win3] */
+        if (win) {
             i0 = i0 > win[0] ? i0 : win[0];
             j0 = j0 > win[1] ? j0 : win[1];
             i1 = i1 < win[2] ? i1 : win[2];
@@ -758,6 +839,7 @@ int orc_resolve_shadowed(const float *pos_w, const float *rgb, const uint8_t *fl
         const uint64_t *g = vis + (size_t)s * 2 * npix, *a = g + npix;
         double *out = out_rgba + (size_t)s * 4 * npix;
         /* pass 1: centre shading of every centre-sample hit */
+#pragma omp parallel for schedule(dynamic, 4) num_threads(orc_nthreads) if (orc_nthreads > 1)
         for (int j = cj0; j <= cj1; ++j)
             for (int i = ci0; i <= ci1; ++i) {
                 size_t p = (size_t)j * width + i;
@@ -772,6 +854,7 @@ int orc_resolve_shadowed(const float *pos_w, const float *rgb, const uint8_t *fl
                 }
             }
         /* pass 2: reconstruction */
+#pragma omp parallel for schedule(dynamic, 4) num_threads(orc_nthreads) if (orc_nthreads > 1)
         for (int j = oj0; j <= oj1; ++j)
             for (int i = oi0; i <= oi1; ++i) {
                 size_t p = (size_t)j * width + i;

@@ -15,6 +15,7 @@ a helix of the stated radius and phase).
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import math
 import os
@@ -37,7 +38,7 @@ def build(force: bool = True) -> str:
     """Compile hm_oracle.c with gcc (binary32 ops kept separate: no contraction)."""
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-o", _LIB, _SRC, "-lm"]
+               "-fopenmp", "-shared", "-o", _LIB, _SRC, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB
 
@@ -53,6 +54,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         u32, u64, f32, i32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float, ctypes.c_int
         P = ctypes.c_void_p
+        L.orc_set_threads.argtypes = [i32]
+        L.orc_get_threads.restype = i32
         L.orc_pcg.restype = u32
         L.orc_pcg.argtypes = [u32]
         L.orc_strand_rand.argtypes = [u32, u32, u32, P]
@@ -96,6 +99,29 @@ def lib():
         L.orc_resolve_gbuf.argtypes = [P, P, u32, i32, i32, P, P]
         _lib = L
     return _lib
+
+
+@contextlib.contextmanager
+def threads(n: int):
+    """Inside the block the raster's segment loop and the resolve's pixel rows
+    run on n threads (the raster takes each pixel's minimum by compare-and-swap);
+    the results are identical for every n."""
+    L = lib()
+    old = L.orc_get_threads()
+    L.orc_set_threads(int(n))
+    try:
+        yield
+    finally:
+        L.orc_set_threads(old)
+
+
+def host_threads(cap: int = 16) -> int:
+    """Threads of this process's CPU share, at most cap."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
 
 
 def _p(a: Optional[np.ndarray]):
@@ -499,8 +525,14 @@ def soft_grad(pos_w, rgb, flags, vis, cams, width, height, rp, d_out, bg=(0.0, 0
 
 
 # ----------------------------------------------------------------- whole frame
-def render(sc, rp=None, want=("vis", "out")):
-    """Oracle for the whole path on one Scene: LOD -> generate -> raster -> resolve."""
+def render(sc, rp=None, want=("vis", "out"), n_threads: int = 1):
+    """Oracle for the whole path on one Scene: LOD -> generate -> raster -> resolve
+    (raster and filtered resolve on n_threads threads; same results for any)."""
+    with threads(n_threads):
+        return _render(sc, rp, want)
+
+
+def _render(sc, rp, want):
     from paper_2607_04230_amd.scenes import ResolveParams, MODE_SOFT  # inputs only
     rp = rp or ResolveParams()
     table, soff, (ns, ncp) = lod_select(sc)

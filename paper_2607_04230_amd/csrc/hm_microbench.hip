@@ -1,8 +1,9 @@
 // Peak-rate microkernels for the raster's rooflines: 64-bit atomic minima in
 // LDS (lane-distinct, consecutive addresses, as the tile raster's candidate
 // pixels are) and in global memory (addresses spread pseudo-randomly over the
-// caller's buffer).  Measurement helpers only; nothing on the rendering path
-// calls them.
+// caller's buffer); and read-only / write-only streams of known size that
+// calibrate the profiler's byte counters.  Measurement helpers only; nothing
+// on the rendering path calls them.
 #include <hip/hip_runtime.h>
 
 #include "hm_bench.h"
@@ -39,9 +40,56 @@ __global__ __launch_bounds__(256) void k_bench_global_min(unsigned long long *bu
     }
 }
 
+// Known-size memory traffic for calibrating the byte counters of the
+// profiler: k_bench_read reads n 16-byte words once (one word per lane per
+// step, consecutive lanes on consecutive words) and writes one 32-bit word per
+// workgroup; k_bench_write writes n 16-byte words once.
+__global__ __launch_bounds__(256) void k_bench_read(const uint4 *buf, uint64_t n, uint32_t *sink)
+{
+    __shared__ uint32_t red;
+    if (threadIdx.x == 0) red = 0u;
+    __syncthreads();
+    uint32_t acc = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint4 v = buf[i];
+        acc ^= (v.x ^ v.y) ^ (v.z ^ v.w);
+    }
+    atomicXor(&red, acc);
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = red;
+}
+
+__global__ __launch_bounds__(256) void k_bench_write(uint4 *buf, uint64_t n, uint32_t val)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        buf[i] = make_uint4(val, val ^ (uint32_t)i, val, (uint32_t)(i >> 32));
+}
+
 }  // namespace hm
 
 using namespace hm;
+
+extern "C" hm_status hm_bench_traffic(int32_t kind, void *buf, size_t bytes, uint32_t *sink,
+                                      uint32_t grid, void *stream)
+{
+    if (!buf || bytes == 0 || bytes % 16 != 0 || grid == 0 || grid > 65536)
+        return HM_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    const uint64_t n = bytes / 16;
+    if (kind == 0) {
+        if (!sink) return HM_ERR_INVALID;
+        hipLaunchKernelGGL(k_bench_read, dim3(grid), dim3(256), 0, st,
+                           reinterpret_cast<const uint4 *>(buf), n, sink);
+    } else if (kind == 1) {
+        hipLaunchKernelGGL(k_bench_write, dim3(grid), dim3(256), 0, st,
+                           reinterpret_cast<uint4 *>(buf), n, 0x5A5A5A5Au);
+    } else {
+        return HM_ERR_INVALID;
+    }
+    return hipGetLastError() == hipSuccess ? HM_OK : HM_ERR_HIP;
+}
 
 extern "C" hm_status hm_bench_atomics(int32_t kind, uint64_t *buf, size_t n_words, uint32_t iters,
                                       uint32_t grid, void *stream)

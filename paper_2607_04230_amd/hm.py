@@ -80,6 +80,8 @@ EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_
            "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
            "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset",
            "hm_dom_accumulate", "hm_dom_shadow", "hm_generate_raster"]
+# measurement helpers (include/hm_bench.h)
+BENCH_EXPORTS = ["hm_bench_atomics", "hm_bench_traffic"]
 
 
 def lod_depth_offset(table, bundle_nstrands, delta_out):
@@ -99,6 +101,17 @@ def bench_atomics(kind: int, buf, iters: int, grid: int):
     L.hm_bench_atomics.restype = _i32
     _check(L.hm_bench_atomics(kind, _ptr(buf), buf.numel(), iters, grid, _stream()),
            "hm_bench_atomics")
+
+
+def bench_traffic(kind: int, buf, sink, grid: int = 2048):
+    """Enqueue the known-size stream microkernel on the current stream: kind 0
+    reads all of buf once (sink: >= grid int32 words), kind 1 writes it."""
+    L = load()
+    L.hm_bench_traffic.argtypes = [_i32, _vp, _sz, _vp, _u32, _vp]
+    L.hm_bench_traffic.restype = _i32
+    nbytes = buf.numel() * buf.element_size()
+    _check(L.hm_bench_traffic(kind, _ptr(buf), nbytes, _ptr(sink), grid, _stream()),
+           "hm_bench_traffic")
 
 
 def generate_raster(mesh, table, strand_base, strand_rgb, gp, st, cams, fr, r_min, scene_z,

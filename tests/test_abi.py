@@ -12,19 +12,23 @@ from paper_2607_04230_amd import hm
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    src = open(os.path.join(ROOT, "include", "hm.h")).read()
+def _declared(header):
+    src = open(os.path.join(ROOT, "include", header)).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(hm_[a-z_]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported():
     L = hm.load()
-    names = _declared()
+    headers = sorted(h for h in os.listdir(os.path.join(ROOT, "include")) if h.endswith(".h"))
+    assert headers == ["hm.h", "hm_bench.h"]
+    names = _declared("hm.h")
     assert "hm_raster_vis" in names and len(names) >= 11
-    for n in names:
+    bench = _declared("hm_bench.h")
+    for n in names + bench:
         assert hasattr(L, n), n
     assert set(names) == set(hm.EXPORTS)
+    assert set(bench) == set(hm.BENCH_EXPORTS)
 
 
 def test_version_and_defaults():
@@ -127,6 +131,12 @@ def test_validation_errors_are_reported():
     assert L.hm_bench_atomics(5, dummy, 4096, 1, 16, None) == 1
     assert L.hm_bench_atomics(0, None, 4096, 1, 16, None) == 1
     assert L.hm_bench_atomics(0, dummy, 8, 1, 16, None) == 2
+    L.hm_bench_traffic.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p]
+    assert L.hm_bench_traffic(0, dummy, 1000, dummy, 16, None) == 1     # not a multiple of 16
+    assert L.hm_bench_traffic(0, dummy, 1024, None, 16, None) == 1      # read needs a sink
+    assert L.hm_bench_traffic(2, dummy, 1024, dummy, 16, None) == 1
+    assert L.hm_bench_traffic(1, dummy, 1024, None, 0, None) == 1
     # compressed G-buffer keys: known payloads only, no shared views, CENTER resolve
     rp = hm.raster_defaults(fr)
     rp.payload = 2

@@ -28,6 +28,21 @@ def _setup(O, torch, sc):
     return ref, pos, rgb, ctx
 
 
+def _oracle_target(O, torch, sc, ref, rp):
+    """The differentiable workload's target: the oracle's soft render (its own
+    visibility) of the parameters perturbed by N(0, 0.01) on positions,
+    multiplicatively on widths, and on colours."""
+    tp, tc = scenes.perturb_stream(ref["pos_w"], ref["rgb"], seed=sc.seed + 1)
+    with O.threads(O.host_threads()):
+        tvis = O.raster(tp, ref["flags"], ref["scene_off"], sc.cams, sc.width, sc.height,
+                        sc.r_min, sc.scene_z)
+    t = O.soft_forward(torch.as_tensor(tp.astype(np.float64)),
+                       torch.as_tensor(tc.astype(np.float64)), ref["flags"], tvis, sc.cams,
+                       sc.width, sc.height, rp).numpy()
+    assert not np.array_equal(tvis, ref["vis"])       # the perturbation moves strands
+    return t.astype(np.float32)
+
+
 def _rel(g, r):
     return float(np.linalg.norm(g - r) / max(np.linalg.norm(r), 1e-30))
 
@@ -42,8 +57,7 @@ def test_soft_gradient_matches_oracle(O, torch, name):
         sc = scenes.config_diff()
     ref, pos, rgb, ctx = _setup(O, torch, sc)
     rp = ResolveParams()
-    rng = np.random.default_rng(11)
-    target = rng.uniform(0.0, 0.2, (sc.n_scenes, sc.height, sc.width, 4)).astype(np.float32)
+    target = _oracle_target(O, torch, sc, ref, rp)
     p = pos.clone().requires_grad_(True)
     c = rgb.clone().requires_grad_(True)
     out = soft_render(p, c, ctx)

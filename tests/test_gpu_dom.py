@@ -22,6 +22,11 @@ def torch():
 
 
 def _oracle_shadowed(O, sc, shp):
+    with O.threads(O.host_threads()):
+        return _oracle_shadowed_1(O, sc, shp)
+
+
+def _oracle_shadowed_1(O, sc, shp):
     table, soff, (ns, ncp) = O.lod_select(sc)
     pos, rgb, fl = O.generate(sc, table, ncp)
     vis = O.raster(pos, fl, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
@@ -81,6 +86,13 @@ def test_head_shadowed_center_and_filter(O, torch):
     out = O.resolve(pos, rgb, fl, ref["vis"], sc.cams, sc.width, sc.height, ResolveParams(), 2,
                     sc.bg, shadow=ref["T"][None])
     assert np.abs(ds.out.cpu().numpy().astype(np.float64) - out).max() <= TOL
+
+
+def test_head_1080p_shadowed_with_a_1024_map(O, torch):
+    """The benchmarked shadow workload: the full head at 1920x1080 with a
+    1024^2 deep opacity map of 4 layers."""
+    sc = scenes.config_head()
+    _check(O, torch, sc, ShadowParams(width=1024, height=1024), "head 1080p, 1024^2 map")
 
 
 def test_lod_scene_shadowed(O, torch):

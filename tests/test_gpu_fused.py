@@ -54,6 +54,20 @@ def test_tiny_fused_matches_oracle(O, torch, cap):
     assert np.abs(ds.out.cpu().numpy().astype(np.float64) - ref["out"]).max() <= TOL
 
 
+def test_head_1080p_fused_matches_oracle(O, torch):
+    """The benchmarked fused workload: the full head at 1920x1080 with its
+    occluder, stream and visibility bit for bit, RGBA within 1e-4."""
+    sc = scenes.config_head()
+    ref = O.render(sc, n_threads=O.host_threads())
+    ds = _fused(sc, torch)
+    pos, rgb, fl = ds.host_stream()
+    assert np.array_equal(fl, ref["flags"])
+    assert np.array_equal(pos.view(np.uint32), ref["pos_w"].view(np.uint32))
+    assert np.array_equal(rgb.view(np.uint32), ref["rgb"].view(np.uint32))
+    assert np.array_equal(ds.host_vis(), ref["vis"])
+    assert np.abs(ds.out.cpu().numpy().astype(np.float64) - ref["out"]).max() <= TOL
+
+
 def test_head_with_occluder_fused_matches_oracle_and_tiled(O, torch):
     sc = scenes.config_head(width=640, height=360, strands_per_quad=16)
     assert sc.scene_z is not None

@@ -41,10 +41,14 @@ def _gpu(sc, torch, rp=None):
     return ds
 
 
-@pytest.mark.parametrize("name", ["tiny", "head"])
+@pytest.mark.parametrize("name", ["tiny", "head", "head1080p"])
 def test_gbuffer_keys_and_resolve_match_oracle(O, torch, name):
-    sc = (scenes.config_tiny() if name == "tiny"
-          else scenes.config_head(width=640, height=360, strands_per_quad=16))
+    if name == "tiny":
+        sc = scenes.config_tiny()
+    elif name == "head":
+        sc = scenes.config_head(width=640, height=360, strands_per_quad=16)
+    else:                                   # the benchmarked G-buffer workload
+        sc = scenes.config_head()
     vis, out = _ref(O, sc)
     ds = _gpu(sc, torch)
     g = ds.host_vis()
