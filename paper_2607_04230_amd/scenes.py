@@ -137,12 +137,16 @@ class Scene:
 
     @property
     def n_cp_full(self) -> int:
-        """Control points before any level of detail (upper bound for buffers)."""
-        return int((self.bundle_nstrands.astype(np.int64) * self.bundle_cmax.astype(np.int64)).sum())
+        """Control points before any level of detail (upper bound for buffers);
+        a count below 2 is taken as 2, as the library and the oracle do."""
+        return int((self.bundle_nstrands.astype(np.int64) * self._cmax()).sum())
 
     @property
     def n_seg_full(self) -> int:
-        return int((self.bundle_nstrands.astype(np.int64) * (self.bundle_cmax.astype(np.int64) - 1)).sum())
+        return int((self.bundle_nstrands.astype(np.int64) * (self._cmax() - 1)).sum())
+
+    def _cmax(self) -> np.ndarray:
+        return np.maximum(self.bundle_cmax.astype(np.int64), 2)
 
 
 # ----------------------------------------------------------------------------- cameras
