@@ -19,7 +19,9 @@
  *     descriptors) are host pointers read during the call only.
  *   - The caller owns every buffer.  The library never allocates device
  *     memory; scratch space is the caller's workspace (size from
- *     hm_workspace_size).  Nothing is retained between calls.
+ *     hm_workspace_size).  Nothing is retained between calls, except by
+ *     hm_resolve_shade_noalloc, whose scratch is a fixed array inside the
+ *     library.
  *   - Every call is asynchronous on `stream` (a hipStream_t, NULL = the null
  *     stream): it validates its arguments on the host, enqueues kernels and
  *     returns; it never synchronises.  Calls are safe to capture in a HIP
@@ -292,6 +294,27 @@ typedef struct {
 hm_status hm_resolve_shade(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,
                            const hm_frame *frame, const hm_shade_params *p, float *out_rgba,
                            void *ws, size_t ws_bytes, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * resolve of hm_resolve_shade without a workspace argument.  Same arguments
+ * (minus ws), kernels and results.  The FILTER mode's per-pixel records (16
+ * B per pixel, written by the centre shading before the filter reads them,
+ * so nothing has to start at zero) live in a scratch array inside the
+ * library of HM_NOALLOC_MAX_PIXELS records (64 MiB), which every GPU the
+ * library runs on holds until the process ends; CENTER and SOFT use none.
+ * A FILTER frame with more than HM_NOALLOC_MAX_PIXELS pixels
+ * (n_scenes * width * height) is rejected with HM_ERR_WORKSPACE before
+ * anything is enqueued.  Nothing is allocated.  `stream` must belong to the
+ * current device; the first call on each device looks up that device's copy
+ * of the array (HM_ERR_HIP if the lookup fails), so make it outside graph
+ * capture.  All calls on one GPU share its array and it keeps the last
+ * call's contents: calls that overlap on one GPU (different streams, or
+ * graphs replayed concurrently) race, and callers must serialise them. */
+#define HM_NOALLOC_MAX_PIXELS 4194304u
+hm_status hm_resolve_shade_noalloc(const hm_strands *s, const uint64_t *vis,
+                                   const hm_camera *cams, const hm_frame *frame,
+                                   const hm_shade_params *p, float *out_rgba, void *stream);
 
 /* Backward of the SOFT resolve with the visibility held fixed: given
  * d_out = dLoss/d out_rgba ([S][H][W][4]), ACCUMULATES dLoss/d pos_w into

@@ -414,6 +414,66 @@ hm_status hm_resolve_shade(const hm_strands *s, const uint64_t *vis, const hm_ca
     return check_launch("hm_resolve_shade");
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------------ no-allocation resolve
+// Scratch of hm_resolve_shade_noalloc: the filter's per-pixel records (one
+// float4 per pixel), for frames of at most HM_NOALLOC_MAX_PIXELS pixels.  Each
+// GPU holds its own copy at its own address; host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address) but the address hipGetSymbolAddress gives for the current device,
+// looked up once per device and kept in g_scratch_ptr.
+static __device__ __align__(256) float4 scratch[HM_NOALLOC_MAX_PIXELS];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+static hm_status scratch_address(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(HM_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+    REQUIRE(dev >= 0 && dev < SCRATCH_MAX_DEVICES, HM_ERR_RANGE,
+            "device ordinal %d beyond the %d devices the scratch table covers", dev,
+            SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(HM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HM_OK;
+}
+
+extern "C" {
+
+hm_status hm_resolve_shade_noalloc(const hm_strands *s, const uint64_t *vis,
+                                   const hm_camera *cams, const hm_frame *frame,
+                                   const hm_shade_params *p, float *out_rgba, void *stream)
+{
+    hm_status st;
+    ShadeK k;
+    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    REQUIRE(vis && cams && out_rgba, HM_ERR_INVALID, "NULL argument");
+    void *ws = nullptr;
+    if (k.mode == HM_RESOLVE_FILTER) {
+        const size_t pix = (size_t)frame->width * frame->height * frame->n_scenes;
+        REQUIRE(pix <= HM_NOALLOC_MAX_PIXELS, HM_ERR_WORKSPACE,
+                "frame of %zu pixels exceeds the %u pixels of the no-allocation scratch", pix,
+                HM_NOALLOC_MAX_PIXELS);
+        if (resolve_workspace(*frame) > sizeof(float4) * (size_t)HM_NOALLOC_MAX_PIXELS)
+            return fail(HM_ERR_WORKSPACE, "resolve records exceed the no-allocation scratch");
+        if ((st = scratch_address(&ws))) return st;
+    }
+    launch_resolve(*s, vis, cams, *frame, k, out_rgba, ws, (hipStream_t)stream);
+    return check_launch("hm_resolve_shade_noalloc");
+}
+
 hm_status hm_resolve_shade_bwd(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,
                                const hm_frame *frame, const hm_shade_params *p,
                                const float *d_out, float *grad_pos_w, float *grad_rgb,

@@ -79,7 +79,8 @@ EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_
            "hm_resolve_shade_bwd", "hm_workspace_size", "hm_raster_defaults", "hm_last_error",
            "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
            "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset",
-           "hm_dom_accumulate", "hm_dom_shadow", "hm_generate_raster"]
+           "hm_dom_accumulate", "hm_dom_shadow", "hm_generate_raster",
+           "hm_resolve_shade_noalloc"]
 # measurement helpers (include/hm_bench.h)
 BENCH_EXPORTS = ["hm_bench_atomics", "hm_bench_traffic"]
 
@@ -212,6 +213,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
                                 _vp]
     L.hm_resolve_shade.argtypes = [P(Strands), _vp, _vp, P(Frame), P(ShadeParams), _vp, _vp, _sz,
                                    _vp]
+    L.hm_resolve_shade_noalloc.argtypes = [P(Strands), _vp, _vp, P(Frame), P(ShadeParams), _vp,
+                                           _vp]
     L.hm_resolve_shade_bwd.argtypes = [P(Strands), _vp, _vp, P(Frame), P(ShadeParams), _vp, _vp,
                                        _vp, _vp]
     L.hm_workspace_size.argtypes = [_i32, P(Frame), _u32, _u32, P(RasterParams), P(_sz)]
@@ -325,6 +328,13 @@ def resolve_shade(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, out, ws):
                                  ctypes.byref(sp), _ptr(out), _ptr(ws),
                                  ws.numel() * ws.element_size(), _stream())
     _check(rc, "hm_resolve_shade")
+
+
+def resolve_shade_noalloc(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, out):
+    """hm_resolve_shade without a workspace (the library's static scratch)."""
+    rc = load().hm_resolve_shade_noalloc(ctypes.byref(st), _ptr(vis), _ptr(cams),
+                                         ctypes.byref(fr), ctypes.byref(sp), _ptr(out), _stream())
+    _check(rc, "hm_resolve_shade_noalloc")
 
 
 def timing_enable(on: bool):
