@@ -148,7 +148,7 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
         # both key layers read, one 16 B record written per pixel; per hair
         # pixel two 16 B control points and two colours gathered
         b = vis_bytes + vis_bytes + hair_px * 64
-    elif kernel in ("k_raster_tiles", "k_raster_direct"):
+    elif kernel in ("k_raster_flat", "k_raster_rows", "k_raster_direct"):
         # algorithmic work: 17 B per segment (screen record + flags) plus one
         # read and one write of the two-layer buffer from HBM, and one 64-bit
         # atomic minimum per covered (segment, pixel, layer) -- counted exactly
@@ -419,7 +419,7 @@ def extra_shadow(steps):
 
 # library kernels of the full-head frame -> the source file that holds them
 KERNEL_SOURCES = {
-    "k_raster_tiles": "paper_2607_04230_amd/csrc/hm_raster.hip",
+    "k_raster_flat": "paper_2607_04230_amd/csrc/hm_raster.hip",
     "k_bin": "paper_2607_04230_amd/csrc/hm_raster.hip",
     "k_prefill": "paper_2607_04230_amd/csrc/hm_raster.hip",
     "k_raster_long": "paper_2607_04230_amd/csrc/hm_raster.hip",
@@ -622,14 +622,14 @@ def main():
     measure_atomic_peaks(sc.width * sc.height)
     roof = roofline(dom, dom_avg, n_cp, n_seg, vis_bytes, hair_px, (2 * r + 1) ** 2)
     roof["kernel"] = dom
-    for k in ("k_generate_bundle", "k_project", "k_bin", "k_raster_tiles", "k_prefill",
+    for k in ("k_generate_bundle", "k_project", "k_bin", "k_raster_flat", "k_prefill",
               "k_shade", "k_filter"):
         if k in per_kernel:
             per_kernel[k]["roofline"] = roofline(k, per_kernel[k]["avg_ms"], n_cp, n_seg,
                                                  vis_bytes, hair_px, (2 * r + 1) ** 2)
     raster_ms = sum(kt.get(k, (0.0, 0))[0] for k in
                     ("k_prefill", "k_project", "k_bin", "k_tile_items", "k_fill_u32",
-                     "k_raster_tiles", "k_raster_long", "k_raster_direct",
+                     "k_raster_flat", "k_raster_rows", "k_raster_long", "k_raster_direct",
                      "k_scan_blocks", "k_scan_partials", "k_scan_add")) / args.steps
     line = {
         "metric": "segments rasterized/s and ms/frame at 1080p",

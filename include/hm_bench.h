@@ -40,6 +40,16 @@ hm_status hm_bench_atomics(int32_t kind, uint64_t *buf, size_t n_words, uint32_t
 hm_status hm_bench_traffic(int32_t kind, void *buf, size_t bytes, uint32_t *sink, uint32_t grid,
                            void *stream);
 
+/* Check of the raster's refined reciprocal (the hardware reciprocal plus one
+ * Newton step, used for the depth 1/z when the camera's depth range keeps
+ * every 1/z within [2^-126, 2^126)): every binary32 bit pattern x in
+ * [lo, hi) (lo < hi; the positive normal range is 0x00800000 .. 0x7F800000)
+ * is compared bit for bit with the correctly rounded 1.0f / x.  counts
+ * (device, two uint32, zeroed by the caller): counts[0] += mismatches,
+ * counts[1] += values tested.  Returns HM_ERR_INVALID for bad arguments,
+ * HM_ERR_HIP if the launch failed. */
+hm_status hm_bench_reciprocal(uint32_t lo, uint32_t hi, uint32_t *counts, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

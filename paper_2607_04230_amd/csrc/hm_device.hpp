@@ -87,6 +87,17 @@ __device__ __forceinline__ float4 project(const Cam &c, float4 p)
     return o;
 }
 
+// 1 / x for x in [2^-126, 2^126): the hardware reciprocal (about 1 ulp)
+// refined by one Newton step with fused multiply-adds, e = 1 - x y, y + e y.
+// On gfx950 this equals the correctly rounded quotient 1.0f / x for every x in
+// that range (hm_bench_reciprocal counts the exceptions over all of them).
+__device__ __forceinline__ float rcp_refined(float x)
+{
+    const float y = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, y, 1.0f);
+    return __builtin_fmaf(e, y, y);
+}
+
 // 24-bit normalised linear depth, truncated and clamped.
 __device__ __forceinline__ uint32_t depth_code(float z, float zn, float inv_range)
 {

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "hm_bench.h"
+#include "hm_device.hpp"
 #include "hm_internal.hpp"
 
 namespace hm {
@@ -67,9 +68,41 @@ __global__ __launch_bounds__(256) void k_bench_write(uint4 *buf, uint64_t n, uin
         buf[i] = make_uint4(val, val ^ (uint32_t)i, val, (uint32_t)(i >> 32));
 }
 
+// Exceptions of the refined reciprocal: every binary32 bit pattern in [lo, hi)
+// is tested against the correctly rounded quotient 1.0f / x (bitwise);
+// counts[0] += mismatches, counts[1] += values tested (one add each per
+// workgroup).
+__global__ __launch_bounds__(256) void k_bench_reciprocal(uint32_t lo, uint32_t hi,
+                                                          uint32_t *counts)
+{
+    __shared__ uint32_t red[2];
+    if (threadIdx.x < 2) red[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t bad = 0, seen = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)lo + blockIdx.x * blockDim.x + threadIdx.x; b < hi; b += stride) {
+        const float x = __uint_as_float((uint32_t)b);
+        bad += __float_as_uint(rcp_refined(x)) != __float_as_uint(1.0f / x) ? 1u : 0u;
+        ++seen;
+    }
+    atomicAdd(&red[0], bad);
+    atomicAdd(&red[1], seen);
+    __syncthreads();
+    if (threadIdx.x < 2) atomicAdd(counts + threadIdx.x, red[threadIdx.x]);
+}
+
 }  // namespace hm
 
 using namespace hm;
+
+extern "C" hm_status hm_bench_reciprocal(uint32_t lo, uint32_t hi, uint32_t *counts,
+                                         void *stream)
+{
+    if (!counts || lo >= hi) return HM_ERR_INVALID;
+    hipLaunchKernelGGL(k_bench_reciprocal, dim3(8192), dim3(256), 0, (hipStream_t)stream, lo, hi,
+                       counts);
+    return hipGetLastError() == hipSuccess ? HM_OK : HM_ERR_HIP;
+}
 
 extern "C" hm_status hm_bench_traffic(int32_t kind, void *buf, size_t bytes, uint32_t *sink,
                                       uint32_t grid, void *stream)

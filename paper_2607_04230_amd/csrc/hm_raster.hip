@@ -26,6 +26,7 @@
 // supplies the per-point tangents) and, for deep-opacity-map shadows, walk
 // a light view's work items a second time to count fragments per layer.
 #include <algorithm>
+#include <type_traits>
 
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
@@ -77,17 +78,20 @@ __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *sce
                                                  uint32_t *clr1, uint32_t n1)
 {
     // also zero the binning counters of this call (saves separate fill launches)
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n0 || i < n1;
-         i += gridDim.x * blockDim.x) {
-        if (i < n0) clr0[i] = 0u;
-        if (i < n1) clr1[i] = 0u;
+    if (blockIdx.y == 0) {
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n0 || i < n1;
+             i += gridDim.x * blockDim.x) {
+            if (i < n0) clr0[i] = 0u;
+            if (i < n1) clr1[i] = 0u;
+        }
     }
-    // scene by scene (no division per pixel), two pixels per 16-byte store
-    // when the scene has an even pixel count and the buffers are aligned
+    // the grid's rows take scenes (all scenes of a frame at once, no division
+    // per pixel), two pixels per 16-byte store when the scene has an even
+    // pixel count and the buffers are aligned
     const size_t hw = (size_t)W * H;
     const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (uint32_t s = 0; s < S; ++s) {
+    for (uint32_t s = blockIdx.y; s < S; s += gridDim.y) {
         const float *zs = scene_z ? scene_z + (size_t)s * hw : nullptr;
         const float zn = cams[s].znear, zf = cams[s].zfar;
         const float inv_range = 1.0f / (zf - zn);
@@ -590,6 +594,115 @@ __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, uint32_t n, uint3
 }
 
 // ------------------------------------------------------------------ tiled raster
+// Shared by both tile kernels.  A work item is a tile and a chunk of its
+// segment list; a tile that is one work item owns its pixels (it starts from
+// the prefilled values and writes back with plain stores), a split tile merges
+// every touched pixel with one 64-bit global atomic minimum per layer.
+//
+// The tile's layers live in LDS with a row pitch of T + 1 keys, so that one
+// column of consecutive rows falls in different banks (the per-pixel spread
+// walks steep segments down columns).
+__host__ __device__ constexpr uint32_t tile_pitch(uint32_t T) { return T + 1u; }
+
+// Tile words of a pass: two layers of 64-bit keys, or (deep-opacity counting)
+// the first-fragment depth code plus one count per layer, 32 bits each; TP =
+// T * pitch words per layer.
+__host__ __device__ inline uint32_t tile_words(uint32_t TP, bool dom, uint32_t n_layers)
+{
+    return dom ? (1u + n_layers) * TP : 4u * TP;
+}
+
+// Deep-opacity counting pass of the tile raster: q0 of every pixel comes from
+// the light view's conservative layer (vis), accepted conservative pairs are
+// counted in layer min((q - q0) / layer_codes, n_layers - 1).
+struct DomK {
+    uint32_t *counts;       // [n_layers][H][W]
+    uint32_t layer_codes, n_layers;
+};
+
+__device__ __forceinline__ void dom_count(uint32_t *cnt, const uint32_t *q0t, uint32_t x,
+                                          uint32_t TP, uint32_t q, const DomK &dk)
+{
+    const uint32_t q0 = q0t[x];
+    uint32_t k = q > q0 ? (q - q0) / dk.layer_codes : 0u;
+    k = k < dk.n_layers - 1u ? k : dk.n_layers - 1u;
+    atomicAdd(&cnt[k * TP + x], 1u);
+}
+
+// Geometry of one work item.
+struct TileItem {
+    uint32_t beg, end, s;
+    int px0, py0, px1, py1;
+    uint32_t tw, th;
+    bool whole;
+};
+
+__device__ __forceinline__ TileItem tile_item(const RasterK &rk, uint32_t item,
+                                              const uint32_t *tile_off, const uint32_t *item_off,
+                                              const uint32_t *item_tile)
+{
+    TileItem it;
+    const uint32_t t = item_tile[item];         // item_off[t] <= item < item_off[t + 1]
+    it.beg = tile_off[t] + (item - item_off[t]) * rk.chunk;
+    const uint32_t end0 = it.beg + rk.chunk, tend = tile_off[t + 1];
+    it.end = end0 < tend ? end0 : tend;
+    const uint32_t tiles_per_scene = rk.ntx * rk.nty;
+    it.s = t / tiles_per_scene;
+    const uint32_t r = t - it.s * tiles_per_scene;
+    const uint32_t ty = r / rk.ntx, tx = r - ty * rk.ntx;
+    it.px0 = (int)(tx * rk.T);
+    it.py0 = (int)(ty * rk.T);
+    it.px1 = min(it.px0 + (int)rk.T, (int)rk.W) - 1;
+    it.py1 = min(it.py0 + (int)rk.T, (int)rk.H) - 1;
+    it.tw = (uint32_t)(it.px1 - it.px0 + 1);
+    it.th = (uint32_t)(it.py1 - it.py0 + 1);
+    it.whole = tend - tile_off[t] <= rk.chunk;
+    return it;
+}
+
+// Two key layers of a tile: set empty, or (a tile that is one work item) load
+// the prefilled values.
+__device__ __forceinline__ void tile_keys_init(uint64_t *lc, uint64_t *la, const TileItem &it,
+                                               const RasterK &rk, const uint64_t *vc,
+                                               const uint64_t *va)
+{
+    const uint32_t P = tile_pitch(rk.T);
+    for (uint32_t x = threadIdx.x; x < rk.T * rk.T; x += blockDim.x) {
+        const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+        uint64_t kc = HM_EMPTY, ka = HM_EMPTY;
+        if (it.whole && lx < it.tw && ly < it.th) {
+            const size_t p = (size_t)(it.py0 + (int)ly) * rk.W + (size_t)(it.px0 + (int)lx);
+            kc = vc[p];
+            ka = va[p];
+        }
+        lc[ly * P + lx] = kc;
+        la[ly * P + lx] = ka;
+    }
+}
+
+// Merge the tile's layers into the buffer: plain stores for a tile that is one
+// work item, else one atomic minimum per touched pixel and layer.
+__device__ __forceinline__ void tile_keys_store(const uint64_t *lc, const uint64_t *la,
+                                                const TileItem &it, const RasterK &rk,
+                                                uint64_t *vc, uint64_t *va)
+{
+    const uint32_t P = tile_pitch(rk.T);
+    for (uint32_t x = threadIdx.x; x < rk.T * rk.T; x += blockDim.x) {
+        const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+        if (lx >= it.tw || ly >= it.th) continue;
+        const size_t p = (size_t)(it.py0 + (int)ly) * rk.W + (size_t)(it.px0 + (int)lx);
+        const uint64_t kc = lc[ly * P + lx], ka = la[ly * P + lx];
+        if (it.whole) {
+            vc[p] = kc;
+            va[p] = ka;
+        } else {
+            if (kc != HM_EMPTY) atomicMin((unsigned long long *)(vc + p), (unsigned long long)kc);
+            if (ka != HM_EMPTY) atomicMin((unsigned long long *)(va + p), (unsigned long long)ka);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ row walker
 // Per-segment records of a batch, struct of arrays with stride nb (fields a
 // caller does not use are not read: the loads are plain LDS reads): the 16
 // geometric fields of Seg (the slack e is recomputed from them), with
@@ -655,178 +768,80 @@ __device__ __forceinline__ bool tile_rows(const Seg &sg, int px0, int px1, int &
     return j0 <= j1;
 }
 
-// Pixel slots of one wave's pixel -> row map (bytes); rows whose candidate
-// pixels exceed it are spread in several windows.
-constexpr uint32_t PIX_WINDOW = 256;
-
-// dynamic LDS bytes of k_raster_tiles for tile edge T and `block` threads:
-// two layers of keys and the segment records; for the per-pixel spread also
-// the row-start bitmap (block * T bits) and each wave's window of pixel
-// descriptors (one word each).  T = 32 with 256 threads takes 39936 B, so
-// four workgroups fit a CU's 160 KiB.
-static inline uint32_t tile_lds_bytes(uint32_t T, uint32_t block, bool flat, bool gb)
+// dynamic LDS bytes of k_raster_rows: two layers and the segment records
+static inline uint32_t rows_lds_bytes(uint32_t T, uint32_t block, bool gb)
 {
-    uint32_t b = 2u * T * T * 8u + block * 4u * rec_words(gb);
-    if (flat) b += block * T / 8u + (block / 64u) * PIX_WINDOW * 4u;
-    return b;
+    return 2u * T * tile_pitch(T) * 8u + block * 4u * rec_words(gb);
 }
 
-// Tile words of a pass: two layers of 64-bit keys, or (deep-opacity counting)
-// the first-fragment depth code plus one count per layer, 32 bits each.
-__host__ __device__ inline uint32_t tile_words(uint32_t TT, bool dom, uint32_t n_layers)
-{
-    return dom ? (1u + n_layers) * TT : 4u * TT;
-}
-
-// Deep-opacity counting pass of the tile raster: q0 of every pixel comes from
-// the light view's conservative layer (vis), accepted conservative pairs are
-// counted in layer min((q - q0) / layer_codes, n_layers - 1).
-struct DomK {
-    uint32_t *counts;       // [n_layers][H][W]
-    uint32_t layer_codes, n_layers;
-};
-
-// Persistent tile raster.  Work items (a tile and a chunk of its segment
-// list) are pulled from counters[1].  The tile's two layers live in LDS.
-//
-// Segments are taken in batches of nb: each lane builds one segment's record
-// (screen geometry, the rows and columns of the tile it can reach, stream id)
-// and one block scan both compacts the segments that reach the tile and
-// numbers their (segment, row) pairs ("row slots").  Then
-//   FLAT = false: each lane takes a contiguous run of row slots and loops over
-//                 the candidate pixels of each row;
-//   FLAT = true:  (nb <= 256: row owners travel as 8-bit ids) each wave takes
-//                 64 row slots at a time, one per lane, finds each slot's
-//                 segment from a bitmap of first rows (ballot + popcount),
-//                 computes the column spans, and a wave scan spreads the
-//                 candidate pixels of those rows over the lanes, one pixel per
-//                 lane per step, so that lanes stay busy whatever the spans.
-//
-// NBC: the workgroup size when known at compile time (the record fields then
-// sit at fixed LDS offsets), 0 for any blockDim.
-__device__ __forceinline__ void dom_count(uint32_t *cnt, const uint32_t *q0t, uint32_t x,
-                                          uint32_t TT, uint32_t q, const DomK &dk)
-{
-    const uint32_t q0 = q0t[x];
-    uint32_t k = q > q0 ? (q - q0) / dk.layer_codes : 0u;
-    k = k < dk.n_layers - 1u ? k : dk.n_layers - 1u;
-    atomicAdd(&cnt[k * TT + x], 1u);
-}
-
-template <bool FLAT, uint32_t NBC, bool DOM, bool GB>
-__global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
-                               const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
-                               uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
-                               const uint32_t *item_tile, const uint32_t *entries, uint32_t *counters, uint64_t *vis,
-                               DomK dk, GbK gk)
+// Tile raster, row walker (HM_RASTER_TILED_ROWS).  Work items (a tile and a
+// chunk of its segment list) are pulled from counters[1].  Segments are taken
+// in batches of nb: each lane builds one segment's record (screen geometry,
+// the rows and columns of the tile it can reach, stream id) and one block scan
+// both compacts the segments that reach the tile and numbers their (segment,
+// row) pairs ("row slots"); each lane then takes a contiguous run of row slots
+// and loops over the candidate pixels of each row.  NBC: the workgroup size
+// when known at compile time (the record fields then sit at fixed LDS
+// offsets), 0 for any blockDim.
+template <uint32_t NBC, bool GB>
+__global__ void k_raster_rows(const float4 *proj, const uint8_t *flags,
+                              const uint32_t *scene_off, const hm_camera *cams, RasterK rk,
+                              uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
+                              const uint32_t *item_tile, const uint32_t *entries,
+                              uint32_t *counters, uint64_t *vis, GbK gk)
 {
     extern __shared__ uint64_t lds[];
     __shared__ uint32_t sh_item;
     __shared__ uint32_t sh_scan[1024 / 64 + 1];
-    const uint32_t TT = rk.T * rk.T;
+    const uint32_t P = tile_pitch(rk.T);
+    const uint32_t TP = rk.T * P;
     const uint32_t nb = NBC ? NBC : blockDim.x;
-    uint64_t *lc = lds, *la = lds + TT;
-    uint32_t *q0t = reinterpret_cast<uint32_t *>(lds), *cnt = q0t + TT;    // DOM only
-    float *rf = reinterpret_cast<float *>(lds) + tile_words(TT, DOM, dk.n_layers);
+    uint64_t *lc = lds, *la = lds + TP;
+    float *rf = reinterpret_cast<float *>(lds) + tile_words(TP, false, 1u);
     uint32_t *rw = reinterpret_cast<uint32_t *>(rf);
     uint32_t *r_sid = rw + rec_floats(GB) * nb;      // stream id
     uint32_t *r_rc = r_sid + nb;                     // first row slot + clip
-    // per-pixel spread only
-    const uint32_t wv = threadIdx.x >> 6;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t nw = nb >> 6;
-    const uint32_t bmp_words = nb * rk.T / 32u;
-    uint32_t *bmp = r_rc + nb;
-    // pixel descriptors: segment | (j - py0) << 8 | (i - px0) << 13
-    uint32_t *pdesc = bmp + bmp_words + wv * PIX_WINDOW;
 
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t n_items = item_off[rk.n_tiles];
     const size_t hw = (size_t)rk.W * rk.H;
-    const uint32_t tiles_per_scene = rk.ntx * rk.nty;
     for (;;) {
         if (threadIdx.x == 0) sh_item = atomicAdd(&counters[1], 1u);
-        if (DOM) {
-            for (uint32_t x = threadIdx.x; x < dk.n_layers * TT; x += blockDim.x) cnt[x] = 0u;
-        } else {
-            for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
-                lc[x] = HM_EMPTY;
-                la[x] = HM_EMPTY;
-            }
-        }
         __syncthreads();
         const uint32_t item = sh_item;
         if (item >= n_items) break;
-        const uint32_t t = item_tile[item];         // item_off[t] <= item < item_off[t + 1]
-        const uint32_t beg = tile_off[t] + (item - item_off[t]) * rk.chunk;
-        const uint32_t end0 = beg + rk.chunk, tend = tile_off[t + 1];
-        const uint32_t end = end0 < tend ? end0 : tend;
-        const uint32_t s = t / tiles_per_scene;
-        const uint32_t r = t - s * tiles_per_scene;
-        const uint32_t ty = r / rk.ntx, tx = r - ty * rk.ntx;
-        const int px0 = (int)(tx * rk.T), py0 = (int)(ty * rk.T);
-        const int px1 = min(px0 + (int)rk.T, (int)rk.W) - 1;
-        const int py1 = min(py0 + (int)rk.T, (int)rk.H) - 1;
+        const TileItem it = tile_item(rk, item, tile_off, item_off, item_tile);
+        const int px0 = it.px0, py0 = it.py0;
         float zn, inv_range;
-        scene_depth_consts(cams, s, zn, inv_range);
-        uint64_t *vc = vis + (size_t)s * 2 * hw, *va = vc + hw;
-        const uint32_t tw = (uint32_t)(px1 - px0 + 1), th = (uint32_t)(py1 - py0 + 1);
-        // a tile that is one work item owns its pixels: start from the
-        // prefilled values and write back without atomics
-        const bool whole = tend - tile_off[t] <= rk.chunk;
-        if (DOM) {
-            for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
-                const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
-                uint32_t q0 = 0xFFFFFFFFu;
-                if (lx < tw && ly < th) {
-                    const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
-                    q0 = (uint32_t)(va[p] >> HM_ID_BITS);
-                }
-                q0t[x] = q0;
-            }
-            __syncthreads();
-        } else if (whole) {
-            for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
-                const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
-                if (lx >= tw || ly >= th) continue;
-                const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
-                lc[x] = vc[p];
-                la[x] = va[p];
-            }
-            __syncthreads();
-        }
+        scene_depth_consts(cams, it.s, zn, inv_range);
+        uint64_t *vc = vis + (size_t)it.s * 2 * hw, *va = vc + hw;
+        tile_keys_init(lc, la, it, rk, vc, va);
+        __syncthreads();
 
-        // each batch's stream inputs are loaded during the previous batch:
-        // its entry (segment unit) at the start, the screen records and flags
-        // once the previous batch's records are built, so that both latencies
-        // overlap the previous batch's pixel work
         uint32_t nx_u = 0;
         EntryIn nx{};
-        if (beg + threadIdx.x < end) {
-            nx_u = entries[beg + threadIdx.x];
+        if (it.beg + threadIdx.x < it.end) {
+            nx_u = entries[it.beg + threadIdx.x];
             nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
         }
-        for (uint32_t e0 = beg; e0 < end; e0 += nb) {
+        for (uint32_t e0 = it.beg; e0 < it.end; e0 += nb) {
             const uint32_t e = e0 + threadIdx.x;
             const EntryIn cur = nx;
-            const bool more = e0 + nb < end;
-            if (more && e + nb < end) nx_u = entries[e + nb];
+            const bool more = e0 + nb < it.end;
+            if (more && e + nb < it.end) nx_u = entries[e + nb];
             uint32_t nr = 0, vu = 0;
             Seg sg;
             int i0, i1, j0, j1;
-            if (e < end) {
+            if (e < it.end) {
                 vu = cur.v;
                 if (seg_from(cur, n, rk.r_min, sg) && seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
                     j0 = max(j0, py0);
-                    j1 = min(j1, py1);
+                    j1 = min(j1, it.py1);
                     i0 = max(i0, px0);
-                    i1 = min(i1, px1);
-                    if (i0 <= i1 && j0 <= j1 && tile_rows(sg, px0, px1, j0, j1))
+                    i1 = min(i1, it.px1);
+                    if (i0 <= i1 && j0 <= j1 && tile_rows(sg, px0, it.px1, j0, j1))
                         nr = (uint32_t)(j1 - j0 + 1);
                 }
-            }
-            if (FLAT) {
-                for (uint32_t x = threadIdx.x; x < bmp_words; x += blockDim.x) bmp[x] = 0u;
             }
             // one scan: low 16 bits number the row slots (at most nb * T),
             // high 16 bits compact the segments that reach the tile
@@ -839,159 +854,439 @@ __global__ void k_raster_tiles(const float4 *proj, const uint8_t *flags,
                 r_sid[c] = vu;
                 r_rc[c] = r0 | ((uint32_t)(j0 - py0) << 15) | ((uint32_t)(i0 - px0) << 20) |
                           ((uint32_t)(i1 - px0) << 25);
-                if (FLAT) atomicOr(&bmp[r0 >> 5], 1u << (r0 & 31u));
             }
             __syncthreads();
-            if (more && e + nb < end) nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
-            if (FLAT) {
-                // contiguous 64-slot groups per wave, so that the count of
-                // segments starting before a group carries from one to the next
-                const uint32_t ng = (tot + 63u) >> 6;
-                const uint32_t G = (ng + nw - 1u) / nw;
-                const uint32_t g0 = wv * G, g1 = min(g0 + G, ng);
-                uint32_t before = 0;                 // segments whose first row < 64 * g0
-                if (g0 < g1) {
-                    uint32_t l2 = 0, h2 = nseg;      // first rows increase strictly
-                    while (l2 < h2) {
-                        const uint32_t mid = (l2 + h2) >> 1;
-                        if (rc_slot(r_rc[mid]) < g0 * 64u) l2 = mid + 1; else h2 = mid;
-                    }
-                    before = l2;
+            if (more && e + nb < it.end) nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
+            const uint32_t per = (tot + nb - 1) / nb;
+            const uint32_t r_beg = threadIdx.x * per;
+            const uint32_t r_end = min(r_beg + per, tot);
+            uint32_t ow = 0;
+            if (r_beg < r_end) {            // owner of the first slot: binary search
+                uint32_t h2 = nseg;
+                while (h2 - ow > 1) {
+                    const uint32_t mid = (ow + h2) >> 1;
+                    if (rc_slot(r_rc[mid]) <= r_beg) ow = mid; else h2 = mid;
                 }
-                const uint64_t le = (2ull << lane) - 1ull;   // lanes <= this one
-                for (uint32_t g = g0; g < g1; ++g) {
-                    const uint32_t rr = g * 64u + lane;
-                    const bool start = rr < tot && ((bmp[rr >> 5] >> (rr & 31u)) & 1u);
-                    const uint64_t M = __ballot(start);
-                    const uint32_t o = before + (uint32_t)__popcll(M & le) - 1u;
-                    before += (uint32_t)__popcll(M);
-                    uint32_t c = 0, d0 = 0;
-                    if (rr < tot) {
-                        const Seg sr = rec_load<GB>(rf, nb, o);
-                        const uint32_t rc = r_rc[o];
-                        const int j = py0 + rc_j0(rc) + (int)(rr - rc_slot(rc));
-                        int a0, a1;
-                        row_span(sr, j, a0, a1);
-                        a0 = max(a0, px0 + rc_i0(rc));
-                        a1 = min(a1, px0 + rc_i1(rc));
-                        if (a1 >= a0) c = (uint32_t)(a1 - a0 + 1);
-                        d0 = o | ((uint32_t)(j - py0) << 8) | ((uint32_t)(a0 - px0) << 13);
-                    }
-                    const uint32_t inc = wave_inclusive_scan(c);
-                    const uint32_t pc = inc - c;
-                    const uint32_t P = wave_last(inc);
-                    for (uint32_t w0 = 0; w0 < P; w0 += PIX_WINDOW) {
-                        const uint32_t m0 = pc > w0 ? pc : w0;
-                        const uint32_t m1 = min(pc + c, w0 + PIX_WINDOW);
-                        // descriptor of pixel a0 + (m - pc) of this lane's row
-                        for (uint32_t m = m0; m < m1; ++m) pdesc[m - w0] = d0 + ((m - pc) << 13);
-                        wave_sync();
-                        const uint32_t wl = min(P - w0, PIX_WINDOW);
-                        for (uint32_t p0 = 0; p0 < wl; p0 += 64) {
-                            const uint32_t pl = p0 + lane;
-                            if (pl < wl) {
-                                const uint32_t d = pdesc[pl];
-                                const uint32_t ow = d & 0xFFu;
-                                const int j = py0 + (int)((d >> 8) & 31u);
-                                const int i = px0 + (int)(d >> 13);
-                                const Seg sp = rec_load<GB>(rf, nb, ow);
-                                uint32_t q;
-                                bool cc, ca;
-                                float ts, z;
-                                const bool msk = cover_tz(sp, i, j, rk.r_min, zn, inv_range, cc,
-                                                          ca, q, ts, z);
-                                const uint32_t x =
-                                    (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
-                                if (DOM) {
-                                    if (ca) dom_count(cnt, q0t, x, TT, q, dk);
-                                } else if (msk) {
-                                    const uint64_t low =
-                                        GB ? gb_payload(gk.tan, gk.rgb, r_sid[ow], ts, z, sp.iz1)
-                                           : (uint64_t)r_sid[ow];
-                                    const unsigned long long key =
-                                        ((unsigned long long)q << HM_ID_BITS) | low;
-                                    if (cc) atomicMin((unsigned long long *)&lc[x], key);
-                                    if (ca) atomicMin((unsigned long long *)&la[x], key);
-                                }
-                            }
-                        }
-                        wave_sync();
-                    }
+            }
+            uint32_t curo = 0xFFFFFFFFu, vo = 0, rc = 0;
+            Seg sr;
+            int jb = 0;
+            uint32_t pb = 0;
+            for (uint32_t rr = r_beg; rr < r_end; ++rr) {
+                while (ow + 1 < nseg && rc_slot(r_rc[ow + 1]) <= rr) ++ow;
+                if (ow != curo) {
+                    curo = ow;
+                    sr = rec_load<GB>(rf, nb, ow);
+                    vo = r_sid[ow];
+                    rc = r_rc[ow];
+                    jb = py0 + rc_j0(rc);
+                    pb = rc_slot(rc);
                 }
-            } else {
-                const uint32_t per = (tot + nb - 1) / nb;
-                const uint32_t r_beg = threadIdx.x * per;
-                const uint32_t r_end = min(r_beg + per, tot);
-                uint32_t ow = 0;
-                if (r_beg < r_end) {            // owner of the first slot: binary search
-                    uint32_t h2 = nseg;
-                    while (h2 - ow > 1) {
-                        const uint32_t mid = (ow + h2) >> 1;
-                        if (rc_slot(r_rc[mid]) <= r_beg) ow = mid; else h2 = mid;
-                    }
-                }
-                uint32_t cur = 0xFFFFFFFFu, vo = 0, rc = 0;
-                Seg sr;
-                int jb = 0;
-                uint32_t pb = 0;
-                for (uint32_t rr = r_beg; rr < r_end; ++rr) {
-                    while (ow + 1 < nseg && rc_slot(r_rc[ow + 1]) <= rr) ++ow;
-                    if (ow != cur) {
-                        cur = ow;
-                        sr = rec_load<GB>(rf, nb, ow);
-                        vo = r_sid[ow];
-                        rc = r_rc[ow];
-                        jb = py0 + rc_j0(rc);
-                        pb = rc_slot(rc);
-                    }
-                    const int j = jb + (int)(rr - pb);
-                    int a0, a1;
-                    row_span(sr, j, a0, a1);
-                    a0 = max(a0, px0 + rc_i0(rc));
-                    a1 = min(a1, px0 + rc_i1(rc));
-                    for (int i = a0; i <= a1; ++i) {
-                        uint32_t q;
-                        bool cc, ca;
-                        float ts, z;
-                        const bool msk =
-                            cover_tz(sr, i, j, rk.r_min, zn, inv_range, cc, ca, q, ts, z);
-                        const uint32_t x = (uint32_t)(j - py0) * rk.T + (uint32_t)(i - px0);
-                        if (DOM) {
-                            if (ca) dom_count(cnt, q0t, x, TT, q, dk);
-                            continue;
-                        }
-                        if (!msk) continue;
-                        const uint64_t low =
-                            GB ? gb_payload(gk.tan, gk.rgb, vo, ts, z, sr.iz1)
-                               : (uint64_t)vo;
-                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
-                        if (cc) atomicMin((unsigned long long *)&lc[x], key);
-                        if (ca) atomicMin((unsigned long long *)&la[x], key);
-                    }
+                const int j = jb + (int)(rr - pb);
+                int a0, a1;
+                row_span(sr, j, a0, a1);
+                a0 = max(a0, px0 + rc_i0(rc));
+                a1 = min(a1, px0 + rc_i1(rc));
+                for (int i = a0; i <= a1; ++i) {
+                    uint32_t q;
+                    bool cc, ca;
+                    float ts, z;
+                    if (!cover_tz(sr, i, j, rk.r_min, zn, inv_range, cc, ca, q, ts, z)) continue;
+                    const uint32_t x = (uint32_t)(j - py0) * P + (uint32_t)(i - px0);
+                    const uint64_t low =
+                        GB ? gb_payload(gk.tan, gk.rgb, vo, ts, z, sr.iz1) : (uint64_t)vo;
+                    const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
+                    if (cc) atomicMin((unsigned long long *)&lc[x], key);
+                    if (ca) atomicMin((unsigned long long *)&la[x], key);
                 }
             }
             __syncthreads();
         }
-        for (uint32_t x = threadIdx.x; x < TT; x += blockDim.x) {
-            const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
-            if (lx >= tw || ly >= th) continue;
-            const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
-            if (DOM) {
+        tile_keys_store(lc, la, it, rk, vc, va);
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------ per-pixel spread
+// The spread walks each segment along lines of candidate pixels parallel to
+// its major axis: a steep segment (|dy| > |dx|) down columns, any other along
+// rows, so that a line holds several candidates.  Its records are those of the
+// row walker (rec_store) with the last field, the reciprocal used to clip a
+// line, holding 1 / dx for a column segment (1 / dy for a row one, 0 when that
+// displacement is below 1e-3), then the stream id and the line word: first
+// line slot (14 bits) | first fixed coordinate in the tile (5) << 14 |
+// varying clip v0, v1 in the tile (5 + 5) << 19, 24 | orientation (1 =
+// columns) << 29.  The candidates themselves are tested with cover_tz's
+// expressions in (x, y), whatever the orientation.
+
+// Pixel descriptors per wave between evaluations (a window of one wave's
+// candidates, gathered over several 64-line groups).
+constexpr uint32_t PIX_WINDOW = 240;
+
+// dynamic LDS bytes of k_raster_flat for tile edge T, `block` threads and a
+// tile of `tile_w` 32-bit words: the tile, the segment records, the bitmap of
+// first line slots, the first segment of every 64-slot group, and per wave a
+// window of pixel descriptors.  T = 32 with 256 threads takes 40704 B, so four
+// workgroups fit a CU's 160 KiB.
+static inline uint32_t flat_lds_bytes(uint32_t T, uint32_t block, bool gb, uint32_t tile_w)
+{
+    const uint32_t slots = block * T;
+    return tile_w * 4u + block * 4u * rec_words(gb) + slots / 8u + ((slots + 63u) / 64u) * 4u +
+           (block / 64u) * PIX_WINDOW * 4u;
+}
+
+// Fixed coordinates [f0, f1] of the tile that the segment can reach: clip it to
+// the tile's slab [v_lo, v_hi] of the varying axis widened by ra (+ slack) and
+// keep the lines whose band [c - ra, c + 1 + ra] meets the clipped part's f
+// extent (tile_rows in the segment's frame: rows for col = false, columns for
+// col = true).  False if none remain.
+__device__ __forceinline__ bool tile_lines(const Seg &sg, bool col, int v_lo, int v_hi, int &f0,
+                                           int &f1)
+{
+    const float e = sg.e;
+    const float o = col ? sg.y0 : sg.x0, of = col ? sg.x0 : sg.y0;
+    const float a = col ? sg.dy : sg.dx, b = col ? sg.dx : sg.dy;
+    const float vmn = col ? sg.symn : sg.sxmn, vmx = col ? sg.symx : sg.sxmx;
+    float fa = col ? sg.sxmn : sg.symn, fb = col ? sg.sxmx : sg.symx;
+    const float xl = ((float)v_lo - sg.ra) - e, xh = (((float)v_hi + 1.0f) + sg.ra) + e;
+    if (fabsf(a) > 1e-3f) {
+        const float ia = 1.0f / a;
+        const float ta = (xl - o) * ia, tb = (xh - o) * ia;
+        const float t0 = fmaxx(fminx(ta, tb), 0.0f), t1 = fminx(fmaxx(ta, tb), 1.0f);
+        if (t0 > t1) return false;
+        const float y_a = of + t0 * b, y_b = of + t1 * b;
+        fa = fminx(y_a, y_b);
+        fb = fmaxx(y_a, y_b);
+    } else if (vmx < xl || vmn > xh) {
+        return false;
+    }
+    const float flo = ((fa - 1.0f) - sg.ra) - e, fhi = (fb + sg.ra) + e;
+    if (flo > -1.0e9f) f0 = max(f0, (int)ceilf(flo));
+    if (fhi < 1.0e9f) f1 = min(f1, (int)floorf(fhi));
+    return f0 <= f1;
+}
+
+// Candidate varying coordinates [v0, v1] of the line at fixed coordinate cf of
+// record k (row_span in the segment's frame: pixel (v, cf) can pass either test
+// only if the segment has a point within ra of both of its bands; same slack).
+__device__ __forceinline__ void line_span(const float *rf, uint32_t nb, uint32_t k, bool col,
+                                          int cf, int &v0, int &v1)
+{
+    const Seg sg = rec_load<false>(rf, nb, k);      // e recomputed; ifx in the idy slot
+    const float e = sg.e, ra = sg.ra;
+    const float of = col ? sg.x0 : sg.y0, ifx = sg.idy;
+    const float ylo = ((float)cf - ra) - e, yhi = (((float)cf + 1.0f) + ra) + e;
+    float xlo = col ? sg.symn : sg.sxmn, xhi = col ? sg.symx : sg.sxmx;
+    if (ifx != 0.0f) {
+        const float ta = (ylo - of) * ifx, tb = (yhi - of) * ifx;
+        const float t0 = fmaxx(fminx(ta, tb), 0.0f), t1 = fminx(fmaxx(ta, tb), 1.0f);
+        if (t0 > t1) { v0 = 1; v1 = 0; return; }
+        const float o = col ? sg.y0 : sg.x0, a = col ? sg.dy : sg.dx;
+        const float xa = o + t0 * a, xb = o + t1 * a;
+        xlo = fminx(xa, xb);
+        xhi = fmaxx(xa, xb);
+    } else if ((col ? sg.sxmx : sg.symx) < ylo || (col ? sg.sxmn : sg.symn) > yhi) {
+        v0 = 1; v1 = 0;
+        return;
+    }
+    const float flo = ((xlo - 1.0f) - ra) - e, fhi = (xhi + ra) + e;
+    v0 = flo > -1.0e9f ? (int)ceilf(flo) : -1000000000;
+    v1 = fhi < 1.0e9f ? (int)floorf(fhi) : 1000000000;
+}
+
+// Tile raster with the per-pixel spread (HM_RASTER_TILED; also the counting
+// pass of deep-opacity maps, DOM, and compressed G-buffer keys, GB).  Work
+// items are pulled from counters[1]; segments are taken in batches of nb = the
+// workgroup size, one per lane:
+//   1. each lane builds its segment's oriented record and the lines (rows or
+//      columns) of the tile it can reach; one block scan compacts the segments
+//      and numbers their lines ("line slots"); a bitmap marks every segment's
+//      first slot and each 64-slot group notes the segments before it;
+//   2. waves take 64-slot groups from an LDS counter; each lane computes one
+//      line's candidate span, and the wave appends the candidates' descriptors
+//      (segment | row and column in the tile) to its window, which gathers the
+//      candidates of several groups;
+//   3. a full window (and the last one of the batch) is evaluated one
+//      candidate per lane, 64 at a time, with LDS 64-bit minima into the tile.
+// NB: the workgroup size when known at compile time (fixed LDS offsets), 0 for
+// any blockDim (at most 256).
+template <uint32_t NB, bool DOM, bool GB>
+__global__ __launch_bounds__(256) void k_raster_flat(
+    const float4 *proj, const uint8_t *flags, const uint32_t *scene_off, const hm_camera *cams,
+    RasterK rk, uint32_t cap, const uint32_t *tile_off, const uint32_t *item_off,
+    const uint32_t *item_tile, const uint32_t *entries, uint32_t *counters, uint64_t *vis,
+    DomK dk, GbK gk)
+{
+    extern __shared__ uint64_t lds[];
+    __shared__ uint32_t sh_item, sh_group;
+    __shared__ uint32_t sh_scan[1024 / 64 + 1];
+    const uint32_t P = tile_pitch(rk.T);
+    const uint32_t TP = rk.T * P;
+    const uint32_t nb = NB ? NB : blockDim.x;
+    uint64_t *lc = lds, *la = lds + TP;
+    uint32_t *q0t = reinterpret_cast<uint32_t *>(lds), *cnt = q0t + TP;    // DOM only
+    float *rf = reinterpret_cast<float *>(lds) + tile_words(TP, DOM, dk.n_layers);
+    uint32_t *rw = reinterpret_cast<uint32_t *>(rf);
+    uint32_t *r_sid = rw + rec_floats(GB) * nb;      // stream id
+    uint32_t *r_rc = r_sid + nb;                     // line word
+    const uint32_t slots_max = nb * rk.T;
+    uint32_t *bmp = r_rc + nb;                       // first slot of each segment
+    uint32_t *gfirst = bmp + slots_max / 32u;        // segment count before each group
+    const uint32_t wv = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    uint32_t *pdesc = gfirst + (slots_max + 63u) / 64u + wv * PIX_WINDOW;
+    const uint64_t le = (2ull << lane) - 1ull;          // lanes <= this one
+    const float rmin = __builtin_canonicalizef(rk.r_min);
+
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    const uint32_t n_items = item_off[rk.n_tiles];
+    const size_t hw = (size_t)rk.W * rk.H;
+    for (;;) {
+        if (threadIdx.x == 0) sh_item = atomicAdd(&counters[1], 1u);
+        __syncthreads();
+        const uint32_t item = sh_item;
+        if (item >= n_items) break;
+        const TileItem it = tile_item(rk, item, tile_off, item_off, item_tile);
+        const int px0 = it.px0, py0 = it.py0;
+        const float zn = cams[it.s].znear, zf = cams[it.s].zfar;
+        const float inv_range = 1.0f / (zf - zn);
+        // every 1/z of the item lies in (1/zf, 1/zn) up to a few ulps
+        const bool fast = zn >= 0x1p-124f && zf <= 0x1p124f;
+        uint64_t *vc = vis + (size_t)it.s * 2 * hw, *va = vc + hw;
+        if (DOM) {
+            for (uint32_t x = threadIdx.x; x < rk.T * rk.T; x += blockDim.x) {
+                const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+                uint32_t q0 = 0xFFFFFFFFu;
+                if (lx < it.tw && ly < it.th) {
+                    const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
+                    q0 = (uint32_t)(va[p] >> HM_ID_BITS);
+                }
+                q0t[ly * P + lx] = q0;
+            }
+            for (uint32_t x = threadIdx.x; x < dk.n_layers * TP; x += blockDim.x) cnt[x] = 0u;
+        } else {
+            tile_keys_init(lc, la, it, rk, vc, va);
+        }
+        __syncthreads();
+
+        // each batch's stream inputs are loaded during the previous batch
+        uint32_t nx_u = 0;
+        EntryIn nx{};
+        if (it.beg + threadIdx.x < it.end) {
+            nx_u = entries[it.beg + threadIdx.x];
+            nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
+        }
+        for (uint32_t e0 = it.beg; e0 < it.end; e0 += nb) {
+            const uint32_t e = e0 + threadIdx.x;
+            const EntryIn cur = nx;
+            const bool more = e0 + nb < it.end;
+            if (more && e + nb < it.end) nx_u = entries[e + nb];
+            // 1. oriented record and reachable lines of this lane's segment
+            uint32_t nr = 0, vu = 0;
+            bool col = false;
+            Seg sg;
+            int f0 = 0, f1 = -1, v0c = 0, v1c = -1;
+            if (e < it.end) {
+                vu = cur.v;
+                int i0, i1, j0, j1;
+                if (seg_from(cur, n, rk.r_min, sg) && seg_box(sg, rk.W, rk.H, i0, i1, j0, j1)) {
+                    i0 = max(i0, px0);
+                    i1 = min(i1, it.px1);
+                    j0 = max(j0, py0);
+                    j1 = min(j1, it.py1);
+                    col = fabsf(sg.dy) > fabsf(sg.dx);
+                    f0 = col ? i0 : j0;
+                    f1 = col ? i1 : j1;
+                    v0c = col ? j0 : i0;
+                    v1c = col ? j1 : i1;
+                    if (i0 <= i1 && j0 <= j1 && tile_lines(sg, col, v0c, v1c, f0, f1))
+                        nr = (uint32_t)(f1 - f0 + 1);
+                }
+            }
+            for (uint32_t x = threadIdx.x; x < slots_max / 32u; x += blockDim.x) bmp[x] = 0u;
+            // one scan: bits 0..13 number the line slots (at most nb * T <=
+            // 8192), bits 14..22 compact the segments that reach the tile,
+            // bits 23..31 count those of zero length (at most nb <= 256 each)
+            const bool degen = nr && !(sg.len2 > 0.0f);
+            uint32_t totp;
+            const uint32_t pre = block_exclusive_scan(
+                nr | (nr ? 1u << 14 : 0u) | (degen ? 1u << 23 : 0u), sh_scan, totp);
+            const uint32_t tot = totp & 0x3FFFu;
+            const bool any_degen = (totp >> 23) != 0u;
+            if (nr) {
+                const uint32_t c = (pre >> 14) & 0x1FFu, r0 = pre & 0x3FFFu;
+                const int fb0 = col ? px0 : py0, vb0 = col ? py0 : px0;
+                // the line-clipping reciprocal of the segment's orientation
+                Seg sr = sg;
+                const float b = col ? sg.dx : sg.dy;
+                sr.idy = fabsf(b) > 1e-3f ? 1.0f / b : 0.0f;
+                rec_store<GB>(rf, nb, c, sr);
+                r_sid[c] = vu;
+                r_rc[c] = r0 | ((uint32_t)(f0 - fb0) << 14) | ((uint32_t)(v0c - vb0) << 19) |
+                          ((uint32_t)(v1c - vb0) << 24) | ((uint32_t)col << 29);
+                atomicOr(&bmp[r0 >> 5], 1u << (r0 & 31u));
+                // groups whose first slot lies in this segment's slots: the
+                // segments before the group are this one's predecessors, plus
+                // this one unless the group starts at its first slot
+                for (uint32_t g = (r0 + 63u) >> 6; (g << 6) < r0 + nr; ++g)
+                    gfirst[g] = c + ((g << 6) > r0 ? 1u : 0u);
+            }
+            if (threadIdx.x == 0) sh_group = 0u;
+            __syncthreads();
+            if (more && e + nb < it.end) nx = entry_load(proj, flags, scene_off, rk, n, nx_u);
+
+            // 2. + 3. lines and candidates, per wave
+            const uint32_t ng = (tot + 63u) >> 6;
+            uint32_t fill = 0;                    // wave-uniform window fill
+            uint32_t Ptot = 0, done = 0;
+            bool pend = false, exhausted = ng == 0;
+            uint32_t cntl = 0, pcl = 0, d0 = 0, dstep = 0;   // this lane's line of the pending group
+            for (;;) {
+                if (!pend && !exhausted) {
+                    uint32_t gg = 0;
+                    if (lane == 0) gg = atomicAdd(&sh_group, 1u);
+                    const uint32_t g = (uint32_t)__builtin_amdgcn_readfirstlane((int)gg);
+                    if (g >= ng) {
+                        exhausted = true;
+                        continue;
+                    }
+                    const uint32_t rr = g * 64u + lane;
+                    const bool start = rr < tot && ((bmp[rr >> 5] >> (rr & 31u)) & 1u);
+                    const uint64_t M = __ballot(start);
+                    cntl = 0;
+                    if (rr < tot) {
+                        const uint32_t o = gfirst[g] + (uint32_t)__popcll(M & le) - 1u;
+                        const uint32_t rc = r_rc[o];
+                        const bool cl = (rc >> 29) & 1u;
+                        const int vb0 = cl ? py0 : px0;
+                        const uint32_t frel = ((rc >> 14) & 31u) + (rr - (rc & 0x3FFFu));
+                        int a0, a1;
+                        line_span(rf, nb, o, cl, (cl ? px0 : py0) + (int)frel, a0, a1);
+                        a0 = max(a0, vb0 + (int)((rc >> 19) & 31u));
+                        a1 = min(a1, vb0 + (int)((rc >> 24) & 31u));
+                        if (a1 >= a0) cntl = (uint32_t)(a1 - a0 + 1);
+                        // descriptor of the line's first candidate: segment |
+                        // row in the tile << 8 | column << 13; the next
+                        // candidates step down the column or along the row
+                        const uint32_t vr = (uint32_t)(a0 - vb0);
+                        d0 = o | ((cl ? vr : frel) << 8) | ((cl ? frel : vr) << 13);
+                        dstep = cl ? 1u << 8 : 1u << 13;
+                    }
+                    const uint32_t inc = wave_inclusive_scan(cntl);
+                    pcl = inc - cntl;
+                    Ptot = wave_last(inc);
+                    if (Ptot == 0) continue;
+                    pend = true;
+                    done = 0;
+                }
+                bool eval;
+                if (pend) {
+                    // append the part of the group's candidates that fits
+                    const uint32_t room = PIX_WINDOW - fill;
+                    const uint32_t nn = min(Ptot - done, room);
+                    const uint32_t m0 = max(pcl, done), m1 = min(pcl + cntl, done + nn);
+                    if (m0 < m1) {
+                        uint32_t *dst = pdesc + fill + (m0 - done);
+                        const uint32_t db = d0 + (m0 - pcl) * dstep;
+                        for (uint32_t s = 0; s < m1 - m0; ++s) dst[s] = db + s * dstep;
+                    }
+                    fill += nn;
+                    done += nn;
+                    if (done == Ptot) pend = false;
+                    eval = fill == PIX_WINDOW;
+                } else {
+                    if (fill == 0) break;     // no group left
+                    eval = true;
+                }
+                if (!eval) continue;
+                wave_sync();
+                // evaluate the window, one candidate per lane; compiled apart
+                // for the (uniform) reciprocal path and for batches holding a
+                // segment of zero length
+                auto evaluate = [&](auto fast_tag, auto degen_tag) {
+                    constexpr bool FAST = decltype(fast_tag)::value;
+                    constexpr bool DEGEN = decltype(degen_tag)::value;
+                    for (uint32_t p0 = 0; p0 < fill; p0 += 64) {
+                        const uint32_t pl = p0 + lane;
+                        if (pl >= fill) continue;
+                        const uint32_t d = pdesc[pl];
+                        const uint32_t o = d & 0xFFu;
+                        const uint32_t jl = (d >> 8) & 31u, il = d >> 13;
+                        const uint32_t x = __umul24(jl, P) + il;
+                        const float fi = (float)(px0 + (int)il), fj = (float)(py0 + (int)jl);
+                        const float x0 = rf[0 * nb + o], y0 = rf[1 * nb + o];
+                        const float w0 = rf[2 * nb + o], dx = rf[4 * nb + o];
+                        const float dy = rf[5 * nb + o], dw = rf[6 * nb + o];
+                        const float len2 = rf[8 * nb + o], ilen2 = rf[9 * nb + o];
+                        const float ra = rf[10 * nb + o];
+                        // cover_tz's expressions: centre sample
+                        const float ux = (fi + 0.5f) - x0;
+                        const float uy = (fj + 0.5f) - y0;
+                        const float tn = ux * dx + uy * dy;
+                        const float t = tn * ilen2;
+                        const float wt = w0 + t * dw;
+                        const float r = fmaxf(0.5f * wt, rmin);
+                        const float r2 = r * r;
+                        const float cr = ux * dy - uy * dx;
+                        bool cc = (tn >= 0.0f) & (tn < len2) & (cr * cr <= r2 * len2);
+                        // a segment of zero length: distance to its point
+                        if (DEGEN && !(len2 > 0.0f)) cc = (ux * ux + uy * uy) <= r2;
+                        // conservative: separating axes x, y and the normal
+                        const float bx0 = fi - ra, bx1 = (fi + 1.0f) + ra;
+                        const float by0 = fj - ra, by1 = (fj + 1.0f) + ra;
+                        const float fa = (bx0 - x0) * dy, fb = (bx1 - x0) * dy;
+                        const float ga = (by0 - y0) * dx, gb = (by1 - y0) * dx;
+                        const float lo = fminf(fa, fb) - fmaxf(ga, gb);
+                        const float hi = fmaxf(fa, fb) - fminf(ga, gb);
+                        const bool ca = (rf[11 * nb + o] <= bx1) & (rf[12 * nb + o] >= bx0) &
+                                        (rf[13 * nb + o] <= by1) & (rf[14 * nb + o] >= by0) &
+                                        (lo <= 0.0f) & (hi >= 0.0f);
+                        if (!(cc | ca)) continue;
+                        // depth at the clamped closest point
+                        float ts = t;
+                        ts = fmaxx(ts, 0.0f);
+                        ts = fminx(ts, 1.0f);
+                        const float iz = rf[3 * nb + o] + ts * rf[7 * nb + o];
+                        const float z = FAST ? rcp_refined(iz) : 1.0f / iz;
+                        const uint32_t q = depth_code(z, zn, inv_range);
+                        if (DOM) {
+                            if (ca) dom_count(cnt, q0t, x, TP, q, dk);
+                        } else {
+                            const uint64_t low =
+                                GB ? gb_payload(gk.tan, gk.rgb, r_sid[o], ts, z,
+                                                rf[REC_FLOATS * nb + o])
+                                   : (uint64_t)r_sid[o];
+                            const unsigned long long key =
+                                ((unsigned long long)q << HM_ID_BITS) | low;
+                            if (cc) atomicMin((unsigned long long *)&lc[x], key);
+                            if (ca) atomicMin((unsigned long long *)&la[x], key);
+                        }
+                    }
+                };
+                using yes = std::true_type;
+                using no = std::false_type;
+                if (fast) {
+                    if (any_degen) evaluate(yes{}, yes{}); else evaluate(yes{}, no{});
+                } else {
+                    if (any_degen) evaluate(no{}, yes{}); else evaluate(no{}, no{});
+                }
+                wave_sync();
+                fill = 0;
+            }
+            __syncthreads();
+        }
+        if (DOM) {
+            for (uint32_t x = threadIdx.x; x < rk.T * rk.T; x += blockDim.x) {
+                const uint32_t ly = x / rk.T, lx = x - ly * rk.T;
+                if (lx >= it.tw || ly >= it.th) continue;
+                const size_t p = (size_t)(py0 + (int)ly) * rk.W + (size_t)(px0 + (int)lx);
                 for (uint32_t k = 0; k < dk.n_layers; ++k) {
-                    const uint32_t c = cnt[k * TT + x];
-                    if (whole) dk.counts[(size_t)k * hw + p] = c;
+                    const uint32_t c = cnt[k * TP + ly * P + lx];
+                    if (it.whole) dk.counts[(size_t)k * hw + p] = c;
                     else if (c) atomicAdd(dk.counts + (size_t)k * hw + p, c);
                 }
-                continue;
             }
-            const uint64_t kc = lc[x], ka = la[x];
-            if (whole) {
-                vc[p] = kc;
-                va[p] = ka;
-            } else {
-                if (kc != HM_EMPTY) atomicMin((unsigned long long *)(vc + p), (unsigned long long)kc);
-                if (ka != HM_EMPTY) atomicMin((unsigned long long *)(va + p), (unsigned long long)ka);
-            }
+        } else {
+            tile_keys_store(lc, la, it, rk, vc, va);
         }
         __syncthreads();
     }
@@ -1161,8 +1456,10 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
 
 uint32_t raster_lds_bytes(const hm_raster_params &p)
 {
-    return tile_lds_bytes(p.tile, p.block, p.algo == HM_RASTER_TILED,
-                          p.payload == HM_PAYLOAD_GBUFFER);
+    const bool gb = p.payload == HM_PAYLOAD_GBUFFER;
+    if (p.algo == HM_RASTER_TILED)
+        return flat_lds_bytes(p.tile, p.block, gb, tile_words(p.tile * tile_pitch(p.tile), false, 1u));
+    return rows_lds_bytes(p.tile, p.block, gb);
 }
 
 size_t raster_workspace(const hm_frame &f, uint32_t cap, const hm_raster_params &p)
@@ -1184,12 +1481,22 @@ void raster_defaults(const hm_frame &f, hm_raster_params &p)
     p.payload = HM_PAYLOAD_SEGMENT;
 }
 
+// Prefill grid: one row of workgroups per scene (rows loop when a frame has
+// more than 65535 scenes), about 4096 workgroups in all.
+static dim3 prefill_grid(const hm_frame &f)
+{
+    const size_t hw = (size_t)f.width * f.height;
+    const uint32_t rows = std::min<uint32_t>(f.n_scenes, 65535u);
+    const uint32_t per = std::max<uint32_t>(1u, std::min<uint32_t>(stride_grid(hw, 256),
+                                                                     4096u / rows));
+    return dim3(per, rows);
+}
+
 void launch_prefill(uint64_t *vis, const float *scene_z, const hm_camera *cams,
                     const hm_frame &f, hipStream_t st)
 {
-    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
-    hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
-                       cams, f.n_scenes, f.width, f.height, (uint32_t *)nullptr, 0u,
+    hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
+                       f.n_scenes, f.width, f.height, (uint32_t *)nullptr, 0u,
                        (uint32_t *)nullptr, 0u);
 }
 
@@ -1201,8 +1508,9 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     RasterWs w = carve(ws, f, s.cap, p);
     const size_t npix = (size_t)f.width * f.height * f.n_scenes;
     const bool tiled = p.algo != HM_RASTER_DIRECT;
-    hipLaunchKernelGGL(k_prefill, dim3(stride_grid(npix, 256)), dim3(256), 0, st, vis, scene_z,
-                       cams, f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
+    (void)npix;
+    hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
+                       f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
                        tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
     const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
     const size_t units = (size_t)s.cap * units_per_cp(f, p);
@@ -1249,29 +1557,37 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                        w.max_items);
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
-#define HM_TILES_LAUNCH(FL, NB, GB)                                                            \
-    hipLaunchKernelGGL((k_raster_tiles<FL, NB, false, GB>), dim3(grid), dim3(p.block), lds, st,  \
+#define HM_FLAT_LAUNCH(NB, GB)                                                                 \
+    hipLaunchKernelGGL((k_raster_flat<NB, false, GB>), dim3(grid), dim3(p.block), lds, st,       \
                        (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,  \
                        s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,          \
-                       (const uint32_t *)w.item_tile, (const uint32_t *)w.entries, w.counters, vis, DomK{nullptr, 1u, 1u}, gk)
-    if (gbuf) {
-        // G-buffer keys: the default shape compiled for its block size, others generic
-        if (p.algo == HM_RASTER_TILED) {
-            if (p.block == 256) HM_TILES_LAUNCH(true, 256, true);
-            else HM_TILES_LAUNCH(true, 0, true);
+                       (const uint32_t *)w.item_tile, (const uint32_t *)w.entries, w.counters,  \
+                       vis, DomK{nullptr, 1u, 1u}, gk)
+#define HM_ROWS_LAUNCH(NB, GB)                                                                 \
+    hipLaunchKernelGGL((k_raster_rows<NB, GB>), dim3(grid), dim3(p.block), lds, st,              \
+                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams, rk,  \
+                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,          \
+                       (const uint32_t *)w.item_tile, (const uint32_t *)w.entries, w.counters,  \
+                       vis, gk)
+    // the default shapes compiled for their block size (fixed LDS offsets),
+    // others generic
+    if (p.algo == HM_RASTER_TILED) {
+        if (gbuf) {
+            if (p.block == 256) HM_FLAT_LAUNCH(256, true);
+            else HM_FLAT_LAUNCH(0, true);
         } else {
-            HM_TILES_LAUNCH(false, 0, true);
+            if (p.block == 256) HM_FLAT_LAUNCH(256, false);
+            else HM_FLAT_LAUNCH(0, false);
         }
-    } else if (p.algo == HM_RASTER_TILED) {
-        if (p.block == 256) HM_TILES_LAUNCH(true, 256, false);
-        else if (p.block == 128) HM_TILES_LAUNCH(true, 128, false);
-        else HM_TILES_LAUNCH(true, 0, false);
+    } else if (gbuf) {
+        HM_ROWS_LAUNCH(0, true);
     } else {
-        if (p.block == 512) HM_TILES_LAUNCH(false, 512, false);
-        else if (p.block == 256) HM_TILES_LAUNCH(false, 256, false);
-        else HM_TILES_LAUNCH(false, 0, false);
+        if (p.block == 512) HM_ROWS_LAUNCH(512, false);
+        else if (p.block == 256) HM_ROWS_LAUNCH(256, false);
+        else HM_ROWS_LAUNCH(0, false);
     }
-#undef HM_TILES_LAUNCH
+#undef HM_FLAT_LAUNCH
+#undef HM_ROWS_LAUNCH
     if (gbuf)
         hipLaunchKernelGGL((k_raster_long<false, true>), dim3(256), dim3(256), 0, st,
                            (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, cams,
@@ -1288,11 +1604,21 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
 
 namespace hm {
 
+// LDS of the counting pass: the first-fragment code and one count per layer
+// for every pixel of the tile instead of two 64-bit layers.
+static uint32_t dom_lds_bytes(uint32_t T, uint32_t n_layers)
+{
+    return flat_lds_bytes(T, 256u, false, tile_words(T * tile_pitch(T), true, n_layers));
+}
+
+// Raster shape of the light view: the defaults, with 16-pixel tiles when the
+// counting pass's LDS for 32-pixel tiles would exceed 64 KiB (many layers).
 static hm_raster_params dom_raster_params(const hm_frame &lf, const hm_dom_params &p)
 {
     hm_raster_params rp;
     raster_defaults(lf, rp);
     rp.r_min = p.r_min;
+    if (dom_lds_bytes(rp.tile, p.n_layers) > 65536u) rp.tile = 16;
     return rp;
 }
 
@@ -1327,12 +1653,10 @@ void launch_dom_accum(const hm_strands &s, const hm_camera *light, const hm_dom_
     hipLaunchKernelGGL(k_dom_clear, dim3(stride_grid(n, 256)), dim3(256), 0, st, counts,
                        (uint32_t)n, w.counters);
     const DomK dk{counts, p.layer_codes, p.n_layers};
-    const uint32_t TT = rp.tile * rp.tile;
-    const uint32_t lds = tile_lds_bytes(rp.tile, rp.block, true, false) - 4u * TT * 4u +
-                         tile_words(TT, true, p.n_layers) * 4u;
-    hipLaunchKernelGGL((k_raster_tiles<true, 256, true, false>), dim3(256u * 8u), dim3(256), lds,
-                       st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light,
-                       rk, s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
+    const uint32_t lds = dom_lds_bytes(rp.tile, p.n_layers);
+    hipLaunchKernelGGL((k_raster_flat<256, true, false>), dim3(256u * 8u), dim3(256), lds, st,
+                       (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off, light, rk,
+                       s.cap, (const uint32_t *)w.tile_cnt, (const uint32_t *)w.items,
                        (const uint32_t *)w.item_tile, (const uint32_t *)w.entries, w.counters,
                        light_vis, dk, GbK{nullptr, nullptr});
     hipLaunchKernelGGL((k_raster_long<true, false>), dim3(256), dim3(256), 0, st,

@@ -2,7 +2,9 @@
 //
 //   k_shade       one thread per pixel: shades the centre-sample hit once
 //                 (deferred, 1 spp) and writes a 16-byte record
-//                 {r, g, b, bits(depth24 | centre-hit << 24 | any-hit << 25)};
+//                 {r, g, b, word}: word = the centre hit's 24-bit depth code,
+//                 REC_CONS_ONLY for a pixel with a conservative hit only,
+//                 REC_EMPTY for no hit;
 //   k_filter      16 x 16 pixel workgroups stage the records of their tile
 //                 plus an r-pixel halo in LDS and run strand connection, the
 //                 elliptical bilateral filter and alpha estimation out of LDS;
@@ -14,6 +16,11 @@
 #include "hm_internal.hpp"
 
 namespace hm {
+
+// Record words of pixels without a centre hit: above every depth code and
+// further from it than any depth window of the filter (thresholds < 2^24 codes).
+constexpr uint32_t REC_EMPTY = 0x40000000u;
+constexpr uint32_t REC_CONS_ONLY = 0x60000000u;
 
 struct V3 { float x, y, z; };
 __device__ __forceinline__ V3 v3(float x, float y, float z) { return {x, y, z}; }
@@ -138,8 +145,8 @@ __global__ __launch_bounds__(256) void k_shade(const float4 *pos, const float4 *
                                                (double)j + 0.5);
             col = shade(g, c, k, k.shadow ? k.shadow[p] : 1.0f);
         }
-        const uint32_t bits = (hc ? (uint32_t)(kc >> HM_ID_BITS) : 0u) | (hc ? 1u << 24 : 0u) |
-                              ((hc || ha) ? 1u << 25 : 0u);
+        const uint32_t bits = hc ? (uint32_t)(kc >> HM_ID_BITS)
+                                 : (ha ? REC_CONS_ONLY : REC_EMPTY);
         if (rec) rec[p] = make_float4(col.x, col.y, col.z, __uint_as_float(bits));
         if (out) {
             out[p] = hc ? make_float4(col.x, col.y, col.z, 1.0f)
@@ -233,9 +240,10 @@ struct FilterPix {
 __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, float fx, float r1,
                                            float r0, float4 Q)
 {
-    const uint32_t bits = __float_as_uint(Q.w);
-    // centre-sample hit within the depth window [qP - rej, qP + rej]
-    const bool take = ((bits >> 24) & 1u) & (((bits & 0xFFFFFFu) - f.q_lo) <= f.q_span);
+    // centre-sample hit within the depth window [qP - rej, qP + rej]: a
+    // centre hit's word is its depth code, every other word lies above 2^29,
+    // beyond any window
+    const bool take = (__float_as_uint(Q.w) - f.q_lo) <= f.q_span;
     // continuous weight (tolerance-compared): fused multiply-adds are fine here
     const float esp = fmaf(fx, fmaf(f.qa, fx, r1), r0);
     const float d0 = f.Cx - Q.x, d1 = f.Cy - Q.y, d2 = f.Cz - Q.z;
@@ -285,8 +293,8 @@ __device__ __forceinline__ void strip_counts(const float4 *tile, int E, int cx, 
             const float perp2 = ex * ex + ey * ey;
             if (perp2 <= h2) {
                 const uint32_t bits = __float_as_uint(tile[(cy + oy) * E + (cx + ox)].w);
-                Ha += (bits >> 25) & 1u;
-                Hc += (bits >> 24) & 1u;
+                Ha += bits != REC_EMPTY ? 1 : 0;
+                Hc += bits <= HM_QMAX ? 1 : 0;          // a centre hit's depth code
             }
         }
     }
@@ -314,7 +322,7 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     for (int x = threadIdx.x; x < E * E; x += blockDim.x) {
         const int ly = x / E, lx = x - ly * E;
         const int gi = ox0 + lx, gj = oy0 + ly;
-        float4 v = make_float4(0.f, 0.f, 0.f, __uint_as_float(0u));
+        float4 v = make_float4(0.f, 0.f, 0.f, __uint_as_float(REC_EMPTY));
         if (gi >= 0 && gj >= 0 && gi < (int)W && gj < (int)H) v = recs[(size_t)gj * W + gi];
         tile[ly * E + lx] = v;
     }
@@ -374,9 +382,12 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     a.acc = false;
     const float4 *ctr = tile + (lj + r) * E + (li + r);
     if (R > 0) {
+        // the window's top-left record: every tap at a fixed non-negative
+        // offset from it (an immediate of the LDS read)
+        const float4 *win = tile + lj * EMAX + li;
 #pragma unroll 1
         for (int oy = -R; oy <= R; ++oy) {
-            const float4 *row = ctr + oy * EMAX - R;    // non-negative LDS offsets
+            const float4 *row = win + (oy + R) * EMAX;
             const float fy = (float)oy;
             const float r1 = f.qb * fy, r0 = f.qc * (fy * fy);
 #pragma unroll

@@ -82,7 +82,7 @@ EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_
            "hm_dom_accumulate", "hm_dom_shadow", "hm_generate_raster",
            "hm_resolve_shade_noalloc"]
 # measurement helpers (include/hm_bench.h)
-BENCH_EXPORTS = ["hm_bench_atomics", "hm_bench_traffic"]
+BENCH_EXPORTS = ["hm_bench_atomics", "hm_bench_traffic", "hm_bench_reciprocal"]
 
 
 def lod_depth_offset(table, bundle_nstrands, delta_out):
@@ -113,6 +113,16 @@ def bench_traffic(kind: int, buf, sink, grid: int = 2048):
     nbytes = buf.numel() * buf.element_size()
     _check(L.hm_bench_traffic(kind, _ptr(buf), nbytes, _ptr(sink), grid, _stream()),
            "hm_bench_traffic")
+
+
+def bench_reciprocal(lo: int, hi: int, counts):
+    """Enqueue the exhaustive check of the raster's refined reciprocal over the
+    binary32 bit patterns [lo, hi); adds (mismatches, values tested) to counts
+    (a two-element int32 device tensor)."""
+    L = load()
+    L.hm_bench_reciprocal.argtypes = [_u32, _u32, _vp, _vp]
+    L.hm_bench_reciprocal.restype = _i32
+    _check(L.hm_bench_reciprocal(lo, hi, _ptr(counts), _stream()), "hm_bench_reciprocal")
 
 
 def generate_raster(mesh, table, strand_base, strand_rgb, gp, st, cams, fr, r_min, scene_z,
