@@ -347,6 +347,15 @@ def extra_fused(steps):
     t = hm.timing_collect()
     hm.timing_enable(False)
     r["kernel_ms_fused"] = {k: v[0] / max(v[1], 1) for k, v in sorted(t.items())}
+    # the paper's stream-free frame: generation fused with the raster into
+    # compressed G-buffer keys (no stream written), decode-only centre resolve
+    # -- against the separate generate + G-buffer raster + decode frame
+    ds.use_gbuffer()
+    ds.render_fused()
+    torch.cuda.synchronize()
+    r["stream_free_frame_ms"] = _time_ms(ds.render_fused, steps, 2)
+    r["stream_free_gen_raster_ms"] = _time_ms(ds.generate_raster, steps, 2)
+    r["gbuffer_frame_ms_separate"] = _time_ms(ds.render, steps, 2)
     del ds
     torch.cuda.empty_cache()
     return r

@@ -174,19 +174,27 @@ hm_status hm_generate_strands(const hm_hair_mesh *mesh, const uint32_t *table,
  * assembles strands and rasterizes their segments in the same workgroup,
  * without a separate pass over a stored stream).  One workgroup or one
  * wave per bundle (the rule of hm_generate_strands) generates its control
- * points exactly as hm_generate_strands (and writes them to out, for the
- * resolve), projects each one where it is made, and
- * rasterizes every segment of a finished chunk of strands from LDS with
- * global atomic minima on both layers.  vis receives exactly what
- * hm_raster_vis writes for the same stream (frame->n_scenes scenes, scene
- * of bundle b = mesh->bundle_scene[b]; r_min as hm_raster_params.r_min;
- * scene_z optional as there); no binning, so no workspace.  One view per
- * scene (no shared views). */
+ * points exactly as hm_generate_strands, projects each one where it is
+ * made, and rasterizes every segment of a finished chunk of strands from LDS
+ * with global atomic minima on both layers.  vis receives exactly what
+ * hm_raster_vis writes for the same stream and payload (frame->n_scenes
+ * scenes, scene of bundle b = mesh->bundle_scene[b]; r_min as
+ * hm_raster_params.r_min; scene_z optional as there); no binning, so no
+ * workspace.  One view per scene (no shared views).
+ * payload = HM_PAYLOAD_SEGMENT: the stream is also written to out (the
+ *   resolve reads it back by segment id).
+ * payload = HM_PAYLOAD_GBUFFER: the keys carry the compressed G-buffer data
+ *   (tangents from the points' neighbours and the strand colour, computed in
+ *   LDS) and NOTHING of the stream is written -- out->pos_w, rgb and flags
+ *   may be NULL; out->scene_off (the LOD output) and out->cap bound the
+ *   points as for any stream.  A CENTER resolve of these keys
+ *   (hm_shade_params.payload = HM_PAYLOAD_GBUFFER) reads no stream either:
+ *   the paper's stream-free frame. */
 hm_status hm_generate_raster(const hm_hair_mesh *mesh, const uint32_t *table,
                              const uint32_t *strand_base, const float *strand_rgb,
                              const hm_gen_params *p, const hm_strands *out,
                              const hm_camera *cams, const hm_frame *frame, float r_min,
-                             const float *scene_z, uint64_t *vis, void *stream);
+                             int32_t payload, const float *scene_z, uint64_t *vis, void *stream);
 
 /* HM_RASTER_TILED: screen tiles resolved in LDS, candidate pixels spread one
  *   per lane (workgroups of at most 256 threads);
@@ -276,7 +284,9 @@ typedef struct {
                               pixel centre from the middle of its depth code's
                               interval, unit tangent from the octahedral code,
                               albedo and AO (which scales the ambient term) from
-                              their 6-bit codes -- with no read of the stream */
+                              their 6-bit codes -- with no read of the stream (its
+                              arrays may then be NULL; scene_off and cap are
+                              still checked) */
 } hm_shade_params;
 
 /* Deferred resolve, out_rgba[S][height][width][4] float (straight colour

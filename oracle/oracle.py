@@ -26,7 +26,11 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "hm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# HM_ORACLE_SANITIZE=1 (tests only): a separate build under AddressSanitizer
+# and UndefinedBehaviorSanitizer, loaded by a process that preloads their
+# runtimes
+_SANITIZE = os.environ.get("HM_ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 
 EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 ID_BITS = 40
@@ -39,6 +43,9 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
                "-fopenmp", "-shared", "-o", _LIB, _SRC, "-lm"]
+        if _SANITIZE:
+            cmd[1:1] = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                        "-fno-omit-frame-pointer", "-g"]
         subprocess.run(cmd, check=True)
     return _LIB
 

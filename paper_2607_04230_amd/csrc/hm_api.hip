@@ -123,15 +123,23 @@ static hm_status check_mesh(const hm_hair_mesh *m)
     return HM_OK;
 }
 
-static hm_status check_strands(const hm_strands *s)
+// The stream's extent (scene offsets, scene count, capacity), for calls that
+// read no control point.
+static hm_status check_stream_bounds(const hm_strands *s)
 {
     REQUIRE(s, HM_ERR_INVALID, "strands is NULL");
-    REQUIRE(s->pos_w && s->rgb && s->flags && s->scene_off, HM_ERR_INVALID,
-            "strands has a NULL array");
+    REQUIRE(s->scene_off, HM_ERR_INVALID, "strands.scene_off is NULL");
     REQUIRE(s->n_scenes >= 1, HM_ERR_INVALID, "strands.n_scenes must be >= 1");
     REQUIRE(s->cap >= 1 && s->cap < 0xFFFFFFFFu, HM_ERR_RANGE,
             "strands.cap must be in [1, 2^32 - 2]");
     return HM_OK;
+}
+
+static hm_status check_strands(const hm_strands *s)
+{
+    REQUIRE(s, HM_ERR_INVALID, "strands is NULL");
+    REQUIRE(s->pos_w && s->rgb && s->flags, HM_ERR_INVALID, "strands has a NULL array");
+    return check_stream_bounds(s);
 }
 
 static hm_status check_ws(void *ws, size_t have, size_t need)
@@ -355,10 +363,14 @@ hm_status hm_generate_raster(const hm_hair_mesh *mesh, const uint32_t *table,
                              const uint32_t *strand_base, const float *strand_rgb,
                              const hm_gen_params *p, const hm_strands *out,
                              const hm_camera *cams, const hm_frame *frame, float r_min,
-                             const float *scene_z, uint64_t *vis, void *stream)
+                             int32_t payload, const float *scene_z, uint64_t *vis, void *stream)
 {
     hm_status st;
-    if ((st = check_mesh(mesh)) || (st = check_strands(out)) || (st = check_frame(frame)))
+    if ((st = check_mesh(mesh)) || (st = check_frame(frame))) return st;
+    REQUIRE(payload == HM_PAYLOAD_SEGMENT || payload == HM_PAYLOAD_GBUFFER, HM_ERR_INVALID,
+            "unknown payload %d", payload);
+    // G-buffer keys write no stream: its arrays may be NULL
+    if ((st = payload == HM_PAYLOAD_GBUFFER ? check_stream_bounds(out) : check_strands(out)))
         return st;
     REQUIRE(table && p && cams && vis, HM_ERR_INVALID, "NULL argument");
     REQUIRE(!strand_rgb || strand_base, HM_ERR_INVALID, "strand_rgb needs strand_base");
@@ -369,7 +381,7 @@ hm_status hm_generate_raster(const hm_hair_mesh *mesh, const uint32_t *table,
             "strands.n_scenes (%u) != frame.n_scenes (%u)", out->n_scenes, frame->n_scenes);
     REQUIRE(isfinite(r_min) && r_min >= 0.0f, HM_ERR_RANGE, "r_min must be finite, >= 0");
     launch_generate_raster(*mesh, table, strand_base, strand_rgb, *p, *out, cams, *frame, r_min,
-                           scene_z, vis, (hipStream_t)stream);
+                           payload, scene_z, vis, (hipStream_t)stream);
     return check_launch("hm_generate_raster");
 }
 
@@ -405,7 +417,10 @@ hm_status hm_resolve_shade(const hm_strands *s, const uint64_t *vis, const hm_ca
 {
     hm_status st;
     ShadeK k;
-    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    if ((st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    // a buffer of G-buffer keys is resolved without reading the stream
+    if ((st = k.payload == HM_PAYLOAD_GBUFFER ? check_stream_bounds(s) : check_strands(s)))
+        return st;
     REQUIRE(vis && cams && out_rgba, HM_ERR_INVALID, "NULL argument");
     if (k.mode == HM_RESOLVE_FILTER) {
         if ((st = check_ws(ws, ws_bytes, resolve_workspace(*frame)))) return st;
@@ -458,7 +473,9 @@ hm_status hm_resolve_shade_noalloc(const hm_strands *s, const uint64_t *vis,
 {
     hm_status st;
     ShadeK k;
-    if ((st = check_strands(s)) || (st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    if ((st = check_frame(frame)) || (st = make_shade(p, k))) return st;
+    if ((st = k.payload == HM_PAYLOAD_GBUFFER ? check_stream_bounds(s) : check_strands(s)))
+        return st;
     REQUIRE(vis && cams && out_rgba, HM_ERR_INVALID, "NULL argument");
     void *ws = nullptr;
     if (k.mode == HM_RESOLVE_FILTER) {

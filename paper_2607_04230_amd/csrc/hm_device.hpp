@@ -253,12 +253,10 @@ __device__ __forceinline__ uint32_t gb_oct16(float tx, float ty, float tz)
 // Payload of segment v (stream point v) at closest-point parameter ts and
 // linear depth z: the perspective-correct segment parameter
 // t3 = ts * (1/z_1) * z, then tangent and albedo interpolated at t3.
-__device__ __forceinline__ uint64_t gb_payload(const float4 *tan, const float4 *rgb, uint32_t v,
-                                               float ts, float z, float iz1)
+__device__ __forceinline__ uint64_t gb_payload_of(float4 T0, float4 T1, float4 c0, float4 c1,
+                                                  float ts, float z, float iz1)
 {
     const float t3 = (ts * iz1) * z;
-    const float4 T0 = tan[v], T1 = tan[v + 1];
-    const float4 c0 = rgb[v], c1 = rgb[v + 1];
     const float tx = T0.x + t3 * (T1.x - T0.x);
     const float ty = T0.y + t3 * (T1.y - T0.y);
     const float tz = T0.z + t3 * (T1.z - T0.z);
@@ -267,6 +265,33 @@ __device__ __forceinline__ uint64_t gb_payload(const float4 *tan, const float4 *
     const float cb = c0.z + t3 * (c1.z - c0.z);
     return ((uint64_t)gb_oct16(tx, ty, tz) << 24) | ((uint64_t)gb_q6(cr) << 18) |
            ((uint64_t)gb_q6(cg) << 12) | ((uint64_t)gb_q6(cb) << 6) | 63u;
+}
+
+__device__ __forceinline__ uint64_t gb_payload(const float4 *tan, const float4 *rgb, uint32_t v,
+                                               float ts, float z, float iz1)
+{
+    return gb_payload_of(tan[v], tan[v + 1], rgb[v], rgb[v + 1], ts, z, iz1);
+}
+
+// Unit tangent of a stream point for the G-buffer keys, as the resolve
+// computes it: root -> next, tip <- previous, else the central difference
+// b - a of its neighbours (a = previous or itself, b = next or itself); zero
+// for a point that is both root and tip (no segment).
+__device__ __forceinline__ float4 cp_unit_tangent(float4 a, float4 b, bool root_and_tip)
+{
+    float dx = 0.0f, dy = 0.0f, dz = 0.0f;
+    if (!root_and_tip) {
+        dx = b.x - a.x;
+        dy = b.y - a.y;
+        dz = b.z - a.z;
+    }
+    const float n2 = (dx * dx + dy * dy) + dz * dz;
+    float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (n2 > 0.0f) {
+        const float inv = 1.0f / sqrtf(n2);
+        t = make_float4(dx * inv, dy * inv, dz * inv, 0.0f);
+    }
+    return t;
 }
 
 // Raster-side inputs of the G-buffer keys (null tan: segment-id keys).

@@ -64,8 +64,8 @@ void launch_prefill(uint64_t *vis, const float *scene_z, const hm_camera *cams,
 void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
                             const uint32_t *strand_base, const float *strand_rgb,
                             const hm_gen_params &p, const hm_strands &s, const hm_camera *cams,
-                            const hm_frame &f, float r_min, const float *scene_z, uint64_t *vis,
-                            hipStream_t st);
+                            const hm_frame &f, float r_min, int payload, const float *scene_z,
+                            uint64_t *vis, hipStream_t st);
 
 // deep-opacity-map shadows
 size_t dom_workspace(const hm_frame &light_frame, uint32_t cap);

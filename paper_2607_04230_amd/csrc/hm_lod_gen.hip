@@ -351,8 +351,13 @@ __device__ __forceinline__ void gen_sync()
 // computes it), and once a chunk of strands is complete each of its segments
 // is rasterized from LDS by one thread with global atomic minima on both
 // layers -- the paper's assembly-and-raster in one pass, with the same
-// coverage tests, depth codes and keys as the raster call.
-template <bool FUSED, bool WAVE>
+// coverage tests, depth codes and keys as the raster call.  GB (fused only):
+// the keys carry the compressed G-buffer payload, built from the points'
+// unit tangents (computed in LDS from their neighbours, as the resolve does)
+// and the strand's colour, and nothing of the stream is written (the paper's
+// register-only assembly); strands longer than the LDS chunk recompute the
+// points a segment needs.
+template <bool FUSED, bool WAVE, bool GB>
 __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
                                                         const uint32_t *strand_base,
                                                         const float *strand_rgb, GenK g,
@@ -365,12 +370,14 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
     constexpr uint32_t SM_FLOATS = GEN_LDS_FLOATS / NB, PR_CPS = FUSE_CPS / NB;
     __shared__ float sm_all[GEN_LDS_FLOATS];
     __shared__ float4 pr_all[FUSED ? FUSE_CPS : GEN_WAVES];
+    __shared__ float4 tn_all[GB ? FUSE_CPS : 1];        // world points, then unit tangents
     const uint32_t wv = WAVE ? threadIdx.x >> 6 : 0u;
     const uint32_t lane = WAVE ? threadIdx.x & 63u : threadIdx.x;
     const uint32_t b = blockIdx.x * NB + wv;
     if (b >= m.n_bundles) return;                  // the whole wave / workgroup
     float *sm = sm_all + wv * SM_FLOATS;
     float4 *pr = pr_all + (FUSED ? wv * PR_CPS : 0u);
+    float4 *tn = tn_all + (GB ? wv * PR_CPS : 0u);
     const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
     const uint32_t n = tb.x, C = tb.y, cp0 = tb.w;
     if (n == 0) return;
@@ -438,11 +445,9 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             o[6 * l + 3] = T.x; o[6 * l + 4] = T.y; o[6 * l + 5] = T.z;
         }
         gen_sync<WAVE>();
-        // control points of strands k0 .. k0+nk-1 (contiguous in the stream)
-        for (uint32_t r = lane; r < nk * C; r += NT) {
-            const uint32_t kk = r / C, j = r - kk * C;
-            const uint32_t c = cp0 + (k0 + kk) * C + j;
-            if (c >= limit) continue;
+        // styled control point j of chunk strand kk: chord-scaled Hermite
+        // between the layer points, then the curl about the bundle axis
+        auto styled_cp = [&](uint32_t kk, uint32_t j) -> float4 {
             const float *o = sm + kk * stride;
             const float w = (float)j / (float)(C - 1u);
             const float x = w * (float)(NL - 1u);
@@ -476,21 +481,61 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
             pw.y = X[1] + amp * (cth * e1.y + sth * e2.y);
             pw.z = X[2] + amp * (cth * e1.z + sth * e2.z);
             pw.w = g.width;
-            pos_w[c] = pw;
-            if (FUSED && in_lds) pr[r] = project(cam, pw);
-            float4 col;
+            return pw;
+        };
+        auto strand_col = [&](uint32_t kk) -> float4 {
             if (strand_rgb) {
                 const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k0 + kk);
-                col = make_float4(sr[0], sr[1], sr[2], 1.0f);
-            } else {
-                col = make_float4(g.br, g.bg, g.bb, 1.0f);
+                return make_float4(sr[0], sr[1], sr[2], 1.0f);
             }
-            rgb[c] = col;
+            return make_float4(g.br, g.bg, g.bb, 1.0f);
+        };
+        // control points of strands k0 .. k0+nk-1 (contiguous in the stream)
+        for (uint32_t r = lane; r < nk * C; r += NT) {
+            const uint32_t kk = r / C, j = r - kk * C;
+            const uint32_t c = cp0 + (k0 + kk) * C + j;
+            if (c >= limit) continue;
+            const float4 pw = styled_cp(kk, j);
+            if (GB) {
+                if (in_lds) tn[r] = pw;
+                continue;
+            }
+            pos_w[c] = pw;
+            if (FUSED && in_lds) pr[r] = project(cam, pw);
+            rgb[c] = strand_col(kk);
             uint8_t fl = 0;
             if (j == 0) fl |= (uint8_t)HM_ROOT;
             // the last CP of a stream truncated to the capacity ends its strand
             if (j == C - 1u || c == limit - 1u) fl |= (uint8_t)HM_TIP;
             flags[c] = fl;
+        }
+        if (GB && in_lds) {
+            // screen records and unit tangents of the chunk's points (the
+            // tangents replace the world points once every lane has read its
+            // neighbours)
+            // a chunk holds at most PR_CPS = 4 NT points: four per lane
+            static_assert(PR_CPS == 4u * NT, "four chunk points per lane");
+            gen_sync<WAVE>();
+            float4 tr[4];
+#pragma unroll
+            for (uint32_t it = 0; it < 4u; ++it) {
+                const uint32_t r = lane + it * NT;
+                const uint32_t kk = r / C, j = r - kk * C;
+                const uint32_t c = cp0 + (k0 + kk) * C + j;
+                tr[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (r >= nk * C || c >= limit) continue;
+                const float4 P = tn[r];
+                pr[r] = project(cam, P);
+                const bool root = j == 0, tip = j == C - 1u || c == limit - 1u;
+                tr[it] = cp_unit_tangent(root ? P : tn[r - 1], tip ? P : tn[r + 1], root && tip);
+            }
+            gen_sync<WAVE>();
+#pragma unroll
+            for (uint32_t it = 0; it < 4u; ++it) {
+                const uint32_t r = lane + it * NT;
+                const uint32_t kk = r / C, j = r - kk * C;
+                if (r < nk * C && cp0 + (k0 + kk) * C + j < limit) tn[r] = tr[it];
+            }
         }
         gen_sync<WAVE>();
         if (FUSED) {
@@ -503,10 +548,31 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
                 const uint32_t kk = r / C, j = r - kk * C;
                 const uint32_t c = cp0 + (k0 + kk) * C + j;
                 if (j + 1u >= C || c + 1u >= limit) continue;
-                const float4 pa = in_lds ? pr[r] : project(cam, pos_w[c]);
-                const float4 pb = in_lds ? pr[r + 1] : project(cam, pos_w[c + 1]);
+                float4 pa, pb, T0, T1;
+                if (in_lds) {
+                    pa = pr[r];
+                    pb = pr[r + 1];
+                    if (GB) {
+                        T0 = tn[r];
+                        T1 = tn[r + 1];
+                    }
+                } else if (GB) {
+                    // no stream to read back: the segment's points again
+                    const float4 P0 = styled_cp(kk, j), P1 = styled_cp(kk, j + 1u);
+                    const bool root = j == 0, tip1 = j + 2u >= C || c + 2u >= limit;
+                    const float4 Pm = root ? P0 : styled_cp(kk, j - 1u);
+                    const float4 P2 = tip1 ? P1 : styled_cp(kk, j + 2u);
+                    pa = project(cam, P0);
+                    pb = project(cam, P1);
+                    T0 = cp_unit_tangent(Pm, P1, false);
+                    T1 = cp_unit_tangent(P0, P2, false);
+                } else {
+                    pa = project(cam, pos_w[c]);
+                    pb = project(cam, pos_w[c + 1]);
+                }
                 if (pa.w == 0.0f || pb.w == 0.0f) continue;
                 const Seg sg = make_seg(pa, pb, fk.r_min);
+                const float4 col = GB ? strand_col(kk) : make_float4(0.f, 0.f, 0.f, 0.f);
                 int i0, i1, j0, j1;
                 if (!seg_box(sg, fk.W, fk.H, i0, i1, j0, j1)) continue;
                 for (int y = j0; y <= j1; ++y) {
@@ -517,8 +583,12 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
                     for (int x = a0; x <= a1; ++x) {
                         uint32_t q;
                         bool cc, ca;
-                        if (!cover(sg, x, y, fk.r_min, zn, inv_range, cc, ca, q)) continue;
-                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | c;
+                        float ts, z;
+                        if (!cover_tz(sg, x, y, fk.r_min, zn, inv_range, cc, ca, q, ts, z))
+                            continue;
+                        const uint64_t low =
+                            GB ? gb_payload_of(T0, T1, col, col, ts, z, pb.w) : (uint64_t)c;
+                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
                         const size_t px = (size_t)y * fk.W + x;
                         if (cc) atomicMin((unsigned long long *)(vc + px), key);
                         if (ca) atomicMin((unsigned long long *)(va + px), key);
@@ -540,7 +610,7 @@ static bool gen_wave(const hm_hair_mesh &m, uint32_t cap)
     return m.n_bundles >= 4096u || (uint64_t)cap <= 512ull * m.n_bundles;
 }
 
-template <bool FUSED>
+template <bool FUSED, bool GB>
 static void launch_gen_kernel(const hm_hair_mesh &m, const uint32_t *table,
                               const uint32_t *strand_base, const float *strand_rgb, GenK g,
                               const hm_strands &s, FuseK fk, hipStream_t st)
@@ -548,7 +618,8 @@ static void launch_gen_kernel(const hm_hair_mesh &m, const uint32_t *table,
     const bool wave = gen_wave(m, s.cap);
     const uint32_t grid = wave ? (m.n_bundles + GEN_WAVES - 1) / GEN_WAVES : m.n_bundles;
 #define HM_GEN_LAUNCH(W)                                                                    \
-    hipLaunchKernelGGL((k_generate_bundle<FUSED, W>), dim3(grid), dim3(256), 0, st, m, table,  \
+    hipLaunchKernelGGL((k_generate_bundle<FUSED, W, GB>), dim3(grid), dim3(256), 0, st, m,    \
+                       table,                                                                \
                        strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),        \
                        reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,    \
                        s.cap, fk)
@@ -565,21 +636,24 @@ void launch_generate(const hm_hair_mesh &m, const uint32_t *table, const uint32_
 {
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    launch_gen_kernel<false>(m, table, strand_base, strand_rgb, g, s,
-                             FuseK{nullptr, nullptr, 0u, 0u, 0.0f}, st);
+    launch_gen_kernel<false, false>(m, table, strand_base, strand_rgb, g, s,
+                                    FuseK{nullptr, nullptr, 0u, 0u, 0.0f}, st);
 }
 
 void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
                             const uint32_t *strand_base, const float *strand_rgb,
                             const hm_gen_params &p, const hm_strands &s, const hm_camera *cams,
-                            const hm_frame &f, float r_min, const float *scene_z, uint64_t *vis,
-                            hipStream_t st)
+                            const hm_frame &f, float r_min, int payload, const float *scene_z,
+                            uint64_t *vis, hipStream_t st)
 {
     launch_prefill(vis, scene_z, cams, f, st);
     GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
            p.base_rgb[2]};
-    launch_gen_kernel<true>(m, table, strand_base, strand_rgb, g, s,
-                            FuseK{cams, vis, f.width, f.height, r_min}, st);
+    const FuseK fk{cams, vis, f.width, f.height, r_min};
+    if (payload == HM_PAYLOAD_GBUFFER)
+        launch_gen_kernel<true, true>(m, table, strand_base, strand_rgb, g, s, fk, st);
+    else
+        launch_gen_kernel<true, false>(m, table, strand_base, strand_rgb, g, s, fk, st);
 }
 
 }  // namespace hm

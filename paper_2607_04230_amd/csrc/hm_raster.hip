@@ -249,20 +249,9 @@ __global__ __launch_bounds__(256) void k_cp_tangent(const float4 *pos, const uin
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n;
          v += gridDim.x * blockDim.x) {
         const uint8_t f = flags[v];
-        float dx = 0.0f, dy = 0.0f, dz = 0.0f;
-        if (!((f & HM_ROOT) && (f & HM_TIP))) {
-            const float4 a = (f & HM_ROOT) ? pos[v] : pos[v - 1];
-            const float4 b = (f & HM_TIP) ? pos[v] : pos[v + 1];
-            dx = b.x - a.x;
-            dy = b.y - a.y;
-            dz = b.z - a.z;
-        }
-        const float n2 = (dx * dx + dy * dy) + dz * dz;
-        float4 t = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (n2 > 0.0f) {
-            const float inv = 1.0f / sqrtf(n2);
-            t = make_float4(dx * inv, dy * inv, dz * inv, 0.0f);
-        }
+        const float4 a = (f & HM_ROOT) ? pos[v] : pos[v - 1];
+        const float4 b = (f & HM_TIP) ? pos[v] : pos[v + 1];
+        const float4 t = cp_unit_tangent(a, b, (f & HM_ROOT) && (f & HM_TIP));
         tan[v] = t;
     }
 }

@@ -126,13 +126,16 @@ def bench_reciprocal(lo: int, hi: int, counts):
 
 
 def generate_raster(mesh, table, strand_base, strand_rgb, gp, st, cams, fr, r_min, scene_z,
-                    vis):
-    """Strand generation fused with the direct raster (stream and visibility)."""
+                    vis, payload: int = 0):
+    """Strand generation fused with the direct raster: the stream and
+    segment-id keys (payload 0), or G-buffer keys and no stream (payload 1)."""
     L = load()
-    L.hm_generate_raster.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f32, _vp, _vp, _vp]
+    L.hm_generate_raster.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _f32, _i32, _vp, _vp,
+                                     _vp]
     _check(L.hm_generate_raster(ctypes.byref(mesh), _ptr(table), _ptr(strand_base),
                                 _ptr(strand_rgb), ctypes.byref(gp), ctypes.byref(st), _ptr(cams),
-                                ctypes.byref(fr), r_min, _ptr(scene_z), _ptr(vis), _stream()),
+                                ctypes.byref(fr), r_min, payload, _ptr(scene_z), _ptr(vis),
+                                _stream()),
            "hm_generate_raster")
 
 

@@ -101,11 +101,20 @@ class DeviceScene:
             self.sp.mode = hm.RESOLVE_CENTER
             self.mode = hm.RESOLVE_CENTER
 
+    def _stream_desc(self, gbuffer: bool) -> hm.Strands:
+        """The stream descriptor of a call; with G-buffer keys the calls read
+        and write no control point, so its arrays are NULL."""
+        if not gbuffer:
+            return self.st
+        return hm.Strands(None, None, None, self.scene_off.data_ptr(), self.S, self.cap)
+
     def generate_raster(self):
-        """Generation and raster in one pass (fused, direct atomics)."""
+        """Generation and raster in one pass (fused, direct atomics); with
+        G-buffer keys (use_gbuffer) no stream is written."""
+        gb = self.rparams.payload == hm.PAYLOAD_GBUFFER
         hm.generate_raster(self.mesh, self.table, self.strand_base, self.strand_rgb, self.gp,
-                           self.st, self.cams, self.fr, self.rparams.r_min, self.scene_z,
-                           self.vis)
+                           self._stream_desc(gb), self.cams, self.fr, self.rparams.r_min,
+                           self.scene_z, self.vis, payload=self.rparams.payload)
 
     def render_fused(self):
         self.lod()
@@ -114,8 +123,9 @@ class DeviceScene:
         return self.out
 
     def resolve(self, out=None):
-        hm.resolve_shade(self.st, self.vis, self.cams, self.fr, self.sp,
-                         self.out if out is None else out, self.ws_resolve)
+        hm.resolve_shade(self._stream_desc(self.sp.payload == hm.PAYLOAD_GBUFFER), self.vis,
+                         self.cams, self.fr, self.sp, self.out if out is None else out,
+                         self.ws_resolve)
 
     def render(self):
         self.lod()

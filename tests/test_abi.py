@@ -112,19 +112,35 @@ def test_validation_errors_are_reported():
     assert L.hm_lod_select(ctypes.byref(m), dummy, ctypes.byref(fr), ctypes.byref(lp), dummy,
                            dummy, dummy, dummy, 1 << 20, None) == 2
     assert b"n_layers" in L.hm_last_error()
-    # fused generation + raster: scene counts must agree, r_min >= 0
+    # fused generation + raster: scene counts must agree, r_min >= 0, a known
+    # payload; segment-id keys need the stream's arrays, G-buffer keys do not
+    P = ctypes.c_void_p
+    L.hm_generate_raster.argtypes = [P, P, P, P, P, P, P, P, ctypes.c_float, ctypes.c_int32, P,
+                                     P, P]
     gp = hm.GenParams()
+    SEG, GBUF = hm.PAYLOAD_SEGMENT, hm.PAYLOAD_GBUFFER
     assert L.hm_generate_raster(ctypes.byref(m), dummy, None, None, ctypes.byref(gp),
-                                ctypes.byref(st), dummy, ctypes.byref(fr2), ctypes.c_float(0.0),
+                                ctypes.byref(st), dummy, ctypes.byref(fr2), 0.0, SEG,
                                 None, dummy, None) == 2          # the mesh's n_layers is 1
     m2 = hm.HairMesh(dummy, dummy, dummy, dummy, dummy, dummy, 4, 4, 10)
     assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
-                                ctypes.byref(st), dummy, ctypes.byref(fr2), ctypes.c_float(0.0),
+                                ctypes.byref(st), dummy, ctypes.byref(fr2), 0.0, SEG,
                                 None, dummy, None) == 1
     assert b"n_scenes" in L.hm_last_error()
     assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
-                                ctypes.byref(st), dummy, ctypes.byref(fr), ctypes.c_float(-1.0),
+                                ctypes.byref(st), dummy, ctypes.byref(fr), -1.0, SEG,
                                 None, dummy, None) == 2
+    assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
+                                ctypes.byref(st), dummy, ctypes.byref(fr), 0.0, 7,
+                                None, dummy, None) == 1
+    assert b"payload" in L.hm_last_error()
+    no_stream = hm.Strands(None, None, None, dummy, 1, 1000)
+    assert L.hm_generate_raster(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
+                                ctypes.byref(no_stream), dummy, ctypes.byref(fr), 0.0, SEG,
+                                None, dummy, None) == 1
+    assert b"NULL array" in L.hm_last_error()
+    # (with G-buffer keys the same arguments pass validation; the call would
+    # launch, so it is exercised by the GPU tests only)
     # atomic-rate microkernels: argument checks before any launch
     L.hm_bench_atomics.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]

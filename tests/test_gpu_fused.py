@@ -147,3 +147,84 @@ def test_fused_wave_shape_with_strands_longer_than_its_lds_slice(O, torch):
     assert np.array_equal(gr.view(np.uint32), rgb.view(np.uint32))
     assert np.array_equal(ds.host_vis(), vis)
     assert (vis != np.uint64(0xFFFFFFFFFFFFFFFF)).sum() > 80      # 105 keys in both layers
+
+
+# ----------------------------------------------------------------- stream-free
+# Generation fused with the raster and the compressed G-buffer keys: no
+# stream is written (the stream buffers are filled with a sentinel first and
+# must come back untouched), the keys equal the oracle's G-buffer raster of
+# the stream it generates, and the centre resolve of the keys alone matches the
+# oracle's within 1e-4.
+def _fused_gbuf(sc, torch, cap=None):
+    from paper_2607_04230_amd.render import DeviceScene
+    print(f"[fused gbuf] {sc.name} {sc.width}x{sc.height} scenes={sc.n_scenes} cap={cap}",
+          flush=True)
+    ds = DeviceScene(sc, cap=cap)
+    ds.use_gbuffer()
+    for t in (ds.pos_w, ds.rgb):
+        t.fill_(float("nan"))
+    ds.flags.fill_(0xA5)
+    ds.render_fused()
+    torch.cuda.synchronize()
+    return ds
+
+
+def _gbuf_ref(O, sc, cap=None):
+    table, soff, (ns, ncp) = O.lod_select(sc)
+    pos, rgb, fl = O.generate(sc, table, ncp, cap=cap)
+    if cap is not None:
+        soff = np.minimum(soff, cap).astype(np.uint32)
+    vis = O.raster_gbuf(pos, rgb, fl, soff, sc.cams, sc.width, sc.height, sc.r_min, sc.scene_z)
+    out = O.resolve_gbuf(vis, sc.cams, sc.width, sc.height, ResolveParams(), sc.bg)
+    return vis, out
+
+
+def _check_stream_free(ds, vis, out):
+    assert bool(ds.pos_w.isnan().all()) and bool(ds.rgb.isnan().all())
+    assert bool((ds.flags == 0xA5).all())
+    assert np.array_equal(ds.host_vis(), vis)
+    assert (vis[:, 0] != np.uint64(0xFFFFFFFFFFFFFFFF)).any()
+    assert np.abs(ds.out.cpu().numpy().astype(np.float64) - out).max() <= TOL
+
+
+@pytest.mark.parametrize("cap", [None, 40000], ids=["wave", "workgroup"])
+def test_tiny_stream_free_gbuffer_matches_oracle(O, torch, cap):
+    sc = scenes.config_tiny()
+    vis, out = _gbuf_ref(O, sc)
+    _check_stream_free(_fused_gbuf(sc, torch, cap=cap), vis, out)
+
+
+def test_head_1080p_stream_free_gbuffer_matches_oracle(O, torch):
+    """The benchmarked stream-free frame: the full head at 1920x1080."""
+    sc = scenes.config_head()
+    vis, out = _gbuf_ref(O, sc)
+    _check_stream_free(_fused_gbuf(sc, torch), vis, out)
+
+
+def test_stream_free_gbuffer_equals_separate_gbuffer_raster(torch):
+    """Same keys as generate + tiled G-buffer raster, on a batched frame."""
+    from paper_2607_04230_amd.render import DeviceScene
+    sc = scenes.config_batched(n_scenes=6, res=256, n_min=1e3, n_max=2e4)
+    ds = _fused_gbuf(sc, torch)
+    sep = DeviceScene(sc)
+    sep.use_gbuffer()
+    sep.render()
+    torch.cuda.synchronize()
+    assert np.array_equal(ds.host_vis(), sep.host_vis())
+    assert torch.equal(ds.out, sep.out)
+
+
+@pytest.mark.parametrize("cap", [1001, 5000])
+def test_stream_free_gbuffer_truncated(O, torch, cap):
+    sc = scenes.config_tiny()
+    vis, out = _gbuf_ref(O, sc, cap=cap)
+    _check_stream_free(_fused_gbuf(sc, torch, cap=cap), vis, out)
+
+
+@pytest.mark.parametrize("n_cp,cap", [(1500, None), (300, 1500)], ids=["workgroup", "wave"])
+def test_stream_free_gbuffer_strands_longer_than_the_lds_chunk(O, torch, n_cp, cap):
+    """Strands whose points do not fit the LDS chunk: each segment generates
+    its four points again (no stream to read back); same keys as the oracle."""
+    sc = scenes.micro_scene(5, n_cp=n_cp, res=48)
+    vis, out = _gbuf_ref(O, sc, cap=cap)
+    _check_stream_free(_fused_gbuf(sc, torch, cap=cap), vis, out)
