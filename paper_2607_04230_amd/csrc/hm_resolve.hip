@@ -216,7 +216,6 @@ constexpr int HALO_MAX = FT + 2 * RMAX;
 // Weighted colour sum of one output pixel, exponent-shifted.
 struct FilterAcc {
     float Sx, Sy, Sz, Wsum, emax;
-    bool acc;               // some neighbour was accepted (the reconstruction exists)
 };
 
 // Per-pixel constants of the weight taps.  Exponents are in log2 units: a
@@ -225,30 +224,39 @@ struct FilterAcc {
 // pw, cw the offset's components along / across the weight tangent (the
 // isotropic fallback has A = B).  The spatial part is the quadratic form
 //   qa fx^2 + qb fx fy + qc fy^2,
-// evaluated per row as fx (qa fx + qb fy) + qc fy^2.  When the centre sample
-// is a hit whose colour the filter compares against, the centre tap has
-// e = 0 >= every other e, so emax = 0 from the start; otherwise emax follows
-// the running maximum (a far-off strand would underflow every weight).
+// evaluated per row as fx (qa fx + qb fy) + qc fy^2.  The colour part is
+// expanded as Csc |C_P|^2 + Csc |C_Q|^2 - 2 Csc C_P . C_Q, with |C_Q|^2 staged
+// beside each record and Csc |C_P|^2 folded into the row constant: four fused
+// multiply-adds per tap (the expansion's rounding, a few 1e-7 of the exponent,
+// is far inside the tolerance).  When the centre sample is a hit whose colour
+// the filter compares against, the centre tap has e = 0 >= every other e (up
+// to that rounding), so emax = 0 from the start; otherwise emax follows the
+// running maximum (a far-off strand would underflow every weight), and the
+// tap at the maximum adds exactly 1 to Wsum, so Wsum > 0 iff some neighbour
+// was accepted.
 struct FilterPix {
     float qa, qb, qc;
     float Csc;
-    float Cx, Cy, Cz;       // centre colour
+    float gx, gy, gz;       // -2 Csc C_P
     uint32_t q_lo, q_span;  // accepted depth codes: (q - q_lo) mod 2^32 <= q_span
     bool track_max;
 };
 
 __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, float fx, float r1,
-                                           float r0, float4 Q)
+                                           float r0, float4 Q, uint32_t word)
 {
     // centre-sample hit within the depth window [qP - rej, qP + rej]: a
     // centre hit's word is its depth code, every other word lies above 2^29,
     // beyond any window
-    const bool take = (__float_as_uint(Q.w) - f.q_lo) <= f.q_span;
-    // continuous weight (tolerance-compared): fused multiply-adds are fine here
-    const float esp = fmaf(fx, fmaf(f.qa, fx, r1), r0);
-    const float d0 = f.Cx - Q.x, d1 = f.Cy - Q.y, d2 = f.Cz - Q.z;
-    const float dc = fmaf(d0, d0, fmaf(d1, d1, d2 * d2));
-    const float e = -fmaf(dc, f.Csc, esp);
+    const bool take = (word - f.q_lo) <= f.q_span;
+    // continuous weight (tolerance-compared): fused multiply-adds are fine
+    // here; Q.w = |C_Q|^2, r0 holds Csc |C_P|^2
+    float g = fmaf(fx, fmaf(f.qa, fx, r1), r0);
+    g = fmaf(Q.w, f.Csc, g);
+    g = fmaf(f.gx, Q.x, g);
+    g = fmaf(f.gy, Q.y, g);
+    g = fmaf(f.gz, Q.z, g);
+    const float e = -g;
     if (f.track_max && take && e > a.emax) {
         const float sc = __builtin_amdgcn_exp2f(a.emax - e);
         a.Sx *= sc; a.Sy *= sc; a.Sz *= sc; a.Wsum *= sc;
@@ -259,7 +267,6 @@ __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, flo
     a.Sy = fmaf(w, Q.y, a.Sy);
     a.Sz = fmaf(w, Q.z, a.Sz);
     a.Wsum += w;
-    a.acc |= take;
 }
 
 // Strip counts for alpha (Sec. 3.3): over the window taps whose distance to
@@ -268,34 +275,41 @@ __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, flo
 // decided in binary32 exactly as perp2 = |o - (o.T) T|^2 <= h^2 (a zero
 // tangent, the isotropic case, gives |o|^2).  Only taps near the line are
 // tested: along the line's major axis every offset a in [-r, r] has its
-// minor-axis candidates in an interval of width 2h / |major component| around
-// the line, widened by 0.05 against rounding (an error of perp2 of a few ulp
-// of r^2 moves the boundary by far less).
-__device__ __forceinline__ void strip_counts(const float4 *tile, int E, int cx, int cy, int r,
+// minor-axis candidates b in an interval of width 2h / |major component|
+// around the line, widened by 0.05 against rounding (an error of perp2 of a
+// few ulp of r^2 moves the boundary by far less).  With (P, Q) the tangent's
+// components along the major and minor axis, o.T = a P + b Q and the two
+// components of o - (o.T) T are a - (o.T) P and b - (o.T) Q: the same
+// products and sums as the (x, y) form, only added in the other order for a
+// steep tangent, which leaves every binary32 result unchanged.
+__device__ __forceinline__ void strip_counts(const uint32_t *words, int E, int cx, int cy, int r,
                                              float Tx, float Ty, float h, float h2, int &Hc,
                                              int &Ha)
 {
     Hc = 0;
     Ha = 0;
     const bool steep = fabsf(Ty) >= fabsf(Tx);      // iso (0, 0) counts as steep
-    const float M = steep ? Ty : Tx, m = steep ? Tx : Ty;
-    const float aM = fabsf(M);
-    const float slope = aM > 0.0f ? m / M : 0.0f;
+    const float P = steep ? Ty : Tx, Q = steep ? Tx : Ty;
+    const float aM = fabsf(P);
+    const float slope = aM > 0.0f ? Q / P : 0.0f;
     const float half = (aM > 0.0f ? h / aM : h) + 0.05f;
+    // word index steps along a and b
+    const int sa = steep ? E : 1, sb = steep ? 1 : E;
+    const int centre = cy * E + cx;
     for (int a = -r; a <= r; ++a) {
-        const float c = (float)a * slope;
+        const float fa = (float)a;
+        const float c = fa * slope;
         const int b0 = max(-r, (int)ceilf(c - half)), b1 = min(r, (int)floorf(c + half));
-        for (int b = b0; b <= b1; ++b) {
-            const int ox = steep ? b : a, oy = steep ? a : b;
-            const float fx = (float)ox, fy = (float)oy;
-            const float par = fx * Tx + fy * Ty;
-            const float ex = fx - par * Tx, ey = fy - par * Ty;
-            const float perp2 = ex * ex + ey * ey;
-            if (perp2 <= h2) {
-                const uint32_t bits = __float_as_uint(tile[(cy + oy) * E + (cx + ox)].w);
-                Ha += bits != REC_EMPTY ? 1 : 0;
-                Hc += bits <= HM_QMAX ? 1 : 0;          // a centre hit's depth code
-            }
+        const float pa = fa * P;
+        int idx = centre + a * sa + b0 * sb;
+        float fb = (float)b0;
+        for (int b = b0; b <= b1; ++b, fb += 1.0f, idx += sb) {
+            const float par = pa + fb * Q;
+            const float u = fa - par * P, v = fb - par * Q;
+            const bool in = u * u + v * v <= h2;
+            const uint32_t bits = words[idx];
+            Ha += in && bits != REC_EMPTY ? 1 : 0;
+            Hc += in && bits <= HM_QMAX ? 1 : 0;            // a centre hit's depth code
         }
     }
 }
@@ -308,7 +322,10 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
                                                 ShadeK k, const float4 *rec, float4 *out)
 {
     constexpr int EMAX = R > 0 ? FT + 2 * R : HALO_MAX;
+    // colours with |C|^2, and the record words apart (the strip reads only
+    // words, at consecutive addresses)
     __shared__ float4 tile[EMAX * EMAX];
+    __shared__ uint32_t words[EMAX * EMAX];
     const int r = R > 0 ? R : k.r;
     const int E = R > 0 ? EMAX : FT + 2 * r;
     const uint32_t tiles_x = (W + FT - 1) / FT;
@@ -324,7 +341,8 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         const int gi = ox0 + lx, gj = oy0 + ly;
         float4 v = make_float4(0.f, 0.f, 0.f, __uint_as_float(REC_EMPTY));
         if (gi >= 0 && gj >= 0 && gi < (int)W && gj < (int)H) v = recs[(size_t)gj * W + gi];
-        tile[ly * E + lx] = v;
+        tile[ly * E + lx] = make_float4(v.x, v.y, v.z, fmaf(v.x, v.x, fmaf(v.y, v.y, v.z * v.z)));
+        words[ly * E + lx] = __float_as_uint(v.w);
     }
     __syncthreads();
     const int li = (int)(threadIdx.x % FT), lj = (int)(threadIdx.x / FT);
@@ -371,7 +389,10 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     f.qb = (float)(2.0 * Tw0 * Tw1 * (A - B));
     f.qc = (float)(A * Tw1 * Tw1 + B * Tw0 * Tw0);
     f.Csc = colour_sim ? (float)(k.inv_sc2 * LOG2E) : 0.0f;
-    f.Cx = CP.x; f.Cy = CP.y; f.Cz = CP.z;
+    f.gx = -2.0f * f.Csc * CP.x;
+    f.gy = -2.0f * f.Csc * CP.y;
+    f.gz = -2.0f * f.Csc * CP.z;
+    const float K0 = f.Csc * CP.w;          // Csc |C_P|^2
     const uint32_t qP = (uint32_t)(src >> HM_ID_BITS);
     f.q_lo = qP - k.dq_rej;
     f.q_span = 2u * k.dq_rej;
@@ -379,29 +400,33 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     FilterAcc a;
     a.Sx = a.Sy = a.Sz = a.Wsum = 0.0f;
     a.emax = colour_sim ? 0.0f : -INFINITY;
-    a.acc = false;
     const float4 *ctr = tile + (lj + r) * E + (li + r);
     if (R > 0) {
         // the window's top-left record: every tap at a fixed non-negative
         // offset from it (an immediate of the LDS read)
         const float4 *win = tile + lj * EMAX + li;
+        const uint32_t *wwin = words + lj * EMAX + li;
 #pragma unroll 1
         for (int oy = -R; oy <= R; ++oy) {
             const float4 *row = win + (oy + R) * EMAX;
+            const uint32_t *wrow = wwin + (oy + R) * EMAX;
             const float fy = (float)oy;
-            const float r1 = f.qb * fy, r0 = f.qc * (fy * fy);
+            const float r1 = f.qb * fy, r0 = fmaf(f.qc, fy * fy, K0);
 #pragma unroll
-            for (int ox = -R; ox <= R; ++ox) filter_tap(f, a, (float)ox, r1, r0, row[ox + R]);
+            for (int ox = -R; ox <= R; ++ox)
+                filter_tap(f, a, (float)ox, r1, r0, row[ox + R], wrow[ox + R]);
         }
     } else {
+        const uint32_t *wctr = words + (lj + r) * E + (li + r);
         for (int oy = -r; oy <= r; ++oy) {
             const float fy = (float)oy;
-            const float r1 = f.qb * fy, r0 = f.qc * (fy * fy);
-            for (int ox = -r; ox <= r; ++ox) filter_tap(f, a, (float)ox, r1, r0, ctr[oy * E + ox]);
+            const float r1 = f.qb * fy, r0 = fmaf(f.qc, fy * fy, K0);
+            for (int ox = -r; ox <= r; ++ox)
+                filter_tap(f, a, (float)ox, r1, r0, ctr[oy * E + ox], wctr[oy * E + ox]);
         }
     }
     int Hc, Ha;
-    strip_counts(tile, E, li + r, lj + r, r, Tx, Ty, k.strip_half, k.strip2, Hc, Ha);
+    strip_counts(words, E, li + r, lj + r, r, Tx, Ty, k.strip_half, k.strip2, Hc, Ha);
     const float aP = Ha > 0 ? (float)Hc / (float)Ha : 1.0f;
     float rr = 0.f, gg = 0.f, bb = 0.f, alpha = 0.f;
     if (hc && !mism) {
@@ -409,14 +434,14 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         alpha = aP;
     } else if (mism) {
         float cr = CP.x, cg = CP.y, cb = CP.z;
-        if (a.acc) {
+        if (a.Wsum > 0.0f) {
             cr = a.Sx / a.Wsum; cg = a.Sy / a.Wsum; cb = a.Sz / a.Wsum;
         }
         rr = aP * cr + (1.0f - aP) * CP.x;
         gg = aP * cg + (1.0f - aP) * CP.y;
         bb = aP * cb + (1.0f - aP) * CP.z;
         alpha = 1.0f;
-    } else if (a.acc) {
+    } else if (a.Wsum > 0.0f) {
         rr = a.Sx / a.Wsum; gg = a.Sy / a.Wsum; bb = a.Sz / a.Wsum;
         alpha = aP;
     }
