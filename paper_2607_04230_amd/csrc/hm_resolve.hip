@@ -336,6 +336,33 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
     const int ox0 = tx * FT - r, oy0 = ty * FT - r;
     const size_t hw = (size_t)W * H;
     const float4 *recs = rec + (size_t)s * hw;
+    const int li = (int)(threadIdx.x % FT), lj = (int)(threadIdx.x / FT);
+    const int i = tx * FT + li, j = ty * FT + lj;
+    const bool inb = i < (int)W && j < (int)H;
+    const size_t loc = (size_t)j * W + i;
+    uint64_t kc = HM_EMPTY, ka = HM_EMPTY;
+    if (inb) {
+        kc = vis[(size_t)s * 2 * hw + loc];
+        ka = vis[(size_t)s * 2 * hw + hw + loc];
+    }
+    const bool hc = is_hit(kc), ha = is_hit(ka);
+    float4 *o = out + (size_t)s * hw + loc;
+    // a tile without hair pixels needs no records
+    if (!__syncthreads_or(hc || ha)) {
+        if (inb) *o = make_float4(k.bgr, k.bgg, k.bgb, 0.0f);
+        return;
+    }
+    // the pixel's segment (the conservative one on a depth mismatch), its
+    // control points loaded while the tile is staged
+    const uint32_t qc = (uint32_t)(kc >> HM_ID_BITS), qa = (uint32_t)(ka >> HM_ID_BITS);
+    const bool mism = hc && ha && qc > qa && (qc - qa) >= k.dq_mis;
+    const uint64_t src = (hc && !mism) ? kc : ka;
+    const uint32_t vs = (uint32_t)(src & HM_ID_MASK);
+    float4 P0 = make_float4(0.f, 0.f, 0.f, 0.f), P1 = P0;
+    if (hc || ha) {
+        P0 = pos[vs];
+        P1 = pos[vs + 1];
+    }
     for (int x = threadIdx.x; x < E * E; x += blockDim.x) {
         const int ly = x / E, lx = x - ly * E;
         const int gi = ox0 + lx, gj = oy0 + ly;
@@ -345,23 +372,13 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         words[ly * E + lx] = __float_as_uint(v.w);
     }
     __syncthreads();
-    const int li = (int)(threadIdx.x % FT), lj = (int)(threadIdx.x / FT);
-    const int i = tx * FT + li, j = ty * FT + lj;
-    if (i >= (int)W || j >= (int)H) return;
-    const size_t loc = (size_t)j * W + i;
-    const uint64_t kc = vis[(size_t)s * 2 * hw + loc], ka = vis[(size_t)s * 2 * hw + hw + loc];
-    const bool hc = is_hit(kc), ha = is_hit(ka);
-    float4 *o = out + (size_t)s * hw + loc;
+    if (!inb) return;
     if (!hc && !ha) {
         *o = make_float4(k.bgr, k.bgg, k.bgb, 0.0f);
         return;
     }
-    const uint32_t qc = (uint32_t)(kc >> HM_ID_BITS), qa = (uint32_t)(ka >> HM_ID_BITS);
-    const bool mism = hc && ha && qc > qa && (qc - qa) >= k.dq_mis;
-    const uint64_t src = (hc && !mism) ? kc : ka;
-    const uint32_t vs = (uint32_t)(src & HM_ID_MASK);
     const Cam c = load_cam(cams + s);
-    const float4 pa = project(c, pos[vs]), pb = project(c, pos[vs + 1]);
+    const float4 pa = project(c, P0), pb = project(c, P1);
     const float tdx = pb.x - pa.x, tdy = pb.y - pa.y;
     const float tlen = sqrtf(tdx * tdx + tdy * tdy);
     const bool iso = !(tlen >= k.iso_len);
@@ -376,7 +393,7 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         const float il = 1.0f / tlen;
         Tx = tdx * il;
         Ty = tdy * il;
-        const DProj da = project_d(c, pos[vs]), db = project_d(c, pos[vs + 1]);
+        const DProj da = project_d(c, P0), db = project_d(c, P1);
         const double ddx = db.x - da.x, ddy = db.y - da.y;
         const double dl = sqrt(ddx * ddx + ddy * ddy);
         Tw0 = ddx / dl;
@@ -406,15 +423,21 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         // offset from it (an immediate of the LDS read)
         const float4 *win = tile + lj * EMAX + li;
         const uint32_t *wwin = words + lj * EMAX + li;
+        // taps from the centre outwards (offsets 0, -1, 1, -2, 2, ...), so
+        // that a running maximum meets its final value early and rescales
+        // rarely
 #pragma unroll 1
-        for (int oy = -R; oy <= R; ++oy) {
+        for (int ky = 0; ky <= 2 * R; ++ky) {
+            const int oy = (ky & 1) ? -((ky + 1) >> 1) : (ky >> 1);
             const float4 *row = win + (oy + R) * EMAX;
             const uint32_t *wrow = wwin + (oy + R) * EMAX;
             const float fy = (float)oy;
             const float r1 = f.qb * fy, r0 = fmaf(f.qc, fy * fy, K0);
 #pragma unroll
-            for (int ox = -R; ox <= R; ++ox)
+            for (int kx = 0; kx <= 2 * R; ++kx) {
+                const int ox = (kx & 1) ? -((kx + 1) >> 1) : (kx >> 1);
                 filter_tap(f, a, (float)ox, r1, r0, row[ox + R], wrow[ox + R]);
+            }
         }
     } else {
         const uint32_t *wctr = words + (lj + r) * E + (li + r);
