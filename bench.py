@@ -176,6 +176,14 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
             # per CU per cycle (four 16-lane SIMDs, four cycles per wave64 op)
             r["valu_issue_frac"] = rec["valu_insts_per_launch"] / (PEAK_VALU_TOPS * 1e12 / 64
                                                                     * s)
+        if rec and rec.get("l2_atomics_per_launch") is not None:
+            # global atomics (split-tile merges, work-item counter) as counted
+            # at the L2, against the measured global 64-bit atomic peak
+            ga = rec["l2_atomics_per_launch"]
+            r.update({"global_atomics": ga, "global_atomics_to_memory":
+                      rec.get("ea_atomics_per_launch"), "global_atomic_per_s": ga / s})
+            if ATOMIC_PEAKS:
+                r["global_atomic_frac"] = ga / s / ATOMIC_PEAKS["global"]
         return r
     elif kernel == "k_prefill":
         b = vis_bytes
@@ -461,12 +469,15 @@ def _read_counter_csv(d: str):
     return out
 
 
-def summarize_counters(fetch_dir: str, write_dir: str, valu_dir: str = None):
+def summarize_counters(fetch_dir: str, write_dir: str, valu_dir: str = None,
+                       atomic_dir: str = None):
     """Per-launch HBM bytes (FETCH_SIZE and WRITE_SIZE in KiB, each scaled by
-    what it reads for the known-size read-only / write-only kernels) and VALU
-    instructions of the library's kernels from three rocprofv3 --pmc runs of
-    `bench.py --profile`; writes profiles/traffic.json keyed by kernel with the
-    hash of its source file, and prints a markdown table."""
+    what it reads for the known-size read-only / write-only kernels), VALU
+    instructions and L2 atomic requests (TCC_ATOMIC: all global atomics;
+    TCC_EA0_ATOMIC: those passed on to memory) of the library's kernels from
+    up to four rocprofv3 --pmc runs of `bench.py --profile`; writes
+    profiles/traffic.json keyed by kernel with the hash of its source file, and
+    prints a markdown table."""
     def per_kernel(d, counter):
         acc = {}
         for (k, _), c in _read_counter_csv(d).items():
@@ -476,6 +487,8 @@ def summarize_counters(fetch_dir: str, write_dir: str, valu_dir: str = None):
     fetch = per_kernel(fetch_dir, "FETCH_SIZE")
     write = per_kernel(write_dir, "WRITE_SIZE")
     valu = per_kernel(valu_dir, "SQ_INSTS_VALU") if valu_dir else {}
+    l2_atom = per_kernel(atomic_dir, "TCC_ATOMIC_sum") if atomic_dir else {}
+    ea_atom = per_kernel(atomic_dir, "TCC_EA0_ATOMIC_sum") if atomic_dir else {}
     known_kib = 256 * 1024
     fscale = known_kib / fetch["k_bench_read"]
     wscale = known_kib / write["k_bench_write"]
@@ -489,8 +502,8 @@ def summarize_counters(fetch_dir: str, write_dir: str, valu_dir: str = None):
           f"(scale {fscale:.3f}); WRITE_SIZE {write['k_bench_write']:.0f} KiB for {known_kib} "
           f"KiB written (scale {wscale:.3f})")
     print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled HBM MB (read + write) | "
-          "SQ_INSTS_VALU |")
-    print("|---|---|---|---|---|")
+          "SQ_INSTS_VALU | TCC_ATOMIC | TCC_EA0_ATOMIC |")
+    print("|---|---|---|---|---|---|---|")
     for k, src in KERNEL_SOURCES.items():
         if k not in fetch or k not in write:
             continue
@@ -499,18 +512,21 @@ def summarize_counters(fetch_dir: str, write_dir: str, valu_dir: str = None):
         b = (fetch[k] * fscale + write[k] * wscale) * 1024
         tab[k] = {"source": src, "source_sha": sha, "bytes_per_launch": b,
                   "fetch_kib": fetch[k], "write_kib": write[k], "fetch_scale": fscale,
-                  "write_scale": wscale, "valu_insts_per_launch": valu.get(k)}
-        v = valu.get(k)
+                  "write_scale": wscale, "valu_insts_per_launch": valu.get(k),
+                  "l2_atomics_per_launch": l2_atom.get(k),
+                  "ea_atomics_per_launch": ea_atom.get(k)}
+        v, a2, ae = valu.get(k), l2_atom.get(k), ea_atom.get(k)
         print(f"| {k} | {fetch[k]:.1f} | {write[k]:.1f} | {b / 1e6:.1f} | "
-              f"{'' if v is None else f'{v:.4g}'} |")
+              f"{'' if v is None else f'{v:.4g}'} | {'' if a2 is None else f'{a2:.4g}'} | "
+              f"{'' if ae is None else f'{ae:.4g}'} |")
     with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as f:
         json.dump(tab, f, indent=1)
 
 
 def main():
     if len(sys.argv) > 1 and sys.argv[1] == "--counters":
-        # python bench.py --counters FETCH_DIR WRITE_DIR [VALU_DIR]
-        summarize_counters(*sys.argv[2:5])
+        # python bench.py --counters FETCH_DIR WRITE_DIR [VALU_DIR [ATOMIC_DIR]]
+        summarize_counters(*sys.argv[2:6])
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)

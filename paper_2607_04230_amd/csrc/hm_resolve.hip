@@ -271,9 +271,10 @@ __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, flo
 
 // Strip counts for alpha (Sec. 3.3): over the window taps whose distance to
 // the strand's screen line through the pixel is within the strip half width
-// h, count those with any hit (Ha) and with a centre hit (Hc).  Membership is
-// decided in binary32 exactly as perp2 = |o - (o.T) T|^2 <= h^2 (a zero
-// tangent, the isotropic case, gives |o|^2).  Only taps near the line are
+// h, count those with any hit (Ha) and with a centre hit (Hc; hcode holds 1 +
+// 2^16 for a centre hit, 1 for a conservative hit only, 0 for none).
+// Membership is decided in binary32 exactly as perp2 = |o - (o.T) T|^2 <= h^2
+// (a zero tangent, the isotropic case, gives |o|^2).  Only taps near the line are
 // tested: along the line's major axis every offset a in [-r, r] has its
 // minor-axis candidates b in an interval of width 2h / |major component|
 // around the line, widened by 0.05 against rounding (an error of perp2 of a
@@ -282,12 +283,11 @@ __device__ __forceinline__ void filter_tap(const FilterPix &f, FilterAcc &a, flo
 // components of o - (o.T) T are a - (o.T) P and b - (o.T) Q: the same
 // products and sums as the (x, y) form, only added in the other order for a
 // steep tangent, which leaves every binary32 result unchanged.
-__device__ __forceinline__ void strip_counts(const uint32_t *words, int E, int cx, int cy, int r,
+__device__ __forceinline__ void strip_counts(const uint32_t *hcode, int E, int cx, int cy, int r,
                                              float Tx, float Ty, float h, float h2, int &Hc,
                                              int &Ha)
 {
-    Hc = 0;
-    Ha = 0;
+    uint32_t cnt = 0;       // Ha + 2^16 Hc
     const bool steep = fabsf(Ty) >= fabsf(Tx);      // iso (0, 0) counts as steep
     const float P = steep ? Ty : Tx, Q = steep ? Tx : Ty;
     const float aM = fabsf(P);
@@ -307,11 +307,11 @@ __device__ __forceinline__ void strip_counts(const uint32_t *words, int E, int c
             const float par = pa + fb * Q;
             const float u = fa - par * P, v = fb - par * Q;
             const bool in = u * u + v * v <= h2;
-            const uint32_t bits = words[idx];
-            Ha += in && bits != REC_EMPTY ? 1 : 0;
-            Hc += in && bits <= HM_QMAX ? 1 : 0;            // a centre hit's depth code
+            cnt += in ? hcode[idx] : 0u;
         }
     }
+    Ha = (int)(cnt & 0xFFFFu);
+    Hc = (int)(cnt >> 16);
 }
 
 // R > 0: the radius is a compile-time constant (each row of taps unrolls into
@@ -322,10 +322,12 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
                                                 ShadeK k, const float4 *rec, float4 *out)
 {
     constexpr int EMAX = R > 0 ? FT + 2 * R : HALO_MAX;
-    // colours with |C|^2, and the record words apart (the strip reads only
-    // words, at consecutive addresses)
+    // colours with |C|^2, the record words apart, and per record the strip's
+    // counts: 1 for any hit plus 2^16 for a centre hit (the strip reads
+    // consecutive addresses)
     __shared__ float4 tile[EMAX * EMAX];
     __shared__ uint32_t words[EMAX * EMAX];
+    __shared__ uint32_t hcode[EMAX * EMAX];
     const int r = R > 0 ? R : k.r;
     const int E = R > 0 ? EMAX : FT + 2 * r;
     const uint32_t tiles_x = (W + FT - 1) / FT;
@@ -369,7 +371,9 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         float4 v = make_float4(0.f, 0.f, 0.f, __uint_as_float(REC_EMPTY));
         if (gi >= 0 && gj >= 0 && gi < (int)W && gj < (int)H) v = recs[(size_t)gj * W + gi];
         tile[ly * E + lx] = make_float4(v.x, v.y, v.z, fmaf(v.x, v.x, fmaf(v.y, v.y, v.z * v.z)));
-        words[ly * E + lx] = __float_as_uint(v.w);
+        const uint32_t wd = __float_as_uint(v.w);
+        words[ly * E + lx] = wd;
+        hcode[ly * E + lx] = (wd != REC_EMPTY ? 1u : 0u) + (wd <= HM_QMAX ? 0x10000u : 0u);
     }
     __syncthreads();
     if (!inb) return;
@@ -449,7 +453,7 @@ __global__ __launch_bounds__(256) void k_filter(const float4 *pos, const uint64_
         }
     }
     int Hc, Ha;
-    strip_counts(words, E, li + r, lj + r, r, Tx, Ty, k.strip_half, k.strip2, Hc, Ha);
+    strip_counts(hcode, E, li + r, lj + r, r, Tx, Ty, k.strip_half, k.strip2, Hc, Ha);
     const float aP = Ha > 0 ? (float)Hc / (float)Ha : 1.0f;
     float rr = 0.f, gg = 0.f, bb = 0.f, alpha = 0.f;
     if (hc && !mism) {
