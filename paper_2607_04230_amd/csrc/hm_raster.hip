@@ -1188,19 +1188,18 @@ __global__ __launch_bounds__(256) void k_raster_flat(
                 }
                 if (!eval) continue;
                 wave_sync();
-                // evaluate the window, one candidate per lane; compiled apart
-                // for the (uniform) reciprocal path and for batches holding a
-                // segment of zero length
+                // evaluate the window; compiled apart for the (uniform)
+                // reciprocal path and for batches holding a segment of zero
+                // length
                 auto evaluate = [&](auto fast_tag, auto degen_tag) {
                     constexpr bool FAST = decltype(fast_tag)::value;
                     constexpr bool DEGEN = decltype(degen_tag)::value;
-                    for (uint32_t p0 = 0; p0 < fill; p0 += 64) {
-                        const uint32_t pl = p0 + lane;
-                        if (pl >= fill) continue;
-                        const uint32_t d = pdesc[pl];
+                    // coverage of both layers and the key of candidate d
+                    auto cand = [&](uint32_t d, bool &cc, bool &ca, uint32_t &x, uint32_t &q,
+                                    unsigned long long &key) {
                         const uint32_t o = d & 0xFFu;
                         const uint32_t jl = (d >> 8) & 31u, il = d >> 13;
-                        const uint32_t x = __umul24(jl, P) + il;
+                        x = __umul24(jl, P) + il;
                         const float fi = (float)(px0 + (int)il), fj = (float)(py0 + (int)jl);
                         const float x0 = rf[0 * nb + o], y0 = rf[1 * nb + o];
                         const float w0 = rf[2 * nb + o], dx = rf[4 * nb + o];
@@ -1216,7 +1215,7 @@ __global__ __launch_bounds__(256) void k_raster_flat(
                         const float r = fmaxf(0.5f * wt, rmin);
                         const float r2 = r * r;
                         const float cr = ux * dy - uy * dx;
-                        bool cc = (tn >= 0.0f) & (tn < len2) & (cr * cr <= r2 * len2);
+                        cc = (tn >= 0.0f) & (tn < len2) & (cr * cr <= r2 * len2);
                         // a segment of zero length: distance to its point
                         if (DEGEN && !(len2 > 0.0f)) cc = (ux * ux + uy * uy) <= r2;
                         // conservative: separating axes x, y and the normal
@@ -1226,28 +1225,60 @@ __global__ __launch_bounds__(256) void k_raster_flat(
                         const float ga = (by0 - y0) * dx, gb = (by1 - y0) * dx;
                         const float lo = fminf(fa, fb) - fmaxf(ga, gb);
                         const float hi = fmaxf(fa, fb) - fminf(ga, gb);
-                        const bool ca = (rf[11 * nb + o] <= bx1) & (rf[12 * nb + o] >= bx0) &
-                                        (rf[13 * nb + o] <= by1) & (rf[14 * nb + o] >= by0) &
-                                        (lo <= 0.0f) & (hi >= 0.0f);
-                        if (!(cc | ca)) continue;
+                        ca = (rf[11 * nb + o] <= bx1) & (rf[12 * nb + o] >= bx0) &
+                             (rf[13 * nb + o] <= by1) & (rf[14 * nb + o] >= by0) &
+                             (lo <= 0.0f) & (hi >= 0.0f);
                         // depth at the clamped closest point
                         float ts = t;
                         ts = fmaxx(ts, 0.0f);
                         ts = fminx(ts, 1.0f);
                         const float iz = rf[3 * nb + o] + ts * rf[7 * nb + o];
                         const float z = FAST ? rcp_refined(iz) : 1.0f / iz;
-                        const uint32_t q = depth_code(z, zn, inv_range);
+                        q = depth_code(z, zn, inv_range);
+                        const uint64_t low =
+                            GB ? gb_payload(gk.tan, gk.rgb, r_sid[o], ts, z,
+                                            rf[REC_FLOATS * nb + o])
+                               : (uint64_t)r_sid[o];
+                        key = ((unsigned long long)q << HM_ID_BITS) | low;
+                    };
+                    auto merge = [&](bool cc, bool ca, uint32_t x, uint32_t q,
+                                     unsigned long long key) {
                         if (DOM) {
                             if (ca) dom_count(cnt, q0t, x, TP, q, dk);
                         } else {
-                            const uint64_t low =
-                                GB ? gb_payload(gk.tan, gk.rgb, r_sid[o], ts, z,
-                                                rf[REC_FLOATS * nb + o])
-                                   : (uint64_t)r_sid[o];
-                            const unsigned long long key =
-                                ((unsigned long long)q << HM_ID_BITS) | low;
                             if (cc) atomicMin((unsigned long long *)&lc[x], key);
                             if (ca) atomicMin((unsigned long long *)&la[x], key);
+                        }
+                    };
+                    if constexpr (GB) {
+                        // one candidate per lane and step: the payload's
+                        // registers would cost occupancy with two
+                        for (uint32_t p0 = 0; p0 < fill; p0 += 64) {
+                            const uint32_t pa = p0 + lane;
+                            if (pa >= fill) continue;
+                            bool cca, caa;
+                            uint32_t xa, qa;
+                            unsigned long long ka;
+                            cand(pdesc[pa], cca, caa, xa, qa, ka);
+                            merge(cca, caa, xa, qa, ka);
+                        }
+                    } else {
+                        // two candidates per lane and step (pl and pl + 64),
+                        // both evaluated without branches so that their LDS
+                        // reads and arithmetic interleave; a lane past the
+                        // window's end evaluates the window's first
+                        // descriptor and discards the result
+                        for (uint32_t p0 = 0; p0 < fill; p0 += 128) {
+                            const uint32_t pa = p0 + lane, pb = pa + 64u;
+                            const bool va = pa < fill, vb = pb < fill;
+                            const uint32_t da = pdesc[va ? pa : 0u], db = pdesc[vb ? pb : 0u];
+                            bool cca, caa, ccb, cab;
+                            uint32_t xa, xb, qa, qb;
+                            unsigned long long ka, kb;
+                            cand(da, cca, caa, xa, qa, ka);
+                            cand(db, ccb, cab, xb, qb, kb);
+                            merge(va & cca, va & caa, xa, qa, ka);
+                            merge(vb & ccb, vb & cab, xb, qb, kb);
                         }
                     }
                 };
