@@ -995,8 +995,9 @@ __device__ __forceinline__ void line_span(const float *rf, uint32_t nb, uint32_t
 //      line's candidate span, and the wave appends the candidates' descriptors
 //      (segment | row and column in the tile) to its window, which gathers the
 //      candidates of several groups;
-//   3. a full window (and the last one of the batch) is evaluated one
-//      candidate per lane, 64 at a time, with LDS 64-bit minima into the tile.
+//   3. a full window (and the last one of the batch) is evaluated two
+//      candidates per lane at a time (one with G-buffer keys), with LDS 64-bit
+//      minima into the tile.
 // NB: the workgroup size when known at compile time (fixed LDS offsets), 0 for
 // any blockDim (at most 256).
 template <uint32_t NB, bool DOM, bool GB>
