@@ -255,6 +255,26 @@ hm_status hm_raster_vis(const hm_strands *s, const hm_camera *cams, const hm_fra
                         const hm_raster_params *p, const float *scene_z, uint64_t *vis,
                         void *ws, size_t ws_bytes, void *stream);
 
+/* Strand generation (Sec. 3.1.1) and the tiled raster (Sec. 3.1.2) in one
+ * call, the generator binning as it assembles: each workgroup of
+ * hm_generate_strands also projects every control point it makes and files
+ * every segment of its finished strands into its screen tiles (tile box,
+ * separating-axis test, per-workgroup LDS table of (segment, tile) counts),
+ * which replaces the raster's first pass over the stored stream; the tile
+ * lists are then filled and the tiles rasterized as by hm_raster_vis.  The
+ * stream written to out and vis are exactly those of hm_generate_strands
+ * followed by hm_raster_vis with the same arguments.  Requires p->algo =
+ * HM_RASTER_TILED, p->payload = HM_PAYLOAD_SEGMENT, p->shared_views = 0 and
+ * out->n_scenes = frame->n_scenes (else HM_ERR_INVALID).  Arguments as for
+ * those two calls; ws: hm_workspace_size(HM_CALL_GEN_RASTER, frame,
+ * mesh->n_bundles, out->cap, p) bytes. */
+hm_status hm_generate_raster_tiled(const hm_hair_mesh *mesh, const uint32_t *table,
+                                   const uint32_t *strand_base, const float *strand_rgb,
+                                   const hm_gen_params *gp, const hm_strands *out,
+                                   const hm_camera *cams, const hm_frame *frame,
+                                   const hm_raster_params *p, const float *scene_z,
+                                   uint64_t *vis, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ resolve */
 enum { HM_RESOLVE_FILTER = 0, HM_RESOLVE_SOFT = 1, HM_RESOLVE_CENTER = 2 };
 
@@ -382,10 +402,12 @@ hm_status hm_dom_shadow(const hm_strands *s, const uint64_t *vis, const hm_camer
                         uint32_t n_bundles, float *shadow, void *stream);
 
 /* ------------------------------------------------------------------ workspace */
-enum { HM_CALL_LOD = 0, HM_CALL_RASTER = 1, HM_CALL_RESOLVE = 2, HM_CALL_DOM = 3 };
+enum { HM_CALL_LOD = 0, HM_CALL_RASTER = 1, HM_CALL_RESOLVE = 2, HM_CALL_DOM = 3,
+       HM_CALL_GEN_RASTER = 4 };
 
-/* Workspace bytes for `call`.  n_bundles (LOD) or cap (raster) size it;
- * raster params may be NULL (defaults).  Returns HM_ERR_RANGE on overflow. */
+/* Workspace bytes for `call`.  n_bundles (LOD, GEN_RASTER) and cap (raster,
+ * GEN_RASTER) size it; raster params may be NULL (defaults).  Returns
+ * HM_ERR_RANGE on overflow. */
 hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bundles,
                             uint32_t cap, const hm_raster_params *p, size_t *bytes);
 

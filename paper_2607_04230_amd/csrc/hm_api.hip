@@ -317,6 +317,14 @@ hm_status hm_workspace_size(int32_t call, const hm_frame *frame, uint32_t n_bund
         st = check_raster_params(p);
         if (st) return st;
         *bytes = raster_workspace(*frame, cap, *p);
+    } else if (call == HM_CALL_GEN_RASTER) {
+        REQUIRE(n_bundles >= 1, HM_ERR_INVALID, "n_bundles must be >= 1");
+        REQUIRE(cap >= 1 && cap < 0xFFFFFFFFu, HM_ERR_RANGE, "cap outside [1, 2^32 - 2]");
+        hm_raster_params d;
+        if (!p) { raster_defaults(*frame, d); p = &d; }
+        st = check_raster_params(p);
+        if (st) return st;
+        *bytes = gen_raster_workspace(n_bundles, *frame, cap, *p);
     } else if (call == HM_CALL_RESOLVE) {
         *bytes = resolve_workspace(*frame);
     } else if (call == HM_CALL_DOM) {
@@ -409,6 +417,40 @@ hm_status hm_raster_vis(const hm_strands *s, const hm_camera *cams, const hm_fra
     if ((st = check_ws(ws, ws_bytes, raster_workspace(*frame, s->cap, *p)))) return st;
     launch_raster(*s, cams, *frame, *p, scene_z, vis, ws, (hipStream_t)stream);
     return check_launch("hm_raster_vis");
+}
+
+hm_status hm_generate_raster_tiled(const hm_hair_mesh *mesh, const uint32_t *table,
+                                   const uint32_t *strand_base, const float *strand_rgb,
+                                   const hm_gen_params *gp, const hm_strands *out,
+                                   const hm_camera *cams, const hm_frame *frame,
+                                   const hm_raster_params *p, const float *scene_z,
+                                   uint64_t *vis, void *ws, size_t ws_bytes, void *stream)
+{
+    hm_status st;
+    if ((st = check_mesh(mesh)) || (st = check_strands(out)) || (st = check_frame(frame)) ||
+        (st = check_raster_params(p)))
+        return st;
+    REQUIRE(table && gp && cams && vis, HM_ERR_INVALID, "NULL argument");
+    REQUIRE(!strand_rgb || strand_base, HM_ERR_INVALID, "strand_rgb needs strand_base");
+    REQUIRE(isfinite(gp->width) && isfinite(gp->curl_amp) && isfinite(gp->curl_turns) &&
+                gp->curl_turns >= 0,
+            HM_ERR_RANGE, "generation parameters must be finite (curl_turns >= 0)");
+    REQUIRE(p->algo == HM_RASTER_TILED && p->payload == HM_PAYLOAD_SEGMENT && !p->shared_views,
+            HM_ERR_INVALID,
+            "generation with binning needs the tiled algorithm, segment ids and one view per "
+            "scene");
+    REQUIRE(out->n_scenes == frame->n_scenes, HM_ERR_INVALID,
+            "strands.n_scenes (%u) != frame.n_scenes (%u)", out->n_scenes, frame->n_scenes);
+    const double tiles = (double)((frame->width + p->tile - 1) / p->tile) *
+                         ((frame->height + p->tile - 1) / p->tile) * frame->n_scenes;
+    REQUIRE(tiles < 1.0e9, HM_ERR_RANGE, "too many tiles");
+    REQUIRE((double)out->cap * p->max_tiles_per_seg < 4.0e9, HM_ERR_RANGE,
+            "cap * max_tiles_per_seg exceeds 32-bit bin offsets");
+    if ((st = check_ws(ws, ws_bytes, gen_raster_workspace(mesh->n_bundles, *frame, out->cap, *p))))
+        return st;
+    launch_gen_raster_tiled(*mesh, table, strand_base, strand_rgb, *gp, *out, cams, *frame, *p,
+                            scene_z, vis, ws, (hipStream_t)stream);
+    return check_launch("hm_generate_raster_tiled");
 }
 
 hm_status hm_resolve_shade(const hm_strands *s, const uint64_t *vis, const hm_camera *cams,

@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "hm.h"
+#include "hm_bin.hpp"
 
 namespace hm {
 
@@ -66,6 +67,21 @@ void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
                             const hm_gen_params &p, const hm_strands &s, const hm_camera *cams,
                             const hm_frame &f, float r_min, int payload, const float *scene_z,
                             uint64_t *vis, hipStream_t st);
+
+// strand generation that also does the tile raster's first binning pass, and
+// the tile raster that follows it (single-view frames, tiled algorithm)
+uint32_t gen_bundles_per_group(uint32_t n_bundles, uint32_t cap);
+uint32_t gen_grid(uint32_t n_bundles, uint32_t cap);
+void launch_generate_bin(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
+                         const float *strand_rgb, const hm_gen_params &p, const hm_strands &s,
+                         const BinK &bk, hipStream_t st);
+size_t gen_raster_workspace(uint32_t n_bundles, const hm_frame &f, uint32_t cap,
+                            const hm_raster_params &p);
+void launch_gen_raster_tiled(const hm_hair_mesh &m, const uint32_t *table,
+                             const uint32_t *strand_base, const float *strand_rgb,
+                             const hm_gen_params &gp, const hm_strands &s, const hm_camera *cams,
+                             const hm_frame &f, const hm_raster_params &p, const float *scene_z,
+                             uint64_t *vis, void *ws, hipStream_t st);
 
 // deep-opacity-map shadows
 size_t dom_workspace(const hm_frame &light_frame, uint32_t cap);

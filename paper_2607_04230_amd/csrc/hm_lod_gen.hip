@@ -10,7 +10,10 @@
 // strands; lanes then evaluate consecutive control points (Hermite + curl)
 // and store them coalesced.  The fused variant also projects each control
 // point and rasterizes the chunk's segments from LDS (the paper's
-// assembly-and-raster in one pass).
+// assembly-and-raster in one pass); the binning variant projects each control
+// point and bins the chunk's segments into screen tiles where they are
+// generated, in place of the tile raster's first binning pass.
+#include "hm_bin.hpp"
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
 #include "hm_scan.hpp"
@@ -357,246 +360,312 @@ __device__ __forceinline__ void gen_sync()
 // and the strand's colour, and nothing of the stream is written (the paper's
 // register-only assembly); strands longer than the LDS chunk recompute the
 // points a segment needs.
-template <bool FUSED, bool WAVE, bool GB>
+template <bool FUSED, bool WAVE, bool GB, bool BIN>
 __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
                                                         const uint32_t *strand_base,
                                                         const float *strand_rgb, GenK g,
                                                         float4 *pos_w, float4 *rgb,
                                                         uint8_t *flags, const uint32_t *scene_off,
-                                                        uint32_t S, uint32_t cap, FuseK fk)
+                                                        uint32_t S, uint32_t cap, FuseK fk,
+                                                        BinK bk)
 {
+    static_assert(!(BIN && (FUSED || GB)), "binning goes with the plain stream");
     constexpr uint32_t NB = WAVE ? GEN_WAVES : 1u;      // bundles per workgroup
     constexpr uint32_t NT = 256u / NB;                  // threads per bundle
     constexpr uint32_t SM_FLOATS = GEN_LDS_FLOATS / NB, PR_CPS = FUSE_CPS / NB;
     __shared__ float sm_all[GEN_LDS_FLOATS];
-    __shared__ float4 pr_all[FUSED ? FUSE_CPS : GEN_WAVES];
+    __shared__ float4 pr_all[FUSED || BIN ? FUSE_CPS : GEN_WAVES];
     __shared__ float4 tn_all[GB ? FUSE_CPS : 1];        // world points, then unit tangents
+    __shared__ uint32_t bkeys[BIN ? BIN_SLOTS : 1], bcnt[BIN ? BIN_SLOTS : 1];
+    __shared__ uint32_t bsave;
+    if (BIN) {
+        // the workgroup's (segment, tile) table
+        for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+            bkeys[x] = BIN_FREE;
+            bcnt[x] = 0u;
+        }
+        if (threadIdx.x == 0) bsave = 0u;
+        __syncthreads();
+    }
     const uint32_t wv = WAVE ? threadIdx.x >> 6 : 0u;
     const uint32_t lane = WAVE ? threadIdx.x & 63u : threadIdx.x;
     const uint32_t b = blockIdx.x * NB + wv;
-    if (b >= m.n_bundles) return;                  // the whole wave / workgroup
-    float *sm = sm_all + wv * SM_FLOATS;
-    float4 *pr = pr_all + (FUSED ? wv * PR_CPS : 0u);
-    float4 *tn = tn_all + (GB ? wv * PR_CPS : 0u);
-    const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
-    const uint32_t n = tb.x, C = tb.y, cp0 = tb.w;
-    if (n == 0) return;
-    const uint32_t total = scene_off[S];
-    const uint32_t limit = total < cap ? total : cap;
-    const uint32_t NL = m.n_layers;
-    const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
-    uint32_t chunk = SM_FLOATS / stride;     // >= 2 (WAVE) / 10 strands for L <= 64
-    // screen records of a chunk stay in LDS when a strand fits (C <= 256
-    // (WAVE) / 1024); longer strands are projected again from the stream
-    // they were just written to (same bits, no LDS limit)
-    const bool in_lds = C <= PR_CPS;
-    if (FUSED && in_lds) chunk = min(chunk, PR_CPS / C);   // >= 2 strands for C <= 127
-    Cam cam;
-    uint32_t sc = 0;
-    if (FUSED) {
-        sc = m.bundle_scene[b];
-        cam = load_cam(fk.cams + sc);
-    }
-    const uint4 q4 = reinterpret_cast<const uint4 *>(m.quads)[b];
-    const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
-    const uint32_t hb = bundle_hash(g.seed, m.bundle_key[b]);
+    // one bundle's work (a return leaves the bundle, not the workgroup)
+    auto bundle = [&]() {
+        if (b >= m.n_bundles) return;                  // the whole wave / workgroup
+        float *sm = sm_all + wv * SM_FLOATS;
+        float4 *pr = pr_all + (FUSED || BIN ? wv * PR_CPS : 0u);
+        float4 *tn = tn_all + (GB ? wv * PR_CPS : 0u);
+        const uint4 tb = reinterpret_cast<const uint4 *>(table)[b];
+        const uint32_t n = tb.x, C = tb.y, cp0 = tb.w;
+        if (n == 0) return;
+        const uint32_t total = scene_off[S];
+        const uint32_t limit = total < cap ? total : cap;
+        const uint32_t NL = m.n_layers;
+        const uint32_t stride = 6u * NL + 3u;                 // P[L], T[L], u, v, phase
+        uint32_t chunk = SM_FLOATS / stride;     // >= 2 (WAVE) / 10 strands for L <= 64
+        // screen records of a chunk stay in LDS when a strand fits (C <= 256
+        // (WAVE) / 1024); longer strands are projected again from the stream
+        // they were just written to (same bits, no LDS limit)
+        const bool in_lds = C <= PR_CPS;
+        if ((FUSED || BIN) && in_lds) chunk = min(chunk, PR_CPS / C);   // >= 2 strands for C <= 127
+        Cam cam;
+        uint32_t sc = 0;
+        if (FUSED || BIN) {
+            sc = m.bundle_scene[b];
+            cam = load_cam((FUSED ? fk.cams : bk.cams) + sc);
+        }
+        const uint4 q4 = reinterpret_cast<const uint4 *>(m.quads)[b];
+        const uint32_t q[4] = {q4.x, q4.y, q4.z, q4.w};
+        const uint32_t hb = bundle_hash(g.seed, m.bundle_key[b]);
 
-    // bundle styling frame from the first layer interval
-    F3 s0 = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) {
-        const F3 a0 = ld3(m.layer_pos + 3 * (size_t)q[k2]);
-        const F3 a1 = ld3(m.layer_pos + ((size_t)m.n_verts + q[k2]) * 3);
-        const F3 d = f3sub(a1, a0);
-        s0.x = s0.x + d.x; s0.y = s0.y + d.y; s0.z = s0.z + d.z;
-    }
-    const F3 nb = f3norm(s0);
-    F3 ax = {0.0f, 0.0f, 1.0f};
-    if (fabsf(nb.z) > 0.9f) { ax.x = 1.0f; ax.z = 0.0f; }
-    const F3 e1 = f3norm(f3cross(nb, ax));
-    const F3 e2 = f3cross(nb, e1);
+        // bundle styling frame from the first layer interval
+        F3 s0 = {0.0f, 0.0f, 0.0f};
+    #pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) {
+            const F3 a0 = ld3(m.layer_pos + 3 * (size_t)q[k2]);
+            const F3 a1 = ld3(m.layer_pos + ((size_t)m.n_verts + q[k2]) * 3);
+            const F3 d = f3sub(a1, a0);
+            s0.x = s0.x + d.x; s0.y = s0.y + d.y; s0.z = s0.z + d.z;
+        }
+        const F3 nb = f3norm(s0);
+        F3 ax = {0.0f, 0.0f, 1.0f};
+        if (fabsf(nb.z) > 0.9f) { ax.x = 1.0f; ax.z = 0.0f; }
+        const F3 e1 = f3norm(f3cross(nb, ax));
+        const F3 e2 = f3cross(nb, e1);
 
-    for (uint32_t k0 = 0; k0 < n; k0 += chunk) {
-        const uint32_t nk = (n - k0) < chunk ? (n - k0) : chunk;
-        // base layer points; the strand's (u, v) and curl phase come from its
-        // hash, recomputed by each of its layers' threads (no separate stage)
-        for (uint32_t x = lane; x < nk * NL; x += NT) {
-            const uint32_t kk = x / NL, l = x - kk * NL;
-            float *o = sm + kk * stride;
-            const uint32_t h1 = pcg(hb + (k0 + kk));
-            const uint32_t h2 = pcg(h1);
-            const float u = unit24(h1), v = unit24(h2);
-            if (l == 0) {
-                o[6u * NL] = u;
-                o[6u * NL + 1] = v;
-                o[6u * NL + 2] = unit24(pcg(h2));
-            }
-            const F3 P = layer_point(m.layer_pos, m.n_verts, l, q, u, v);
-            o[6 * l + 0] = P.x; o[6 * l + 1] = P.y; o[6 * l + 2] = P.z;
-        }
-        gen_sync<WAVE>();
-        // finite-difference layer tangents
-        for (uint32_t x = lane; x < nk * NL; x += NT) {
-            const uint32_t kk = x / NL, l = x - kk * NL;
-            float *o = sm + kk * stride;
-            const uint32_t la = l == 0 ? 1u : (l == NL - 1 ? l : l + 1);
-            const uint32_t lb = l == 0 ? 0u : l - 1;
-            const F3 T = f3norm(f3sub(ld3(o + 6 * la), ld3(o + 6 * lb)));
-            o[6 * l + 3] = T.x; o[6 * l + 4] = T.y; o[6 * l + 5] = T.z;
-        }
-        gen_sync<WAVE>();
-        // styled control point j of chunk strand kk: chord-scaled Hermite
-        // between the layer points, then the curl about the bundle axis
-        auto styled_cp = [&](uint32_t kk, uint32_t j) -> float4 {
-            const float *o = sm + kk * stride;
-            const float w = (float)j / (float)(C - 1u);
-            const float x = w * (float)(NL - 1u);
-            int i = (int)x;
-            i = i > (int)NL - 2 ? (int)NL - 2 : i;
-            const float t = x - (float)i;
-            const F3 Pi = ld3(o + 6 * i), Pj = ld3(o + 6 * (i + 1));
-            const F3 Ti = ld3(o + 6 * i + 3), Tj = ld3(o + 6 * (i + 1) + 3);
-            const F3 ch = f3sub(Pj, Pi);
-            const float chord = sqrtf((ch.x * ch.x + ch.y * ch.y) + ch.z * ch.z);
-            const float t2 = t * t, t3 = t2 * t;
-            const float h00 = (2.0f * t3 - 3.0f * t2) + 1.0f;
-            const float h10 = (t3 - 2.0f * t2) + t;
-            const float h01 = 3.0f * t2 - 2.0f * t3;
-            const float h11 = t3 - t2;
-            const float pi3[3] = {Pi.x, Pi.y, Pi.z}, pj3[3] = {Pj.x, Pj.y, Pj.z};
-            const float ti3[3] = {Ti.x, Ti.y, Ti.z}, tj3[3] = {Tj.x, Tj.y, Tj.z};
-            float X[3];
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                const float m0 = chord * ti3[d], m1 = chord * tj3[d];
-                X[d] = ((h00 * pi3[d] + h10 * m0) + h01 * pj3[d]) + h11 * m1;
-            }
-            float f = g.curl_turns * w + o[6u * NL + 2];
-            f = f - floorf(f);
-            const float a = (f - 0.5f) * 0x1.921fb6p+2f;
-            const float cth = -tcos(a), sth = -tsin(a);
-            const float amp = g.curl_amp * w;
-            float4 pw;
-            pw.x = X[0] + amp * (cth * e1.x + sth * e2.x);
-            pw.y = X[1] + amp * (cth * e1.y + sth * e2.y);
-            pw.z = X[2] + amp * (cth * e1.z + sth * e2.z);
-            pw.w = g.width;
-            return pw;
-        };
-        auto strand_col = [&](uint32_t kk) -> float4 {
-            if (strand_rgb) {
-                const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k0 + kk);
-                return make_float4(sr[0], sr[1], sr[2], 1.0f);
-            }
-            return make_float4(g.br, g.bg, g.bb, 1.0f);
-        };
-        // control points of strands k0 .. k0+nk-1 (contiguous in the stream)
-        for (uint32_t r = lane; r < nk * C; r += NT) {
-            const uint32_t kk = r / C, j = r - kk * C;
-            const uint32_t c = cp0 + (k0 + kk) * C + j;
-            if (c >= limit) continue;
-            const float4 pw = styled_cp(kk, j);
-            if (GB) {
-                if (in_lds) tn[r] = pw;
-                continue;
-            }
-            pos_w[c] = pw;
-            if (FUSED && in_lds) pr[r] = project(cam, pw);
-            rgb[c] = strand_col(kk);
-            uint8_t fl = 0;
-            if (j == 0) fl |= (uint8_t)HM_ROOT;
-            // the last CP of a stream truncated to the capacity ends its strand
-            if (j == C - 1u || c == limit - 1u) fl |= (uint8_t)HM_TIP;
-            flags[c] = fl;
-        }
-        if (GB && in_lds) {
-            // screen records and unit tangents of the chunk's points (the
-            // tangents replace the world points once every lane has read its
-            // neighbours)
-            // a chunk holds at most PR_CPS = 4 NT points: four per lane
-            static_assert(PR_CPS == 4u * NT, "four chunk points per lane");
-            gen_sync<WAVE>();
-            float4 tr[4];
-#pragma unroll
-            for (uint32_t it = 0; it < 4u; ++it) {
-                const uint32_t r = lane + it * NT;
-                const uint32_t kk = r / C, j = r - kk * C;
-                const uint32_t c = cp0 + (k0 + kk) * C + j;
-                tr[it] = make_float4(0.f, 0.f, 0.f, 0.f);
-                if (r >= nk * C || c >= limit) continue;
-                const float4 P = tn[r];
-                pr[r] = project(cam, P);
-                const bool root = j == 0, tip = j == C - 1u || c == limit - 1u;
-                tr[it] = cp_unit_tangent(root ? P : tn[r - 1], tip ? P : tn[r + 1], root && tip);
+        for (uint32_t k0 = 0; k0 < n; k0 += chunk) {
+            const uint32_t nk = (n - k0) < chunk ? (n - k0) : chunk;
+            // base layer points; the strand's (u, v) and curl phase come from its
+            // hash, recomputed by each of its layers' threads (no separate stage)
+            for (uint32_t x = lane; x < nk * NL; x += NT) {
+                const uint32_t kk = x / NL, l = x - kk * NL;
+                float *o = sm + kk * stride;
+                const uint32_t h1 = pcg(hb + (k0 + kk));
+                const uint32_t h2 = pcg(h1);
+                const float u = unit24(h1), v = unit24(h2);
+                if (l == 0) {
+                    o[6u * NL] = u;
+                    o[6u * NL + 1] = v;
+                    o[6u * NL + 2] = unit24(pcg(h2));
+                }
+                const F3 P = layer_point(m.layer_pos, m.n_verts, l, q, u, v);
+                o[6 * l + 0] = P.x; o[6 * l + 1] = P.y; o[6 * l + 2] = P.z;
             }
             gen_sync<WAVE>();
-#pragma unroll
-            for (uint32_t it = 0; it < 4u; ++it) {
-                const uint32_t r = lane + it * NT;
-                const uint32_t kk = r / C, j = r - kk * C;
-                if (r < nk * C && cp0 + (k0 + kk) * C + j < limit) tn[r] = tr[it];
+            // finite-difference layer tangents
+            for (uint32_t x = lane; x < nk * NL; x += NT) {
+                const uint32_t kk = x / NL, l = x - kk * NL;
+                float *o = sm + kk * stride;
+                const uint32_t la = l == 0 ? 1u : (l == NL - 1 ? l : l + 1);
+                const uint32_t lb = l == 0 ? 0u : l - 1;
+                const F3 T = f3norm(f3sub(ld3(o + 6 * la), ld3(o + 6 * lb)));
+                o[6 * l + 3] = T.x; o[6 * l + 4] = T.y; o[6 * l + 5] = T.z;
             }
-        }
-        gen_sync<WAVE>();
-        if (FUSED) {
-            // segments of the chunk: CP j of strand kk joins j + 1 unless j
-            // is a tip (last CP of its strand, or of a truncated stream)
-            const size_t hw = (size_t)fk.W * fk.H;
-            uint64_t *vc = fk.vis + (size_t)sc * 2 * hw, *va = vc + hw;
-            const float zn = cam.zn, inv_range = 1.0f / (cam.zf - zn);
+            gen_sync<WAVE>();
+            // styled control point j of chunk strand kk: chord-scaled Hermite
+            // between the layer points, then the curl about the bundle axis
+            auto styled_cp = [&](uint32_t kk, uint32_t j) -> float4 {
+                const float *o = sm + kk * stride;
+                const float w = (float)j / (float)(C - 1u);
+                const float x = w * (float)(NL - 1u);
+                int i = (int)x;
+                i = i > (int)NL - 2 ? (int)NL - 2 : i;
+                const float t = x - (float)i;
+                const F3 Pi = ld3(o + 6 * i), Pj = ld3(o + 6 * (i + 1));
+                const F3 Ti = ld3(o + 6 * i + 3), Tj = ld3(o + 6 * (i + 1) + 3);
+                const F3 ch = f3sub(Pj, Pi);
+                const float chord = sqrtf((ch.x * ch.x + ch.y * ch.y) + ch.z * ch.z);
+                const float t2 = t * t, t3 = t2 * t;
+                const float h00 = (2.0f * t3 - 3.0f * t2) + 1.0f;
+                const float h10 = (t3 - 2.0f * t2) + t;
+                const float h01 = 3.0f * t2 - 2.0f * t3;
+                const float h11 = t3 - t2;
+                const float pi3[3] = {Pi.x, Pi.y, Pi.z}, pj3[3] = {Pj.x, Pj.y, Pj.z};
+                const float ti3[3] = {Ti.x, Ti.y, Ti.z}, tj3[3] = {Tj.x, Tj.y, Tj.z};
+                float X[3];
+    #pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const float m0 = chord * ti3[d], m1 = chord * tj3[d];
+                    X[d] = ((h00 * pi3[d] + h10 * m0) + h01 * pj3[d]) + h11 * m1;
+                }
+                float f = g.curl_turns * w + o[6u * NL + 2];
+                f = f - floorf(f);
+                const float a = (f - 0.5f) * 0x1.921fb6p+2f;
+                const float cth = -tcos(a), sth = -tsin(a);
+                const float amp = g.curl_amp * w;
+                float4 pw;
+                pw.x = X[0] + amp * (cth * e1.x + sth * e2.x);
+                pw.y = X[1] + amp * (cth * e1.y + sth * e2.y);
+                pw.z = X[2] + amp * (cth * e1.z + sth * e2.z);
+                pw.w = g.width;
+                return pw;
+            };
+            auto strand_col = [&](uint32_t kk) -> float4 {
+                if (strand_rgb) {
+                    const float *sr = strand_rgb + 3 * ((size_t)strand_base[b] + k0 + kk);
+                    return make_float4(sr[0], sr[1], sr[2], 1.0f);
+                }
+                return make_float4(g.br, g.bg, g.bb, 1.0f);
+            };
+            // control points of strands k0 .. k0+nk-1 (contiguous in the stream)
             for (uint32_t r = lane; r < nk * C; r += NT) {
                 const uint32_t kk = r / C, j = r - kk * C;
                 const uint32_t c = cp0 + (k0 + kk) * C + j;
-                if (j + 1u >= C || c + 1u >= limit) continue;
-                float4 pa, pb, T0, T1;
-                if (in_lds) {
-                    pa = pr[r];
-                    pb = pr[r + 1];
-                    if (GB) {
-                        T0 = tn[r];
-                        T1 = tn[r + 1];
-                    }
-                } else if (GB) {
-                    // no stream to read back: the segment's points again
-                    const float4 P0 = styled_cp(kk, j), P1 = styled_cp(kk, j + 1u);
-                    const bool root = j == 0, tip1 = j + 2u >= C || c + 2u >= limit;
-                    const float4 Pm = root ? P0 : styled_cp(kk, j - 1u);
-                    const float4 P2 = tip1 ? P1 : styled_cp(kk, j + 2u);
-                    pa = project(cam, P0);
-                    pb = project(cam, P1);
-                    T0 = cp_unit_tangent(Pm, P1, false);
-                    T1 = cp_unit_tangent(P0, P2, false);
-                } else {
-                    pa = project(cam, pos_w[c]);
-                    pb = project(cam, pos_w[c + 1]);
+                if (c >= limit) continue;
+                const float4 pw = styled_cp(kk, j);
+                if (GB) {
+                    if (in_lds) tn[r] = pw;
+                    continue;
                 }
-                if (pa.w == 0.0f || pb.w == 0.0f) continue;
-                const Seg sg = make_seg(pa, pb, fk.r_min);
-                const float4 col = GB ? strand_col(kk) : make_float4(0.f, 0.f, 0.f, 0.f);
-                int i0, i1, j0, j1;
-                if (!seg_box(sg, fk.W, fk.H, i0, i1, j0, j1)) continue;
-                for (int y = j0; y <= j1; ++y) {
-                    int a0, a1;
-                    row_span(sg, y, a0, a1);
-                    a0 = a0 > i0 ? a0 : i0;
-                    a1 = a1 < i1 ? a1 : i1;
-                    for (int x = a0; x <= a1; ++x) {
-                        uint32_t q;
-                        bool cc, ca;
-                        float ts, z;
-                        if (!cover_tz(sg, x, y, fk.r_min, zn, inv_range, cc, ca, q, ts, z))
-                            continue;
-                        const uint64_t low =
-                            GB ? gb_payload_of(T0, T1, col, col, ts, z, pb.w) : (uint64_t)c;
-                        const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
-                        const size_t px = (size_t)y * fk.W + x;
-                        if (cc) atomicMin((unsigned long long *)(vc + px), key);
-                        if (ca) atomicMin((unsigned long long *)(va + px), key);
-                    }
+                pos_w[c] = pw;
+                if (FUSED && in_lds) pr[r] = project(cam, pw);
+                if (BIN) {
+                    // the point's screen record, as the binning pass projects it
+                    const float4 a = project(cam, pw);
+                    bk.proj[c] = a;
+                    if (in_lds) pr[r] = a;
+                }
+                rgb[c] = strand_col(kk);
+                uint8_t fl = 0;
+                if (j == 0) fl |= (uint8_t)HM_ROOT;
+                // the last CP of a stream truncated to the capacity ends its strand
+                if (j == C - 1u || c == limit - 1u) fl |= (uint8_t)HM_TIP;
+                flags[c] = fl;
+            }
+            if (GB && in_lds) {
+                // screen records and unit tangents of the chunk's points (the
+                // tangents replace the world points once every lane has read its
+                // neighbours)
+                // a chunk holds at most PR_CPS = 4 NT points: four per lane
+                static_assert(PR_CPS == 4u * NT, "four chunk points per lane");
+                gen_sync<WAVE>();
+                float4 tr[4];
+    #pragma unroll
+                for (uint32_t it = 0; it < 4u; ++it) {
+                    const uint32_t r = lane + it * NT;
+                    const uint32_t kk = r / C, j = r - kk * C;
+                    const uint32_t c = cp0 + (k0 + kk) * C + j;
+                    tr[it] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (r >= nk * C || c >= limit) continue;
+                    const float4 P = tn[r];
+                    pr[r] = project(cam, P);
+                    const bool root = j == 0, tip = j == C - 1u || c == limit - 1u;
+                    tr[it] = cp_unit_tangent(root ? P : tn[r - 1], tip ? P : tn[r + 1], root && tip);
+                }
+                gen_sync<WAVE>();
+    #pragma unroll
+                for (uint32_t it = 0; it < 4u; ++it) {
+                    const uint32_t r = lane + it * NT;
+                    const uint32_t kk = r / C, j = r - kk * C;
+                    if (r < nk * C && cp0 + (k0 + kk) * C + j < limit) tn[r] = tr[it];
                 }
             }
-            // pr is rewritten only after the next chunk's two barriers
+            gen_sync<WAVE>();
+            if (FUSED) {
+                // segments of the chunk: CP j of strand kk joins j + 1 unless j
+                // is a tip (last CP of its strand, or of a truncated stream)
+                const size_t hw = (size_t)fk.W * fk.H;
+                uint64_t *vc = fk.vis + (size_t)sc * 2 * hw, *va = vc + hw;
+                const float zn = cam.zn, inv_range = 1.0f / (cam.zf - zn);
+                for (uint32_t r = lane; r < nk * C; r += NT) {
+                    const uint32_t kk = r / C, j = r - kk * C;
+                    const uint32_t c = cp0 + (k0 + kk) * C + j;
+                    if (j + 1u >= C || c + 1u >= limit) continue;
+                    float4 pa, pb, T0, T1;
+                    if (in_lds) {
+                        pa = pr[r];
+                        pb = pr[r + 1];
+                        if (GB) {
+                            T0 = tn[r];
+                            T1 = tn[r + 1];
+                        }
+                    } else if (GB) {
+                        // no stream to read back: the segment's points again
+                        const float4 P0 = styled_cp(kk, j), P1 = styled_cp(kk, j + 1u);
+                        const bool root = j == 0, tip1 = j + 2u >= C || c + 2u >= limit;
+                        const float4 Pm = root ? P0 : styled_cp(kk, j - 1u);
+                        const float4 P2 = tip1 ? P1 : styled_cp(kk, j + 2u);
+                        pa = project(cam, P0);
+                        pb = project(cam, P1);
+                        T0 = cp_unit_tangent(Pm, P1, false);
+                        T1 = cp_unit_tangent(P0, P2, false);
+                    } else {
+                        pa = project(cam, pos_w[c]);
+                        pb = project(cam, pos_w[c + 1]);
+                    }
+                    if (pa.w == 0.0f || pb.w == 0.0f) continue;
+                    const Seg sg = make_seg(pa, pb, fk.r_min);
+                    const float4 col = GB ? strand_col(kk) : make_float4(0.f, 0.f, 0.f, 0.f);
+                    int i0, i1, j0, j1;
+                    if (!seg_box(sg, fk.W, fk.H, i0, i1, j0, j1)) continue;
+                    for (int y = j0; y <= j1; ++y) {
+                        int a0, a1;
+                        row_span(sg, y, a0, a1);
+                        a0 = a0 > i0 ? a0 : i0;
+                        a1 = a1 < i1 ? a1 : i1;
+                        for (int x = a0; x <= a1; ++x) {
+                            uint32_t q;
+                            bool cc, ca;
+                            float ts, z;
+                            if (!cover_tz(sg, x, y, fk.r_min, zn, inv_range, cc, ca, q, ts, z))
+                                continue;
+                            const uint64_t low =
+                                GB ? gb_payload_of(T0, T1, col, col, ts, z, pb.w) : (uint64_t)c;
+                            const unsigned long long key = ((unsigned long long)q << HM_ID_BITS) | low;
+                            const size_t px = (size_t)y * fk.W + x;
+                            if (cc) atomicMin((unsigned long long *)(vc + px), key);
+                            if (ca) atomicMin((unsigned long long *)(va + px), key);
+                        }
+                    }
+                }
+                // pr is rewritten only after the next chunk's two barriers
+            }
+            if (BIN) {
+                // each control point's unit: the tile box and tiles of the
+                // segment it starts (none for a tip), counted in the table
+                for (uint32_t r = lane; r < nk * C; r += NT) {
+                    const uint32_t kk = r / C, j = r - kk * C;
+                    const uint32_t c = cp0 + (k0 + kk) * C + j;
+                    if (c >= limit) continue;
+                    SegTiles st;
+                    st.nt = 0;
+                    bool ok = false;
+                    if (j + 1u < C && c + 1u < limit) {
+                        float4 pa, pb;
+                        if (in_lds) {
+                            pa = pr[r];
+                            pb = pr[r + 1];
+                        } else {
+                            pa = project(cam, pos_w[c]);
+                            pb = project(cam, pos_w[c + 1]);
+                        }
+                        ok = seg_tiles_of(pa, pb, sc, bk.rk, st);
+                    }
+                    bk.segrec[c] = bin_count(st, ok, c, bk.rk, bk.kmax, bkeys, bcnt, bk.tile_cnt,
+                                             bk.long_list, bk.counters);
+                }
+            }
         }
+    };
+    bundle();
+    if (BIN) {
+        // flush the table: one global add per (workgroup, tile), and save
+        // its occupied slots (slot, tile, count) for the scatter pass
+        __syncthreads();
+        uint32_t *sv = bk.saved + (size_t)blockIdx.x * BIN_SAVE_WORDS;
+        for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+            const uint32_t t = bkeys[x];
+            if (t == BIN_FREE) continue;
+            const uint32_t c = bcnt[x];
+            atomicAdd(&bk.tile_cnt[t], c);
+            const uint32_t i = atomicAdd(&bsave, 1u);
+            sv[1 + 3 * i] = x;
+            sv[2 + 3 * i] = t;
+            sv[3 + 3 * i] = c;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) sv[0] = bsave;
     }
 }
 
@@ -605,24 +674,36 @@ __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const u
 // at full detail averages at most two control points per thread of a
 // workgroup (a workgroup would idle); otherwise one workgroup per bundle.
 // cap bounds the stream, so cap / n_bundles bounds the average bundle.
-static bool gen_wave(const hm_hair_mesh &m, uint32_t cap)
+static bool gen_wave(uint32_t n_bundles, uint32_t cap)
 {
-    return m.n_bundles >= 4096u || (uint64_t)cap <= 512ull * m.n_bundles;
+    return n_bundles >= 4096u || (uint64_t)cap <= 512ull * n_bundles;
 }
 
-template <bool FUSED, bool GB>
+uint32_t gen_bundles_per_group(uint32_t n_bundles, uint32_t cap)
+{
+    return gen_wave(n_bundles, cap) ? GEN_WAVES : 1u;
+}
+
+uint32_t gen_grid(uint32_t n_bundles, uint32_t cap)
+{
+    const uint32_t nb = gen_bundles_per_group(n_bundles, cap);
+    return (n_bundles + nb - 1) / nb;
+}
+
+template <bool FUSED, bool GB, bool BIN = false>
 static void launch_gen_kernel(const hm_hair_mesh &m, const uint32_t *table,
                               const uint32_t *strand_base, const float *strand_rgb, GenK g,
-                              const hm_strands &s, FuseK fk, hipStream_t st)
+                              const hm_strands &s, FuseK fk, hipStream_t st,
+                              BinK bk = BinK{})
 {
-    const bool wave = gen_wave(m, s.cap);
-    const uint32_t grid = wave ? (m.n_bundles + GEN_WAVES - 1) / GEN_WAVES : m.n_bundles;
+    const bool wave = gen_wave(m.n_bundles, s.cap);
+    const uint32_t grid = gen_grid(m.n_bundles, s.cap);
 #define HM_GEN_LAUNCH(W)                                                                    \
-    hipLaunchKernelGGL((k_generate_bundle<FUSED, W, GB>), dim3(grid), dim3(256), 0, st, m,    \
-                       table,                                                                \
+    hipLaunchKernelGGL((k_generate_bundle<FUSED, W, GB, BIN>), dim3(grid), dim3(256), 0, st,  \
+                       m, table,                                                             \
                        strand_base, strand_rgb, g, reinterpret_cast<float4 *>(s.pos_w),        \
                        reinterpret_cast<float4 *>(s.rgb), s.flags, s.scene_off, s.n_scenes,    \
-                       s.cap, fk)
+                       s.cap, fk, bk)
     if (wave)
         HM_GEN_LAUNCH(true);
     else
@@ -654,6 +735,16 @@ void launch_generate_raster(const hm_hair_mesh &m, const uint32_t *table,
         launch_gen_kernel<true, true>(m, table, strand_base, strand_rgb, g, s, fk, st);
     else
         launch_gen_kernel<true, false>(m, table, strand_base, strand_rgb, g, s, fk, st);
+}
+
+void launch_generate_bin(const hm_hair_mesh &m, const uint32_t *table, const uint32_t *strand_base,
+                         const float *strand_rgb, const hm_gen_params &p, const hm_strands &s,
+                         const BinK &bk, hipStream_t st)
+{
+    GenK g{p.seed, p.width, p.curl_amp, p.curl_turns, p.base_rgb[0], p.base_rgb[1],
+           p.base_rgb[2]};
+    launch_gen_kernel<false, false, true>(m, table, strand_base, strand_rgb, g, s,
+                                          FuseK{nullptr, nullptr, 0u, 0u, 0.0f}, st, bk);
 }
 
 }  // namespace hm

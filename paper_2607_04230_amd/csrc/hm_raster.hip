@@ -28,48 +28,13 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "hm_bin.hpp"
 #include "hm_device.hpp"
 #include "hm_internal.hpp"
 #include "hm_scan.hpp"
 
 namespace hm {
 
-struct RasterK {
-    uint32_t S, W, H;
-    float r_min;
-    uint32_t T, ntx, nty, n_tiles;
-    uint32_t chunk, K;
-    uint32_t views;     // 0: scene s draws stream range scene_off[s..s+1];
-                        // 1: every scene (view) draws the whole stream
-};
-
-// Segment space.  A unit u names (scene, stream control point v); screen
-// records, bin entries and long-list entries are indexed by u, keys carry v.
-//   views == 0: u = v, scene from the scene offsets;
-//   views == 1: u = s * n + v over S views of one stream of n points.
-__device__ __forceinline__ uint32_t stream_len(const uint32_t *scene_off, const RasterK &rk,
-                                               uint32_t cap)
-{
-    const uint32_t total = rk.views ? scene_off[1] : scene_off[rk.S];
-    return total < cap ? total : cap;
-}
-
-__device__ __forceinline__ uint32_t unit_count(uint32_t n, const RasterK &rk)
-{
-    return rk.views ? n * rk.S : n;
-}
-
-__device__ __forceinline__ void unit_map(const uint32_t *scene_off, const RasterK &rk, uint32_t n,
-                                         uint32_t u, uint32_t &s, uint32_t &v)
-{
-    if (rk.views) {
-        s = u / n;
-        v = u - s * n;
-    } else {
-        v = u;
-        s = scene_of(scene_off, rk.S, u);
-    }
-}
 
 // ------------------------------------------------------------------ prefill
 __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *scene_z,
@@ -257,30 +222,6 @@ __global__ __launch_bounds__(256) void k_cp_tangent(const float4 *pos, const uin
 }
 
 // ------------------------------------------------------------------ binning
-// Tile-box test: can the segment reach any pixel of tile box [px0, px1) x
-// [py0, py1)?  Separating axes x, y and the segment normal on the box widened
-// by ra + 1 px (a superset of both predicates' support).
-__device__ __forceinline__ bool seg_hits_box(const Seg &sg, float px0, float px1, float py0,
-                                             float py1)
-{
-    const float m = sg.ra + 1.0f;
-    const float bx0 = px0 - m, bx1 = px1 + m, by0 = py0 - m, by1 = py1 + m;
-    if (!(sg.sxmn <= bx1 && sg.sxmx >= bx0 && sg.symn <= by1 && sg.symx >= by0)) return false;
-    const float fa = (bx0 - sg.x0) * sg.dy, fb = (bx1 - sg.x0) * sg.dy;
-    const float ga = (by0 - sg.y0) * sg.dx, gb = (by1 - sg.y0) * sg.dx;
-    const float lo = fminx(fa, fb) - fmaxx(ga, gb);
-    const float hi = fmaxx(fa, fb) - fminx(ga, gb);
-    // widen the sign test by a relative slack against rounding
-    const float slack = 1e-4f * (fabsf(fa) + fabsf(fb) + fabsf(ga) + fabsf(gb)) + 1e-3f;
-    return lo <= slack && hi >= -slack;
-}
-
-// Tiles of one segment: the box [tx0, tx1] x [ty0, ty1] of tiles its candidate
-// pixels fall in (nt = 0: nothing to draw; nt > K: a long segment).
-struct SegTiles {
-    Seg sg;
-    uint32_t s, tx0, ty0, bw, nt;
-};
 
 // Stream inputs of one unit's segment.  The binning loads them one step
 // ahead, so that their latency overlaps the previous segment's tile work.
@@ -318,46 +259,14 @@ __device__ __forceinline__ bool seg_tiles(const SegIn &in, const hm_camera *cams
 {
     st.nt = 0;
     if (!in.live) return false;
-    st.s = in.s;
-    const Cam cam = load_cam(cams + st.s);
+    const Cam cam = load_cam(cams + in.s);
     const float4 a = project(cam, in.p0);
     proj[u] = a;
     if (in.v + 1 >= n || (in.f & HM_TIP)) return false;
-    const float4 b = project(cam, in.p1);
-    if (a.w == 0.0f || b.w == 0.0f) return false;
-    // the fields of make_seg that the tile tests read, computed the same way
-    Seg &sg = st.sg;
-    sg = Seg{};
-    sg.x0 = a.x;
-    sg.y0 = a.y;
-    sg.dx = b.x - a.x;
-    sg.dy = b.y - a.y;
-    sg.ra = fmaxx(0.5f * fmaxx(a.z, b.z), rk.r_min);
-    sg.sxmn = fminx(a.x, b.x); sg.sxmx = fmaxx(a.x, b.x);
-    sg.symn = fminx(a.y, b.y); sg.symx = fmaxx(a.y, b.y);
-    int i0, i1, j0, j1;
-    if (!seg_box(st.sg, rk.W, rk.H, i0, i1, j0, j1)) return false;
-    st.tx0 = (uint32_t)i0 / rk.T;
-    st.ty0 = (uint32_t)j0 / rk.T;
-    st.bw = (uint32_t)i1 / rk.T - st.tx0 + 1;
-    st.nt = st.bw * ((uint32_t)j1 / rk.T - st.ty0 + 1);
-    return true;
+    return seg_tiles_of(a, project(cam, in.p1), in.s, rk, st);
 }
 
-// Tile (tx0 + kx, ty0 + ky) of the segment's tile box; returns false when the
-// segment cannot reach it.  A box of a single tile needs no test (an extra
-// pair would be harmless: the raster tests every pixel exactly).
-__device__ __forceinline__ bool seg_tile_at(const SegTiles &st, const RasterK &rk, uint32_t kx,
-                                            uint32_t ky, uint32_t &tile)
-{
-    const uint32_t tx = st.tx0 + kx, ty = st.ty0 + ky;
-    tile = (st.s * rk.nty + ty) * rk.ntx + tx;
-    if (st.nt == 1u) return true;
-    const float px0 = (float)(tx * rk.T), py0 = (float)(ty * rk.T);
-    return seg_hits_box(st.sg, px0, px0 + (float)rk.T, py0, py0 + (float)rk.T);
-}
 
-constexpr uint32_t BIN_SLOTS = 1024;      // LDS hash slots per workgroup
 #ifndef HM_BIN_SUB
 #define HM_BIN_SUB 8
 #endif
@@ -371,19 +280,6 @@ constexpr uint32_t BIN_SUB = HM_BIN_SUB;      // most segments per thread betwee
 constexpr uint32_t BIN_BLOCK = HM_BIN_BLOCK;  // threads per binning workgroup
 static_assert(BIN_BLOCK % 64 == 0 && BIN_BLOCK <= 1024, "binning workgroups are whole waves");
 constexpr uint32_t BIN_WGS = HM_BIN_WGS;      // workgroups the segments are spread over (at least)
-constexpr uint32_t BIN_FREE = 0xFFFFFFFFu;
-
-// Slot of `tile` in the workgroup's LDS table (linear probing), -1 if full.
-__device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
-{
-    const uint32_t h = (tile * 2654435761u) >> 22;          // 10 bits
-    for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
-        const uint32_t sl = (h + i) & (BIN_SLOTS - 1);
-        const uint32_t prev = atomicCAS(&keys[sl], BIN_FREE, tile);
-        if (prev == BIN_FREE || prev == tile) return (int)sl;
-    }
-    return -1;
-}
 
 // Per-tile segment lists.  Each workgroup takes nsub * blockDim consecutive
 // segments (a "span"; consecutive segments belong to the same few strands, so
@@ -395,27 +291,14 @@ __device__ __forceinline__ int bin_slot(uint32_t *keys, uint32_t tile)
 //           box width and a bit mask of the accepted tiles (segments with
 //           more than BIN_KMAX or K tiles go to the long list); counts pairs
 //           per tile in the table, flushes them with one non-returning
-//           global add per (span, tile) and saves the table;
+//           global add per (span, tile) and saves the table's occupied
+//           slots (slot, tile, count);
 //   pass 1: restores the span's table, reserves a range of each tile's list
 //           with one returning global add per (span, tile), then walks the
 //           segment records and gives each pair an LDS-atomic rank inside
 //           its range -- no screen record is read again.
 // Pairs that found the table full go straight to global counters in both
 // passes.
-constexpr uint32_t BIN_KMAX = 24;         // tile-mask bits in a segment record
-constexpr uint32_t BIN_NONE = 0xFFFFFFFFu;
-
-__device__ __forceinline__ int bin_find(const uint32_t *keys, uint32_t tile)
-{
-    const uint32_t h = (tile * 2654435761u) >> 22;
-    for (uint32_t i = 0; i < BIN_SLOTS; ++i) {
-        const uint32_t q = (h + i) & (BIN_SLOTS - 1);
-        const uint32_t kq = keys[q];
-        if (kq == tile) return (int)q;
-        if (kq == BIN_FREE) return -1;
-    }
-    return -1;
-}
 
 __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const float4 *pos_w,
                                                    const hm_camera *cams, const uint8_t *flags,
@@ -429,6 +312,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                                                    uint32_t max_items)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
+    __shared__ uint32_t sh_nsave;
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
     const uint32_t span = BIN_BLOCK * nsub;        // segments per table flush
@@ -446,7 +330,7 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
     }
     // v below is a segment unit (see unit_map); lists store units
     for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
-        uint32_t *sv = saved + (size_t)(base / span) * (2 * BIN_SLOTS);
+        uint32_t *sv = saved + (size_t)(base / span) * BIN_SAVE_WORDS;
         if (pass == 0) {
             for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
                 keys[x] = BIN_FREE;
@@ -459,43 +343,37 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                 const SegIn cur = nxt;
                 if (sub + 1 < nsub) nxt = seg_load(pos_w, flags, scene_off, rk, v + blockDim.x, n);
                 SegTiles st;
-                bool ok = seg_tiles(cur, cams, proj, rk, v, n, st);
-                if (ok && st.nt > kmax) {
-                    long_list[atomicAdd(&counters[0], 1u)] = v;
-                    ok = false;
-                }
-                uint2 rec = make_uint2(BIN_NONE, 0u);
-                if (ok) {
-                    uint32_t mask = 0, tile0 = 0;
-                    for (uint32_t ky = 0, k = 0; k < st.nt; ++ky)
-                    for (uint32_t kx = 0; kx < st.bw; ++kx, ++k) {
-                        uint32_t tile;
-                        const bool hit = seg_tile_at(st, rk, kx, ky, tile);
-                        if (k == 0) tile0 = tile;
-                        if (!hit) continue;
-                        mask |= 1u << k;
-                        const int sl = bin_slot(keys, tile);
-                        if (sl >= 0) atomicAdd(&cnt[sl], 1u);
-                        else atomicAdd(&tile_cnt[tile], 1u);
-                    }
-                    if (mask) rec = make_uint2(tile0, st.bw | (mask << 8));
-                }
+                const bool ok = seg_tiles(cur, cams, proj, rk, v, n, st);
+                const uint2 rec = bin_count(st, ok, v, rk, kmax, keys, cnt, tile_cnt, long_list,
+                                            counters);
                 if (v < nu) segrec[v] = rec;
             }
             __syncthreads();
+            if (threadIdx.x == 0) sh_nsave = 0u;
+            __syncthreads();
+            // flush, and save the occupied slots as (slot, tile, count)
             for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
                 const uint32_t t = keys[x], c = cnt[x];
-                sv[x] = t;
-                sv[BIN_SLOTS + x] = c;
-                if (t != BIN_FREE) atomicAdd(&tile_cnt[t], c);
+                if (t == BIN_FREE) continue;
+                atomicAdd(&tile_cnt[t], c);
+                const uint32_t i = atomicAdd(&sh_nsave, 1u);
+                sv[1 + 3 * i] = x;
+                sv[2 + 3 * i] = t;
+                sv[3 + 3 * i] = c;
             }
             __syncthreads();
+            if (threadIdx.x == 0) sv[0] = sh_nsave;
         } else {
             for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
-                const uint32_t t = sv[x];
-                keys[x] = t;
+                keys[x] = BIN_FREE;
                 cnt[x] = 0;
-                if (t != BIN_FREE) basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], sv[BIN_SLOTS + x]);
+            }
+            __syncthreads();
+            const uint32_t m = sv[0];
+            for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+                const uint32_t x = sv[1 + 3 * i], t = sv[2 + 3 * i];
+                keys[x] = t;
+                basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], sv[3 + 3 * i]);
             }
             __syncthreads();
             // records loaded one step ahead (see SegIn)
@@ -506,21 +384,68 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                 const uint2 rec = nrec;
                 if (sub + 1 < nsub) nrec = v + blockDim.x < nu ? segrec[v + blockDim.x] : none;
                 if (v >= nu) continue;
-                if (rec.x == BIN_NONE) continue;
-                const uint32_t bw = rec.y & 0xFFu;
-                uint32_t mask = rec.y >> 8;
-                while (mask) {
-                    const uint32_t k = (uint32_t)__builtin_ctz(mask);
-                    mask &= mask - 1u;
-                    const uint32_t ky = k / bw, kx = k - ky * bw;
-                    const uint32_t tile = rec.x + ky * rk.ntx + kx;
-                    const int sl = bin_find(keys, tile);
-                    if (sl >= 0) entries[basev[sl] + atomicAdd(&cnt[sl], 1u)] = v;
-                    else entries[tile_off[tile] + atomicAdd(&tile_cur[tile], 1u)] = v;
-                }
+                bin_scatter(rec, v, rk, keys, cnt, basev, tile_off, tile_cur, entries);
             }
             __syncthreads();
         }
+    }
+}
+
+// Scatter pass after binning by the strand generator: workgroup w takes the
+// units of generator workgroup w (bundles [w nb, (w + 1) nb), a contiguous
+// range of the stream), restores that workgroup's saved table, reserves each
+// of its tiles' ranges with one returning global add, and ranks every
+// (unit, tile) pair in LDS.  Like pass 1, it first writes the tile of every
+// raster work item.
+__global__ __launch_bounds__(BIN_BLOCK) void k_bin_spans(RasterK rk, const uint32_t *table,
+                                                         uint32_t n_bundles, uint32_t nb,
+                                                         const uint32_t *scene_off, uint32_t cap,
+                                                         const uint32_t *tile_off,
+                                                         uint32_t *tile_cur, uint32_t *entries,
+                                                         const uint2 *segrec,
+                                                         const uint32_t *saved,
+                                                         const uint32_t *item_off,
+                                                         uint32_t *item_tile, uint32_t max_items)
+{
+    __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
+    {
+        const uint32_t nw = blockDim.x >> 6, lane = threadIdx.x & 63u;
+        for (uint32_t t = blockIdx.x * nw + (threadIdx.x >> 6); t < rk.n_tiles;
+             t += gridDim.x * nw) {
+            const uint32_t i1 = min(item_off[t + 1], max_items);
+            for (uint32_t i = item_off[t] + lane; i < i1; i += 64u) item_tile[i] = t;
+        }
+    }
+    const uint32_t n = stream_len(scene_off, rk, cap);
+    const uint32_t b0 = blockIdx.x * nb;
+    const uint32_t b1 = min(b0 + nb, n_bundles) - 1u;        // last bundle of the span
+    const uint4 t0 = reinterpret_cast<const uint4 *>(table)[b0];
+    const uint4 t1 = reinterpret_cast<const uint4 *>(table)[b1];
+    const uint32_t u0 = min(t0.w, n);
+    const uint32_t u1 = (uint32_t)min<uint64_t>((uint64_t)t1.w + (uint64_t)t1.x * t1.y, n);
+    for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
+        keys[x] = BIN_FREE;
+        cnt[x] = 0u;
+    }
+    __syncthreads();
+    if (u0 < u1) {
+        const uint32_t *sv = saved + (size_t)blockIdx.x * BIN_SAVE_WORDS;
+        const uint32_t m = sv[0];
+        for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+            const uint32_t x = sv[1 + 3 * i], t = sv[2 + 3 * i];
+            keys[x] = t;
+            basev[x] = tile_off[t] + atomicAdd(&tile_cur[t], sv[3 + 3 * i]);
+        }
+    }
+    __syncthreads();
+    // records loaded one step ahead
+    const uint2 none = make_uint2(BIN_NONE, 0u);
+    uint32_t v = u0 + threadIdx.x;
+    uint2 nrec = v < u1 ? segrec[v] : none;
+    for (; v < u1; v += blockDim.x) {
+        const uint2 rec = nrec;
+        if (v + blockDim.x < u1) nrec = segrec[v + blockDim.x];
+        bin_scatter(rec, v, rk, keys, cnt, basev, tile_off, tile_cur, entries);
     }
 }
 
@@ -1417,7 +1342,7 @@ struct RasterWs {
     uint2 *segrec;        // per unit: first tile of its box, box width | tile mask << 8
     uint32_t *item_tile;  // per work item: its tile
     uint32_t max_items;   // bound on the work items: n_tiles + units * K / chunk
-    uint32_t *saved;      // per binning span: its LDS table (keys, counts)
+    uint32_t *saved;      // per binning span: count, then (slot, tile, count) per occupied slot
     uint32_t nsub;        // segments per thread and span
     size_t bytes;
 };
@@ -1456,7 +1381,7 @@ static RasterWs carve(void *ws, const hm_frame &f, uint32_t cap, const hm_raster
         w.nsub = bin_nsub(units);
         const size_t spans = (units + (size_t)BIN_BLOCK * w.nsub - 1) / ((size_t)BIN_BLOCK * w.nsub);
         w.segrec = (uint2 *)take(sizeof(uint2) * units);
-        w.saved = (uint32_t *)take(sizeof(uint32_t) * 2 * BIN_SLOTS * spans);
+        w.saved = (uint32_t *)take(sizeof(uint32_t) * BIN_SAVE_WORDS * spans);
         // every list entry belongs to one item of its tile: sum over tiles of
         // ceil(count / chunk) <= n_tiles + entries / chunk
         const size_t mi = nt + (units * p.max_tiles_per_seg + p.chunk - 1) / p.chunk;
@@ -1521,48 +1446,12 @@ void launch_prefill(uint64_t *vis, const float *scene_z, const hm_camera *cams,
                        (uint32_t *)nullptr, 0u);
 }
 
-void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,
-                   const hm_raster_params &p, const float *scene_z, uint64_t *vis, void *ws,
-                   hipStream_t st)
+// Offsets of the tile lists (in place over the counts) and the work items of
+// every tile, after the counting pass.
+static void plan_items(const RasterK &rk, const RasterWs &w, hipStream_t st)
 {
-    const RasterK rk = make_rk(f, p);
-    RasterWs w = carve(ws, f, s.cap, p);
-    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
-    const bool tiled = p.algo != HM_RASTER_DIRECT;
-    (void)npix;
-    hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
-                       f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
-                       tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
-    const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
-    const size_t units = (size_t)s.cap * units_per_cp(f, p);
-    const bool gbuf = p.payload == HM_PAYLOAD_GBUFFER;
-    const GbK gk{w.tan, reinterpret_cast<const float4 *>(s.rgb)};
-    if (gbuf)
-        hipLaunchKernelGGL(k_cp_tangent, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st, pos,
-                           (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tan);
-    if (p.algo == HM_RASTER_DIRECT) {
-        hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
-                           s.scene_off, rk, cams, s.cap, w.proj);
-        if (gbuf)
-            hipLaunchKernelGGL(k_raster_direct<true>, dim3(stride_grid(units, 256)), dim3(256), 0,
-                               st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off,
-                               cams, rk, s.cap, vis, gk);
-        else
-            hipLaunchKernelGGL(k_raster_direct<false>, dim3(stride_grid(units, 256)), dim3(256),
-                               0, st, (const float4 *)w.proj, (const uint8_t *)s.flags,
-                               s.scene_off, cams, rk, s.cap, vis, gk);
-        return;
-    }
-    // pass 0 of the binning also writes every unit's screen record
     const uint32_t nt = rk.n_tiles;
-    const uint32_t nsub = w.nsub;
-    const uint32_t gb = stride_grid((units + nsub - 1) / nsub, BIN_BLOCK);
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
-                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
-                       (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters,
-                       nsub, w.segrec, w.saved, (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
-    const bool small = nt <= PLAN_SMALL;
-    if (small) {
+    if (nt <= PLAN_SMALL) {
         hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(1024), 0, st, w.tile_cnt, nt, rk.chunk,
                            w.items, w.tile_cur);
     } else {
@@ -1571,11 +1460,14 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                            (const uint32_t *)w.tile_cnt, nt, rk.chunk, w.items, w.tile_cur);
         scan_exclusive<uint32_t>(w.items, w.items, nt, w.partials, st);
     }
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
-                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
-                       (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
-                       w.counters, nsub, w.segrec, w.saved, (const uint32_t *)w.items, w.item_tile,
-                       w.max_items);
+}
+
+// The tile raster over the binned work items, then the long segments.
+static void draw_tiles(const hm_strands &s, const hm_camera *cams, const hm_raster_params &p,
+                       const RasterK &rk, const RasterWs &w, const GbK &gk, uint64_t *vis,
+                       hipStream_t st)
+{
+    const bool gbuf = p.payload == HM_PAYLOAD_GBUFFER;
     const uint32_t lds = raster_lds_bytes(p);
     uint32_t grid = p.grid ? p.grid : 256u * 8u;
 #define HM_FLAT_LAUNCH(NB, GB)                                                                 \
@@ -1621,7 +1513,96 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
                            vis, DomK{nullptr, 1u, 1u}, gk);
 }
 
+void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f,
+                   const hm_raster_params &p, const float *scene_z, uint64_t *vis, void *ws,
+                   hipStream_t st)
+{
+    const RasterK rk = make_rk(f, p);
+    RasterWs w = carve(ws, f, s.cap, p);
+    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
+    const bool tiled = p.algo != HM_RASTER_DIRECT;
+    (void)npix;
+    hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
+                       f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
+                       tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
+    const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
+    const size_t units = (size_t)s.cap * units_per_cp(f, p);
+    const bool gbuf = p.payload == HM_PAYLOAD_GBUFFER;
+    const GbK gk{w.tan, reinterpret_cast<const float4 *>(s.rgb)};
+    if (gbuf)
+        hipLaunchKernelGGL(k_cp_tangent, dim3(stride_grid(s.cap, 256)), dim3(256), 0, st, pos,
+                           (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tan);
+    if (p.algo == HM_RASTER_DIRECT) {
+        hipLaunchKernelGGL(k_project, dim3(stride_grid(units, 256)), dim3(256), 0, st, pos,
+                           s.scene_off, rk, cams, s.cap, w.proj);
+        if (gbuf)
+            hipLaunchKernelGGL(k_raster_direct<true>, dim3(stride_grid(units, 256)), dim3(256), 0,
+                               st, (const float4 *)w.proj, (const uint8_t *)s.flags, s.scene_off,
+                               cams, rk, s.cap, vis, gk);
+        else
+            hipLaunchKernelGGL(k_raster_direct<false>, dim3(stride_grid(units, 256)), dim3(256),
+                               0, st, (const float4 *)w.proj, (const uint8_t *)s.flags,
+                               s.scene_off, cams, rk, s.cap, vis, gk);
+        return;
+    }
+    // pass 0 of the binning also writes every unit's screen record
+    const uint32_t nt = rk.n_tiles;
+    const uint32_t nsub = w.nsub;
+    const uint32_t gb = stride_grid((units + nsub - 1) / nsub, BIN_BLOCK);
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
+                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
+                       (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters,
+                       nsub, w.segrec, w.saved, (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+    plan_items(rk, w, st);
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
+                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
+                       (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
+                       w.counters, nsub, w.segrec, w.saved, (const uint32_t *)w.items, w.item_tile,
+                       w.max_items);
+    draw_tiles(s, cams, p, rk, w, gk, vis, st);
+}
+
+// Strand generation that bins as it writes (pass 0 of the binning done by the
+// generator's workgroups), then the scatter over the generator's spans and
+// the tile raster: the same buffer as generate + raster (single-view frames,
+// tiled algorithm with segment ids).  Workspace: the raster's plus one saved
+// table per generator workgroup.
+size_t gen_raster_workspace(uint32_t n_bundles, const hm_frame &f, uint32_t cap,
+                            const hm_raster_params &p)
+{
+    return raster_workspace(f, cap, p) +
+           align_up(sizeof(uint32_t) * (size_t)BIN_SAVE_WORDS * gen_grid(n_bundles, cap));
+}
+
+void launch_gen_raster_tiled(const hm_hair_mesh &m, const uint32_t *table,
+                             const uint32_t *strand_base, const float *strand_rgb,
+                             const hm_gen_params &gp, const hm_strands &s, const hm_camera *cams,
+                             const hm_frame &f, const hm_raster_params &p, const float *scene_z,
+                             uint64_t *vis, void *ws, hipStream_t st)
+{
+    const RasterK rk = make_rk(f, p);
+    const RasterWs w = carve(ws, f, s.cap, p);
+    uint32_t *saved = reinterpret_cast<uint32_t *>((char *)ws + raster_workspace(f, s.cap, p));
+    hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
+                       f.n_scenes, f.width, f.height, w.tile_cnt, rk.n_tiles + 1, w.counters,
+                       64u);
+    const BinK bk{rk,         cams,          w.proj,   w.segrec,
+                  w.tile_cnt, w.long_list,   w.counters, saved,
+                  rk.K < BIN_KMAX ? rk.K : BIN_KMAX};
+    launch_generate_bin(m, table, strand_base, strand_rgb, gp, s, bk, st);
+    plan_items(rk, w, st);
+    hipLaunchKernelGGL(k_bin_spans, dim3(gen_grid(m.n_bundles, s.cap)), dim3(BIN_BLOCK), 0, st,
+                       rk, table, m.n_bundles, gen_bundles_per_group(m.n_bundles, s.cap),
+                       s.scene_off, s.cap,
+                       (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries,
+                       (const uint2 *)w.segrec, (const uint32_t *)saved,
+                       (const uint32_t *)w.items, w.item_tile, w.max_items);
+    const GbK gk{nullptr, reinterpret_cast<const float4 *>(s.rgb)};
+    draw_tiles(s, cams, p, rk, w, gk, vis, st);
+}
+
 }  // namespace hm
+
 
 namespace hm {
 

@@ -21,7 +21,7 @@ LOD_OFF, LOD_ON = 0, 1
 RASTER_TILED, RASTER_DIRECT, RASTER_TILED_ROWS = 0, 1, 2
 RESOLVE_FILTER, RESOLVE_SOFT, RESOLVE_CENTER = 0, 1, 2
 PAYLOAD_SEGMENT, PAYLOAD_GBUFFER = 0, 1
-CALL_LOD, CALL_RASTER, CALL_RESOLVE, CALL_DOM = 0, 1, 2, 3
+CALL_LOD, CALL_RASTER, CALL_RESOLVE, CALL_DOM, CALL_GEN_RASTER = 0, 1, 2, 3, 4
 
 _u32, _i32, _f32, _vp, _sz = ctypes.c_uint32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p, ctypes.c_size_t
 
@@ -80,7 +80,7 @@ EXPORTS = ["hm_lod_select", "hm_generate_strands", "hm_raster_vis", "hm_resolve_
            "hm_version", "hm_timing_enable", "hm_timing_collect", "hm_render_frame",
            "hm_graph_create", "hm_graph_launch", "hm_graph_destroy", "hm_lod_depth_offset",
            "hm_dom_accumulate", "hm_dom_shadow", "hm_generate_raster",
-           "hm_resolve_shade_noalloc"]
+           "hm_resolve_shade_noalloc", "hm_generate_raster_tiled"]
 # measurement helpers (include/hm_bench.h)
 BENCH_EXPORTS = ["hm_bench_atomics", "hm_bench_traffic", "hm_bench_reciprocal"]
 
@@ -334,6 +334,21 @@ def raster_vis(st: Strands, cams, fr: Frame, rp: RasterParams, scene_z, vis, ws)
                               _ptr(scene_z), _ptr(vis), _ptr(ws), ws.numel() * ws.element_size(),
                               _stream())
     _check(rc, "hm_raster_vis")
+
+
+def generate_raster_tiled(mesh: HairMesh, table, strand_base, strand_rgb, gp: GenParams,
+                          st: Strands, cams, fr: Frame, rp: RasterParams, scene_z, vis, ws):
+    """Strand generation that bins as it assembles, then the tiled raster:
+    the stream and vis of generate_strands + raster_vis in one call."""
+    L = load()
+    L.hm_generate_raster_tiled.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                           _vp, _vp, _sz, _vp]
+    _check(L.hm_generate_raster_tiled(ctypes.byref(mesh), _ptr(table), _ptr(strand_base),
+                                      _ptr(strand_rgb), ctypes.byref(gp), ctypes.byref(st),
+                                      _ptr(cams), ctypes.byref(fr), ctypes.byref(rp),
+                                      _ptr(scene_z), _ptr(vis), _ptr(ws),
+                                      ws.numel() * ws.element_size(), _stream()),
+           "hm_generate_raster_tiled")
 
 
 def resolve_shade(st: Strands, vis, cams, fr: Frame, sp: ShadeParams, out, ws):

@@ -89,6 +89,19 @@ class DeviceScene:
         hm.raster_vis(self.st, self.cams, self.fr, self.rparams, self.scene_z, self.vis,
                       self.ws_raster)
 
+    def generate_raster_tiled(self):
+        """Generation that bins as it assembles, then the tiled raster (one
+        call; the same stream and vis as generate() + raster())."""
+        import torch
+        need = hm.workspace_size(hm.CALL_GEN_RASTER, self.fr, n_bundles=self.sc.n_bundles,
+                                 cap=self.cap, rparams=self.rparams)
+        ws = getattr(self, "ws_gen_raster", None)
+        if ws is None or ws.numel() < need:
+            self.ws_gen_raster = torch.zeros(need, dtype=torch.uint8, device="cuda")
+        hm.generate_raster_tiled(self.mesh, self.table, self.strand_base, self.strand_rgb,
+                                 self.gp, self.st, self.cams, self.fr, self.rparams,
+                                 self.scene_z, self.vis, self.ws_gen_raster)
+
     def use_gbuffer(self, on: bool = True):
         """Compressed G-buffer keys (depth | tangent, albedo, AO) instead of
         segment ids; the resolve then shades each centre hit from its key
@@ -131,6 +144,13 @@ class DeviceScene:
         self.lod()
         self.generate()
         self.raster()
+        self.resolve()
+        return self.out
+
+    def render_binned(self):
+        """The frame with generation and binning in one pass."""
+        self.lod()
+        self.generate_raster_tiled()
         self.resolve()
         return self.out
 

@@ -141,6 +141,29 @@ def test_validation_errors_are_reported():
     assert b"NULL array" in L.hm_last_error()
     # (with G-buffer keys the same arguments pass validation; the call would
     # launch, so it is exercised by the GPU tests only)
+    # generation with binning: the tiled algorithm, segment ids and one view
+    # per scene only; matching scene counts; its own workspace size
+    L.hm_generate_raster_tiled.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t,
+                                           P]
+    # (sized for this stream's cap of 10, so that no call below gets as far as
+    # a launch on these placeholder pointers)
+    need = hm.workspace_size(hm.CALL_GEN_RASTER, fr, n_bundles=m2.n_bundles, cap=st.cap,
+                             rparams=rp)
+    assert need > hm.workspace_size(hm.CALL_RASTER, fr, cap=st.cap, rparams=rp)
+
+    def gen_tiled(rparams, frame=fr, ws_bytes=need):
+        return L.hm_generate_raster_tiled(ctypes.byref(m2), dummy, None, None, ctypes.byref(gp),
+                                          ctypes.byref(st), dummy, ctypes.byref(frame),
+                                          ctypes.byref(rparams), None, dummy, dummy, ws_bytes,
+                                          None)
+    for field, value in (("algo", hm.RASTER_DIRECT), ("payload", GBUF), ("shared_views", 1)):
+        bad = hm.RasterParams.from_buffer_copy(rp)
+        setattr(bad, field, value)
+        assert gen_tiled(bad) == 1, field
+    assert gen_tiled(rp, frame=fr2) == 1
+    assert b"n_scenes" in L.hm_last_error()
+    assert gen_tiled(rp, ws_bytes=need - 1) == 3
+    assert b"workspace" in L.hm_last_error()
     # atomic-rate microkernels: argument checks before any launch
     L.hm_bench_atomics.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t,
                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
