@@ -369,6 +369,42 @@ def extra_fused(steps):
     return r
 
 
+def extra_binned(steps):
+    """Generation that bins as it assembles (hm_generate_raster_tiled) against
+    the separate generate + binning + tile raster, on the 1080p head and the
+    64-scene batch: whole frames, the generation + raster part, and the
+    kernels of both."""
+    import torch
+    from paper_2607_04230_amd import hm, scenes
+    from paper_2607_04230_amd.render import DeviceScene
+    out = {}
+    for name, sc in (("head", scenes.config_head()), ("batched", scenes.config_batched())):
+        ds = DeviceScene(sc)
+        ds.lod()
+        torch.cuda.synchronize()
+
+        def separate():
+            ds.generate()
+            ds.raster()
+        r = {"frame_ms_separate": _time_ms(ds.render, steps, 2),
+             "frame_ms_binned": _time_ms(ds.render_binned, steps, 2),
+             "gen_raster_ms_separate": _time_ms(separate, steps, 2),
+             "gen_raster_ms_binned": _time_ms(ds.generate_raster_tiled, steps, 2)}
+        for label, fn in (("separate", separate), ("binned", ds.generate_raster_tiled)):
+            hm.timing_enable(True)
+            hm.timing_collect()
+            for _ in range(steps):
+                fn()
+            torch.cuda.synchronize()
+            t = hm.timing_collect()
+            hm.timing_enable(False)
+            r["kernel_ms_" + label] = {k: v[0] / max(v[1], 1) for k, v in sorted(t.items())}
+        out[name] = r
+        del ds
+        torch.cuda.empty_cache()
+    return out
+
+
 def extra_gbuffer(steps):
     """Compressed G-buffer keys against segment-id keys on the 1080p head: the
     raster call, the centre resolve (decode vs gather) and the frame."""
@@ -692,7 +728,7 @@ def main():
         torch.cuda.empty_cache()
         for name, fn in (("lod", extra_lod), ("batched", extra_batched), ("diff", extra_diff),
                          ("shadow", extra_shadow), ("fused", extra_fused),
-                         ("gbuffer", extra_gbuffer)):
+                         ("binned", extra_binned), ("gbuffer", extra_gbuffer)):
             print(f"[bench] extra workload: {name}", file=sys.stderr, flush=True)
             line[name] = fn(max(args.steps // 2, 5))
     if not args.no_cpu:

@@ -359,7 +359,13 @@ __device__ __forceinline__ void gen_sync()
 // unit tangents (computed in LDS from their neighbours, as the resolve does)
 // and the strand's colour, and nothing of the stream is written (the paper's
 // register-only assembly); strands longer than the LDS chunk recompute the
-// points a segment needs.
+// points a segment needs.  BIN (plain stream only): every control point is
+// also projected where it is generated and its screen record written, and
+// once a chunk is complete each segment's tile box and accepted tiles are
+// found and counted in the workgroup's LDS table (the tile raster's first
+// binning pass, with the same record per unit); at the end the table is
+// flushed to the tile counts and its occupied slots saved for the scatter
+// pass, which walks the workgroup's span of the stream.
 template <bool FUSED, bool WAVE, bool GB, bool BIN>
 __global__ __launch_bounds__(256) void k_generate_bundle(hm_hair_mesh m, const uint32_t *table,
                                                         const uint32_t *strand_base,
