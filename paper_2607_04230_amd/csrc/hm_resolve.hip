@@ -85,6 +85,62 @@ __device__ __forceinline__ V3 cp_tangent(const float4 *pos, const uint8_t *flags
     return nrm(d);
 }
 
+// The stream values the shading of segment v reads: its points and colours,
+// the flags of both points and the neighbours their tangents may need.
+struct SegPts {
+    float4 Pm, P0, P1, P2, C0, C1;
+    uint8_t f0, f1;
+};
+
+// All of them loaded together (one round of gathers): a neighbour outside
+// the stream (v = 0, or v + 2 >= n) is replaced by a point of the segment,
+// which the flags then never use (v is a root, or v + 1 a tip).
+__device__ __forceinline__ SegPts load_seg_pts(const float4 *pos, const float4 *rgb,
+                                               const uint8_t *flags, uint32_t v, uint32_t n)
+{
+    SegPts q;
+    q.f0 = flags[v];
+    q.f1 = flags[v + 1];
+    q.Pm = pos[v > 0 ? v - 1 : v];
+    q.P0 = pos[v];
+    q.P1 = pos[v + 1];
+    q.P2 = pos[v + 2 < n ? v + 2 : v + 1];
+    q.C0 = rgb[v];
+    q.C1 = rgb[v + 1];
+    return q;
+}
+
+// cp_tangent of the two points from the loaded values (the same differences).
+__device__ __forceinline__ void seg_tangents(const SegPts &q, V3 &T0, V3 &T1)
+{
+    V3 d0, d1;
+    if (q.f0 & HM_ROOT) d0 = xyz(q.P1) - xyz(q.P0);
+    else if (q.f0 & HM_TIP) d0 = xyz(q.P0) - xyz(q.Pm);
+    else d0 = xyz(q.P1) - xyz(q.Pm);
+    if (q.f1 & HM_ROOT) d1 = xyz(q.P2) - xyz(q.P1);
+    else if (q.f1 & HM_TIP) d1 = xyz(q.P1) - xyz(q.P0);
+    else d1 = xyz(q.P2) - xyz(q.P0);
+    T0 = nrm(d0);
+    T1 = nrm(d1);
+}
+
+__device__ __forceinline__ SegShade seg_shade_pts(const SegPts &q, DProj a, DProj b, double px,
+                                                  double py)
+{
+    SegShade r;
+    r.ts = closest_t(a, b, px, py);
+    const double iz = a.iz + r.ts * (b.iz - a.iz);
+    r.t3 = (float)(r.ts * b.iz / iz);
+    const V3 P0 = xyz(q.P0), P1 = xyz(q.P1);
+    r.X = P0 + (P1 - P0) * r.t3;
+    V3 T0, T1;
+    seg_tangents(q, T0, T1);
+    r.T = nrm(T0 + (T1 - T0) * r.t3);
+    const V3 c0 = xyz(q.C0), c1 = xyz(q.C1);
+    r.alb = c0 + (c1 - c0) * r.t3;
+    return r;
+}
+
 __device__ __forceinline__ SegShade seg_shade_point(const float4 *pos, const float4 *rgb,
                                                     const uint8_t *flags, DProj a, DProj b,
                                                     uint32_t v, double px, double py)
@@ -123,9 +179,10 @@ __device__ __forceinline__ V3 shade(const SegShade &g, const Cam &c, const Shade
 
 // ------------------------------------------------------------------ centre shading
 __global__ __launch_bounds__(256) void k_shade(const float4 *pos, const float4 *rgb,
-                                               const uint8_t *flags, const uint64_t *vis,
-                                               const hm_camera *cams, uint32_t S, uint32_t W,
-                                               uint32_t H, ShadeK k, float4 *rec, float4 *out)
+                                               const uint8_t *flags, uint32_t n_cp,
+                                               const uint64_t *vis, const hm_camera *cams,
+                                               uint32_t S, uint32_t W, uint32_t H, ShadeK k,
+                                               float4 *rec, float4 *out)
 {
     const size_t hw = (size_t)W * H;
     const size_t n = hw * S;
@@ -139,10 +196,10 @@ __global__ __launch_bounds__(256) void k_shade(const float4 *pos, const float4 *
         if (hc) {
             const Cam c = load_cam(cams + s);
             const uint32_t v = (uint32_t)(kc & HM_ID_MASK);
-            const DProj a = project_d(c, pos[v]), b = project_d(c, pos[v + 1]);
+            const SegPts q = load_seg_pts(pos, rgb, flags, v, n_cp);
+            const DProj a = project_d(c, q.P0), b = project_d(c, q.P1);
             const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
-            const SegShade g = seg_shade_point(pos, rgb, flags, a, b, v, (double)i + 0.5,
-                                               (double)j + 0.5);
+            const SegShade g = seg_shade_pts(q, a, b, (double)i + 0.5, (double)j + 0.5);
             col = shade(g, c, k, k.shadow ? k.shadow[p] : 1.0f);
         }
         const uint32_t bits = hc ? (uint32_t)(kc >> HM_ID_BITS)
@@ -544,14 +601,14 @@ void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *c
     }
     if (k.mode == HM_RESOLVE_CENTER) {
         hipLaunchKernelGGL(k_shade, dim3(full_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
-                           (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k,
-                           (float4 *)nullptr, o);
+                           (const uint8_t *)s.flags, s.cap, vis, cams, f.n_scenes, f.width,
+                           f.height, k, (float4 *)nullptr, o);
         return;
     }
     float4 *rec = reinterpret_cast<float4 *>(ws);
     hipLaunchKernelGGL(k_shade, dim3(full_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
-                       (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k, rec,
-                       (float4 *)nullptr);
+                       (const uint8_t *)s.flags, s.cap, vis, cams, f.n_scenes, f.width,
+                       f.height, k, rec, (float4 *)nullptr);
     const uint32_t tiles = ((f.width + FT - 1) / FT) * ((f.height + FT - 1) / FT) * f.n_scenes;
     if (k.r == 5) {             // the paper's radius: unrolled taps
         hipLaunchKernelGGL(k_filter<5>, dim3(tiles), dim3(FT * FT), 0, st, pos, vis, cams,
