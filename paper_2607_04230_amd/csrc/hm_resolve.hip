@@ -75,16 +75,6 @@ __device__ __forceinline__ double closest_t(DProj a, DProj b, double px, double 
     return t < 0.0 ? 0.0 : (t > 1.0 ? 1.0 : t);
 }
 
-__device__ __forceinline__ V3 cp_tangent(const float4 *pos, const uint8_t *flags, uint32_t v)
-{
-    const uint8_t f = flags[v];
-    V3 d;
-    if (f & HM_ROOT) d = xyz(pos[v + 1]) - xyz(pos[v]);
-    else if (f & HM_TIP) d = xyz(pos[v]) - xyz(pos[v - 1]);
-    else d = xyz(pos[v + 1]) - xyz(pos[v - 1]);
-    return nrm(d);
-}
-
 // The stream values the shading of segment v reads: its points and colours,
 // the flags of both points and the neighbours their tangents may need.
 struct SegPts {
@@ -110,7 +100,8 @@ __device__ __forceinline__ SegPts load_seg_pts(const float4 *pos, const float4 *
     return q;
 }
 
-// cp_tangent of the two points from the loaded values (the same differences).
+// Unit tangents of the segment's two points from the loaded values: forward
+// difference at a root, backward at a tip, central otherwise.
 __device__ __forceinline__ void seg_tangents(const SegPts &q, V3 &T0, V3 &T1)
 {
     V3 d0, d1;
@@ -137,23 +128,6 @@ __device__ __forceinline__ SegShade seg_shade_pts(const SegPts &q, DProj a, DPro
     seg_tangents(q, T0, T1);
     r.T = nrm(T0 + (T1 - T0) * r.t3);
     const V3 c0 = xyz(q.C0), c1 = xyz(q.C1);
-    r.alb = c0 + (c1 - c0) * r.t3;
-    return r;
-}
-
-__device__ __forceinline__ SegShade seg_shade_point(const float4 *pos, const float4 *rgb,
-                                                    const uint8_t *flags, DProj a, DProj b,
-                                                    uint32_t v, double px, double py)
-{
-    SegShade r;
-    r.ts = closest_t(a, b, px, py);
-    const double iz = a.iz + r.ts * (b.iz - a.iz);
-    r.t3 = (float)(r.ts * b.iz / iz);
-    const V3 P0 = xyz(pos[v]), P1 = xyz(pos[v + 1]);
-    r.X = P0 + (P1 - P0) * r.t3;
-    const V3 T0 = cp_tangent(pos, flags, v), T1 = cp_tangent(pos, flags, v + 1);
-    r.T = nrm(T0 + (T1 - T0) * r.t3);
-    const V3 c0 = xyz(rgb[v]), c1 = xyz(rgb[v + 1]);
     r.alb = c0 + (c1 - c0) * r.t3;
     return r;
 }
@@ -540,9 +514,10 @@ __device__ __forceinline__ uint64_t soft_source(uint64_t kc, uint64_t ka)
 }
 
 __global__ __launch_bounds__(256) void k_soft(const float4 *pos, const float4 *rgb,
-                                              const uint8_t *flags, const uint64_t *vis,
-                                              const hm_camera *cams, uint32_t S, uint32_t W,
-                                              uint32_t H, ShadeK k, float4 *out)
+                                              const uint8_t *flags, uint32_t n_cp,
+                                              const uint64_t *vis, const hm_camera *cams,
+                                              uint32_t S, uint32_t W, uint32_t H, ShadeK k,
+                                              float4 *out)
 {
     const size_t hw = (size_t)W * H;
     const size_t n = hw * S;
@@ -558,11 +533,12 @@ __global__ __launch_bounds__(256) void k_soft(const float4 *pos, const float4 *r
         }
         const Cam c = load_cam(cams + s);
         const uint32_t v = (uint32_t)(src & HM_ID_MASK);
-        const float4 P0 = pos[v], P1 = pos[v + 1];
+        const SegPts q = load_seg_pts(pos, rgb, flags, v, n_cp);
+        const float4 P0 = q.P0, P1 = q.P1;
         const DProj a = project_d(c, P0), b = project_d(c, P1);
         const uint32_t j = (uint32_t)(loc / W), i = (uint32_t)(loc - (size_t)j * W);
         const double px = (double)i + 0.5, py = (double)j + 0.5;
-        const SegShade g = seg_shade_point(pos, rgb, flags, a, b, v, px, py);
+        const SegShade g = seg_shade_pts(q, a, b, px, py);
         const double ex = px - (a.x + g.ts * (b.x - a.x)), ey = py - (a.y + g.ts * (b.y - a.y));
         const float d = (float)sqrt(ex * ex + ey * ey);
         const double w0 = (double)P0.w * c.fy * a.iz, w1 = (double)P1.w * c.fy * b.iz;
@@ -590,8 +566,8 @@ void launch_resolve(const hm_strands &s, const uint64_t *vis, const hm_camera *c
     const size_t npix = (size_t)f.width * f.height * f.n_scenes;
     if (k.mode == HM_RESOLVE_SOFT) {
         hipLaunchKernelGGL(k_soft, dim3(stride_grid(npix, 256)), dim3(256), 0, st, pos, rgb,
-                           (const uint8_t *)s.flags, vis, cams, f.n_scenes, f.width, f.height, k,
-                           o);
+                           (const uint8_t *)s.flags, s.cap, vis, cams, f.n_scenes, f.width,
+                           f.height, k, o);
         return;
     }
     if (k.payload == HM_PAYLOAD_GBUFFER) {
