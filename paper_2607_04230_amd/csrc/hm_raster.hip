@@ -4,14 +4,16 @@
 // image atomicMin per pixel and layer.  Here:
 //   1. k_prefill writes both layers (empty or the opaque scene depth);
 //   2. each control point's screen record is computed once, by the first
-//      binning pass (or by k_project on the direct path);
+//      binning pass (or by k_project on the direct path, or by the strand
+//      generator when it bins as it assembles);
 //   3. TILED path: k_bin pass 0 finds each segment's screen tiles (T x T
 //      pixels), stores them as an 8-byte record and counts (segment, tile)
 //      pairs in LDS tables flushed once per (span, tile); an exclusive scan
 //      turns counts into offsets and each tile is cut into work items of
-//      `chunk` segments; pass 1 walks the records and scatters the segment
-//      ids into the per-tile lists;
-//   4. k_raster_tiles is a persistent kernel: each workgroup pulls work items
+//      `chunk` segments; pass 1 (or k_bin_spans after the generator's
+//      counting) walks the records and scatters the segment ids into the
+//      per-tile lists;
+//   4. k_raster_flat is a persistent kernel: each workgroup pulls work items
 //      from a device counter, keeps the tile's two layers in LDS, resolves all
 //      coverage with LDS ds_min_u64, then merges the touched pixels into the
 //      global buffer with one 64-bit atomic min each (plain stores when the
@@ -37,26 +39,19 @@ namespace hm {
 
 
 // ------------------------------------------------------------------ prefill
-__global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *scene_z,
-                                                 const hm_camera *cams, uint32_t S, uint32_t W,
-                                                 uint32_t H, uint32_t *clr0, uint32_t n0,
-                                                 uint32_t *clr1, uint32_t n1)
+// Prefill of both layers by block (bx, by) of an nbx x nby grid: the grid's
+// rows take scenes (all scenes of a frame at once, no division per pixel),
+// two pixels per 16-byte store when the scene has an even pixel count and the
+// buffers are aligned.
+__device__ __forceinline__ void prefill_pixels(uint64_t *vis, const float *scene_z,
+                                               const hm_camera *cams, uint32_t S, uint32_t W,
+                                               uint32_t H, uint32_t bx, uint32_t nbx,
+                                               uint32_t by, uint32_t nby)
 {
-    // also zero the binning counters of this call (saves separate fill launches)
-    if (blockIdx.y == 0) {
-        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n0 || i < n1;
-             i += gridDim.x * blockDim.x) {
-            if (i < n0) clr0[i] = 0u;
-            if (i < n1) clr1[i] = 0u;
-        }
-    }
-    // the grid's rows take scenes (all scenes of a frame at once, no division
-    // per pixel), two pixels per 16-byte store when the scene has an even
-    // pixel count and the buffers are aligned
     const size_t hw = (size_t)W * H;
-    const size_t tid = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (uint32_t s = blockIdx.y; s < S; s += gridDim.y) {
+    const size_t tid = bx * (size_t)blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)nbx * blockDim.x;
+    for (uint32_t s = by; s < S; s += nby) {
         const float *zs = scene_z ? scene_z + (size_t)s * hw : nullptr;
         const float zn = cams[s].znear, zf = cams[s].zfar;
         const float inv_range = 1.0f / (zf - zn);
@@ -89,6 +84,30 @@ __global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *sce
         }
     }
 }
+
+__global__ __launch_bounds__(256) void k_prefill(uint64_t *vis, const float *scene_z,
+                                                 const hm_camera *cams, uint32_t S, uint32_t W,
+                                                 uint32_t H, uint32_t *clr0, uint32_t n0,
+                                                 uint32_t *clr1, uint32_t n1)
+{
+    // also zero the binning counters of this call (saves separate fill launches)
+    if (blockIdx.y == 0) {
+        for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n0 || i < n1;
+             i += gridDim.x * blockDim.x) {
+            if (i < n0) clr0[i] = 0u;
+            if (i < n1) clr1[i] = 0u;
+        }
+    }
+    prefill_pixels(vis, scene_z, cams, S, W, H, blockIdx.x, gridDim.x, blockIdx.y, gridDim.y);
+}
+
+// The prefill as extra workgroups of the first binning pass (which neither
+// reads nor writes the buffer), so that it overlaps the binning.
+struct PrefillK {
+    uint64_t *vis;
+    const float *scene_z;
+    uint32_t per, rows;     // the prefill grid (per x rows workgroups)
+};
 
 // ------------------------------------------------------------------ projection
 __global__ __launch_bounds__(256) void k_project(const float4 *pos_w, const uint32_t *scene_off,
@@ -309,10 +328,18 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
                                                    uint32_t *counters, uint32_t nsub,
                                                    uint2 *segrec, uint32_t *saved,
                                                    const uint32_t *item_off, uint32_t *item_tile,
-                                                   uint32_t max_items)
+                                                   uint32_t max_items, uint32_t nbin, PrefillK pf)
 {
     __shared__ uint32_t keys[BIN_SLOTS], cnt[BIN_SLOTS], basev[BIN_SLOTS];
     __shared__ uint32_t sh_nsave;
+    if (blockIdx.x >= nbin) {
+        // a prefill workgroup
+        const uint32_t b = blockIdx.x - nbin;
+        const uint32_t by = b / pf.per;
+        prefill_pixels(pf.vis, pf.scene_z, cams, rk.S, rk.W, rk.H, b - by * pf.per, pf.per, by,
+                       pf.rows);
+        return;
+    }
     const uint32_t n = stream_len(scene_off, rk, cap);
     const uint32_t nu = unit_count(n, rk);
     const uint32_t span = BIN_BLOCK * nsub;        // segments per table flush
@@ -323,13 +350,13 @@ __global__ __launch_bounds__(BIN_BLOCK) void k_bin(int pass, float4 *proj, const
         // raster workgroup finds its tile with one load
         const uint32_t nw = blockDim.x >> 6, lane = threadIdx.x & 63u;
         for (uint32_t t = blockIdx.x * nw + (threadIdx.x >> 6); t < rk.n_tiles;
-             t += gridDim.x * nw) {
+             t += nbin * nw) {
             const uint32_t i1 = min(item_off[t + 1], max_items);
             for (uint32_t i = item_off[t] + lane; i < i1; i += 64u) item_tile[i] = t;
         }
     }
     // v below is a segment unit (see unit_map); lists store units
-    for (uint32_t base = blockIdx.x * span; base < nu; base += gridDim.x * span) {
+    for (uint32_t base = blockIdx.x * span; base < nu; base += nbin * span) {
         uint32_t *sv = saved + (size_t)(base / span) * BIN_SAVE_WORDS;
         if (pass == 0) {
             for (uint32_t x = threadIdx.x; x < BIN_SLOTS; x += blockDim.x) {
@@ -1519,12 +1546,16 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
 {
     const RasterK rk = make_rk(f, p);
     RasterWs w = carve(ws, f, s.cap, p);
-    const size_t npix = (size_t)f.width * f.height * f.n_scenes;
     const bool tiled = p.algo != HM_RASTER_DIRECT;
-    (void)npix;
-    hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
-                       f.n_scenes, f.width, f.height, tiled ? w.tile_cnt : nullptr,
-                       tiled ? rk.n_tiles + 1 : 0u, tiled ? w.counters : nullptr, tiled ? 64u : 0u);
+    // tiled: the binning counters are cleared first and the buffer is
+    // prefilled by extra workgroups of the first binning pass
+    if (tiled)
+        hipLaunchKernelGGL(k_prefill, dim3(1), dim3(256), 0, st, vis, scene_z, cams, 0u,
+                           f.width, f.height, w.tile_cnt, rk.n_tiles + 1, w.counters, 64u);
+    else
+        hipLaunchKernelGGL(k_prefill, prefill_grid(f), dim3(256), 0, st, vis, scene_z, cams,
+                           f.n_scenes, f.width, f.height, (uint32_t *)nullptr, 0u,
+                           (uint32_t *)nullptr, 0u);
     const float4 *pos = reinterpret_cast<const float4 *>(s.pos_w);
     const size_t units = (size_t)s.cap * units_per_cp(f, p);
     const bool gbuf = p.payload == HM_PAYLOAD_GBUFFER;
@@ -1549,16 +1580,19 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     const uint32_t nt = rk.n_tiles;
     const uint32_t nsub = w.nsub;
     const uint32_t gb = stride_grid((units + nsub - 1) / nsub, BIN_BLOCK);
-    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos, cams,
-                       (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
+    const dim3 pg = prefill_grid(f);
+    const PrefillK pf{vis, scene_z, pg.x, pg.y};
+    hipLaunchKernelGGL(k_bin, dim3(gb + pg.x * pg.y), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos,
+                       cams, (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)nullptr, w.tile_cur, w.entries, w.long_list, w.counters,
-                       nsub, w.segrec, w.saved, (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u);
+                       nsub, w.segrec, w.saved, (const uint32_t *)nullptr, (uint32_t *)nullptr, 0u,
+                       gb, pf);
     plan_items(rk, w, st);
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(BIN_BLOCK), 0, st, 1, w.proj, pos, cams,
                        (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
                        (const uint32_t *)w.tile_cnt, w.tile_cur, w.entries, w.long_list,
                        w.counters, nsub, w.segrec, w.saved, (const uint32_t *)w.items, w.item_tile,
-                       w.max_items);
+                       w.max_items, gb, PrefillK{nullptr, nullptr, 1u, 1u});
     draw_tiles(s, cams, p, rk, w, gk, vis, st);
 }
 
