@@ -143,7 +143,9 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
     elif kernel == "k_project":
         b = n_cp * PROJ_BYTES_PER_CP
     elif kernel == "k_bin":
-        b = n_cp * RASTER_BYTES_PER_SEG          # screen records + flags, per pass
+        # screen records + flags per pass; the first pass also prefills both
+        # layers of the buffer (its extra workgroups): half a buffer per launch
+        b = n_cp * RASTER_BYTES_PER_SEG + vis_bytes // 2
     elif kernel == "k_shade":
         # both key layers read, one 16 B record written per pixel; per hair
         # pixel two 16 B control points and two colours gathered
@@ -185,8 +187,6 @@ def roofline(kernel: str, avg_ms: float, n_cp: int, n_seg: int, vis_bytes: int, 
             if ATOMIC_PEAKS:
                 r["global_atomic_frac"] = ga / s / ATOMIC_PEAKS["global"]
         return r
-    elif kernel == "k_prefill":
-        b = vis_bytes
     else:
         b = n_cp * 16
     ach = b / s / 1e9
@@ -683,7 +683,7 @@ def main():
     measure_atomic_peaks(sc.width * sc.height)
     roof = roofline(dom, dom_avg, n_cp, n_seg, vis_bytes, hair_px, (2 * r + 1) ** 2)
     roof["kernel"] = dom
-    for k in ("k_generate_bundle", "k_project", "k_bin", "k_raster_flat", "k_prefill",
+    for k in ("k_generate_bundle", "k_project", "k_bin", "k_raster_flat",
               "k_shade", "k_filter"):
         if k in per_kernel:
             per_kernel[k]["roofline"] = roofline(k, per_kernel[k]["avg_ms"], n_cp, n_seg,
