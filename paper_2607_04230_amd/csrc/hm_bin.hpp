@@ -8,6 +8,8 @@
 
 namespace hm {
 
+// One raster call's frame, tile grid and binning parameters (built on the
+// host, passed by value).
 struct RasterK {
     uint32_t S, W, H;
     float r_min;
