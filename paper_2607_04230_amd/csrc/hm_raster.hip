@@ -1583,7 +1583,9 @@ void launch_raster(const hm_strands &s, const hm_camera *cams, const hm_frame &f
     const uint32_t nt = rk.n_tiles;
     const uint32_t nsub = w.nsub;
     const uint32_t gb = stride_grid((units + nsub - 1) / nsub, BIN_BLOCK);
-    const dim3 pg = prefill_grid(f);
+    // the prefill grid holds as many threads as the prefill kernel's own
+    dim3 pg = prefill_grid(f);
+    pg.x = std::max<uint32_t>(1u, pg.x * 256u / BIN_BLOCK);
     const PrefillK pf{vis, scene_z, pg.x, pg.y};
     hipLaunchKernelGGL(k_bin, dim3(gb + pg.x * pg.y), dim3(BIN_BLOCK), 0, st, 0, w.proj, pos,
                        cams, (const uint8_t *)s.flags, s.scene_off, rk, s.cap, w.tile_cnt,
